@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Benchmark of the buffer k-d tree exact kNN query on one MI355X.
+
+One step = one complete query call (Algorithm 1 to completion: every
+FindLeafBatch, buffer insertion, ProcessAllBuffers leaf scan and the final
+conversion) over all m queries of the workload, with the tree built and the
+queries resident in HBM before the timed region starts.  Prints one JSON line.
+
+Workloads (seeded synthetic stand-ins for the paper's catalogues, Section 4.1):
+  ondevice  n = m = 2^22, d = 10, 16-component Gaussian mixture, k = 10, height 10 (default)
+  small     n = 2^15, m = 2^12, d = 10 uniform on [0,1]^10, k = 10, height 6
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import datagen  # noqa: E402
+
+# Peaks of one MI355X (vendor figures).
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # vendor FP32 vector figure (counts packed dual-rate FP32)
+FP32_NONPACKED_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12  # 256 CU x 64 lanes x FMA x 2.4 GHz = 78.6
+
+WORKLOADS = {
+    "ondevice": dict(n=1 << 22, m=1 << 22, d=10, k=10, h=10, kind="mixture", comps=16),
+    "small": dict(n=1 << 15, m=1 << 12, d=10, k=10, h=6, kind="uniform", comps=0),
+}
+
+
+def make_inputs(w, seed):
+    if w["kind"] == "uniform":
+        return datagen.small_uniform(seed, w["n"], w["m"], w["d"])
+    return datagen.mixture_pq(seed, w["n"], w["m"], w["d"], w["comps"])
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def cpu_baseline(P, Q, k, budget_s):
+    """The oracle's float64 k-d tree (leaf size 32), OpenMP over queries on every host core."""
+    import oracle
+    threads = oracle.max_threads()
+    tree = oracle.KdTree64(P, 32)
+    # calibrate on a small sample, then time a bounded sample of about budget_s seconds
+    cal = min(len(Q), 2048)
+    t0 = time.perf_counter()
+    tree.query(Q[:cal], k)
+    rate = cal / max(time.perf_counter() - t0, 1e-6)
+    ns = int(min(len(Q), max(cal, rate * budget_s)))
+    t0 = time.perf_counter()
+    tree.query(Q[:ns], k)
+    dt = time.perf_counter() - t0
+    return {"value": ns / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {ns} of {len(Q)} queries against all {len(P)} points; float64 k-d tree, "
+                      f"leaf size 32, OpenMP over queries ({threads} threads, {cpu_model()})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ondevice", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=datagen.DEFAULT_SEED)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU baseline sample size in seconds")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the query path has no multi-GPU form here "
+              "(queries would shard by ranks with no exchange); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1512_02831_amd as bkd
+
+    w = WORKLOADS[args.workload]
+    n, m, d, k, h = w["n"], w["m"], w["d"], w["k"], w["h"]
+    P, Q = make_inputs(w, args.seed)
+    # lock-step rounds: every active query is fetched each iteration (results do not depend on B, M)
+    tree = bkd.build(P, h, buffer_size=-1, fetch_size=-1, flags=bkd.FLAG_TIMING)
+    dQ = torch.from_numpy(Q).to("cuda")
+    di = torch.empty((m, k), dtype=torch.int64, device="cuda")
+    dd = torch.empty((m, k), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.Stream()
+
+    for _ in range(args.warmup):
+        bkd.query_async(tree, dQ, k, di, dd, stream=stream)
+    torch.cuda.synchronize()
+
+    scan_ms, launches, pairs, calls = 0.0, 0, 0, 0
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        bkd.query_async(tree, dQ, k, di, dd, stream=stream)
+        st = bkd.last_stats(tree)
+        scan_ms += st["scan_ms"]
+        launches += st["scan_launches"]
+        pairs += st["pairs"]
+        calls += st["calls"]
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+
+    ms_per_step = wall * 1e3 / args.steps
+    value = m * args.steps / wall
+    # dominant kernel: the leaf scan; algorithmic work = 3d flops per (query, point) pair
+    flops = 3.0 * d * pairs
+    achieved = flops / (scan_ms * 1e-3) / 1e12 if scan_ms > 0 else 0.0
+    roofline = {
+        "kernel": "k_leaf_scan",
+        "bound": "alu",
+        "achieved": round(achieved, 3),
+        "peak": FP32_VECTOR_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+        "traffic": None,
+        "peak_nonpacked": round(FP32_NONPACKED_TFLOPS, 1),
+        "frac_nonpacked": round(achieved / FP32_NONPACKED_TFLOPS, 4),
+        "avg_launch_ms": round(scan_ms / max(launches, 1), 4),
+        "launches_per_step": launches / args.steps,
+        "pairs_per_step": pairs // args.steps,
+        "flops_per_pair": 3 * d,
+        "scan_share_of_step": round(scan_ms / max(gpu_ms, 1e-9), 4),
+    }
+    out = {
+        "metric": "kNN queries/s (d=10,k=10)",
+        "value": round(value, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: n={n} m={m} d={d} k={k} height={h} "
+                               f"{'16-component Gaussian mixture' if w['kind'] == 'mixture' else 'uniform [0,1]^d'}, "
+                               f"seed {args.seed}, lock-step rounds",
+                   "n": n, "m": m, "d": d, "k": k, "height": h, "rounds_per_step": calls / args.steps},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(P, Q, k, args.cpu_seconds)
+    tree.free()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

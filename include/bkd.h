@@ -1,0 +1,208 @@
+/*
+ * bkd.h -- C ABI of the MI355X buffer k-d tree exact kNN library.
+ *
+ * Method: Gieseke, Oancea, Mahabal, Igel, Heskes, "Bigger Buffer k-d Trees on
+ * Multi-Many-Core Systems" (arXiv 1512.02831).  The problem solved is the one
+ * of Section 2.2: for every query q in Q, the k >= 1 nearest points of the
+ * reference set P under the Euclidean distance.  A query runs the buffered
+ * loop of Algorithm 1 (Section 2.4) on one AMD Instinct MI355X (gfx950):
+ * queries are routed through a top tree (FindLeafBatch), parked in per-leaf
+ * buffers, and all buffers are then processed by a brute-force leaf scan with
+ * a top-k merge (ProcessAllBuffers).  When the leaf structure exceeds the
+ * device budget it is streamed in chunks with copy/compute overlap
+ * (Section 3.2).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns BKD_OK (0) or a negative BKD_E* code.  No C++
+ *     exception, abort or exit crosses this boundary.  bkd_last_error()
+ *     returns a thread-local message describing the last failure.
+ *   - Points are float32, row-major [count][d].  Indices are 0-based rows of P.
+ *   - Results are row-major [m][k]: the k nearest points of each query in
+ *     ascending distance; exact distance ties are broken by smaller index.
+ *     Distances are Euclidean (the square root of the float32 squared
+ *     distance defined under bkd_query).
+ *   - On error the outputs are unspecified, bkd_build creates nothing and an
+ *     existing tree stays valid.
+ *   - A tree may be used by one query at a time (the served API interleaves
+ *     requests on shared trees itself).
+ */
+#ifndef BKD_H
+#define BKD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes. */
+#define BKD_OK 0
+#define BKD_EINVAL (-1)   /* invalid argument (NULL, range, non-finite value)          */
+#define BKD_ENOMEM (-2)   /* host, pinned or device allocation failed                   */
+#define BKD_EBUDGET (-3)  /* leaf budget smaller than two leaves of the leaf structure  */
+#define BKD_EDEVICE (-4)  /* a HIP call failed; the message holds hipGetErrorString     */
+#define BKD_EBUSY (-5)    /* served form: no capacity left and the call is non-blocking */
+#define BKD_ETIMEOUT (-6) /* served form: bkd_wait timed out                            */
+#define BKD_ENOTFOUND (-7)/* served form: unknown request or tree id                    */
+
+#define BKD_MAX_DIM 32
+#define BKD_MAX_K 64
+#define BKD_MAX_HEIGHT 24
+
+/* Chunk partition of the leaf structure (Section 3.2). */
+#define BKD_CHUNK_LEAF 0     /* chunks hold whole leaves, packed up to the chunk capacity      */
+#define BKD_CHUNK_POSITION 1 /* chunk j of N holds positions [ceil((j-1)n/N), ceil(jn/N))      */
+
+/* Option flags. */
+#define BKD_FLAG_TRACE 1  /* record every fetch's (query, leaf) pairs (for parity checks)     */
+#define BKD_FLAG_TIMING 2 /* time every leaf-scan launch with HIP events                       */
+#define BKD_FLAG_SQUARED 4 /* out_dist receives the float32 squared distance, not its root      */
+
+typedef struct bkd_tree bkd_tree;
+
+/*
+ * Schedule and memory options of a tree.  Zero-initialised fields take the
+ * defaults of Section 4.1 (footnote on parameters): B = 2^(24-h), M = 10 B.
+ *   buffer_size   B.  A ProcessAllBuffers call is triggered once a buffer holds
+ *                 at least ceil(B/2) query indices (Algorithm 1).  < 0: never
+ *                 half-full; buffers are processed only when both queues are
+ *                 empty.  Buffers are pooled, so B only sets the trigger.
+ *   fetch_size    M, indices fetched per iteration (reinsert first, then
+ *                 input, both FIFO).  < 0: fetch everything available, which
+ *                 makes every iteration one lock-step round over all active
+ *                 queries.  Results do not depend on B or M.
+ *   leaf_budget_bytes  device bytes reserved for the leaf structure.  0 (and
+ *                 num_chunks 0): the whole structure is resident on the
+ *                 device.  Otherwise, if the structure does not fit, it stays
+ *                 in pinned host memory and is streamed through two device
+ *                 chunk buffers of budget/2 bytes each (Section 3.1, 3.2).
+ *   chunk_mode    BKD_CHUNK_LEAF or BKD_CHUNK_POSITION.
+ *   num_chunks    > 0 forces streaming with exactly this many chunks (testing
+ *                 and the chunked-versus-resident comparison).
+ *   device        HIP device ordinal.
+ *   flags         BKD_FLAG_* bits.
+ * Results are identical for every value of these options.
+ */
+typedef struct bkd_options {
+    int64_t buffer_size;
+    int64_t fetch_size;
+    int64_t leaf_budget_bytes;
+    int32_t chunk_mode;
+    int32_t num_chunks;
+    int32_t device;
+    int32_t flags;
+} bkd_options;
+
+/* Static facts of a built tree. */
+typedef struct bkd_tree_info {
+    int64_t n;            /* reference points                                  */
+    int32_t d;            /* dimension                                         */
+    int32_t height;       /* h: 2^h leaves, 2^h - 1 splitting values           */
+    int64_t buffer_size;  /* effective B (-1: never half-full)                 */
+    int64_t fetch_size;   /* effective M (-1: everything available)            */
+    int32_t num_chunks;   /* 1 when resident                                   */
+    int32_t resident;     /* 1: leaf structure lives on the device             */
+    int64_t leaf_bytes;   /* bytes of the leaf structure (points + indices)    */
+    int64_t chunk_capacity_bytes; /* bytes of one device chunk buffer          */
+} bkd_tree_info;
+
+/* Counters of the last query on a tree. */
+typedef struct bkd_stats {
+    int64_t queries;      /* m                                                 */
+    int64_t fetches;      /* FindLeafBatch invocations                         */
+    int64_t calls;        /* ProcessAllBuffers invocations                     */
+    int64_t pairs;        /* (query, leaf point) pairs scanned                 */
+    int64_t visits;       /* (query, leaf) visits                              */
+    int64_t scan_launches;/* leaf-scan kernel launches                         */
+    int64_t chunk_copies; /* host-to-device chunk copies                       */
+    int64_t bytes_h2d;    /* bytes of those copies                             */
+    double scan_ms;       /* sum of leaf-scan launch durations (BKD_FLAG_TIMING)*/
+    double total_ms;      /* wall time of the query call on the host           */
+} bkd_stats;
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *bkd_last_error(void);
+
+/* Library version string. */
+const char *bkd_version(void);
+
+/* Fill *out with the defaults for a tree of the given height.  Host only. */
+int bkd_default_options(int32_t height, bkd_options *out);
+
+/*
+ * Build a buffer k-d tree (Section 2.3 construction, Section 3.1 host build).
+ *   P       host pointer, row-major [n][d] float32, caller-owned; the library
+ *           copies what it needs and keeps no pointer to P.
+ *   n       1 <= n <= 2^31 - 1.
+ *   d       1 <= d <= BKD_MAX_DIM.
+ *   height  0 <= h <= BKD_MAX_HEIGHT and 2^h <= n.  A node holding c points
+ *           splits dimension (level mod d) at the point of rank floor(c/2)
+ *           under the order (coordinate, index): the left child takes the
+ *           floor(c/2) smallest, the split value is the coordinate of the
+ *           smallest point on the right, and a query goes left iff its
+ *           coordinate is below the split value.  Leaves keep ascending index.
+ *   opt     NULL for defaults.
+ *   out     receives the tree handle, owned by the library until bkd_free.
+ * Errors: BKD_EINVAL (NULL, ranges, non-finite P), BKD_EBUDGET, BKD_ENOMEM,
+ * BKD_EDEVICE.
+ */
+int bkd_build(const float *P, int64_t n, int32_t d, int32_t height, const bkd_options *opt, bkd_tree **out);
+
+/* Release a tree and all of its host and device memory.  NULL is a no-op. */
+int bkd_free(bkd_tree *tree);
+
+/*
+ * Exact kNN of m queries (Algorithm 1), host pointers, blocking.
+ *   Q         host [m][d] float32 (finite), caller-owned.
+ *   m         0 <= m <= 2^31 - 1.
+ *   k         1 <= k <= min(n, BKD_MAX_K).
+ *   out_idx   host [m][k] int64, caller-owned.
+ *   out_dist  host [m][k] float32, caller-owned.
+ * Squared distances are computed in float32 as t_j = q_j - x_j (rounded),
+ * acc = fma(t_j, t_j, acc) for j = 0..d-1 from +0; out_dist = sqrt(acc).
+ * Errors: BKD_EINVAL, BKD_ENOMEM, BKD_EDEVICE.
+ */
+int bkd_query(bkd_tree *tree, const float *Q, int64_t m, int32_t k, int64_t *out_idx, float *out_dist);
+
+/*
+ * Same with device pointers, ordered on `stream` (a hipStream_t; NULL = the
+ * null stream).  dQ, d_idx and d_dist must stay valid until the work on the
+ * stream has completed.  The host takes part in the loop's control flow
+ * (reading a few counters per iteration), so the call returns once the last
+ * kernel is enqueued; synchronise the stream before reading the outputs.
+ */
+int bkd_query_async(bkd_tree *tree, const float *dQ, int64_t m, int32_t k, int64_t *d_idx, float *d_dist,
+                    void *stream);
+
+/* Static facts of the tree. */
+int bkd_tree_info_get(const bkd_tree *tree, bkd_tree_info *out);
+
+/*
+ * Copy out the serialized tree: split [2^h - 1] (heap order), leaf_off
+ * [2^h + 1] (leaf l holds leaf-structure positions [leaf_off[l],
+ * leaf_off[l+1])) and perm [n] (index of the point at each position).
+ * Any pointer may be NULL to skip that array.
+ */
+int bkd_tree_export(const bkd_tree *tree, float *split, int64_t *leaf_off, int32_t *perm);
+
+/* Chunk bounds (positions [lo[j], hi[j])) of the streaming plan; num_chunks entries. */
+int bkd_chunk_plan(const bkd_tree *tree, int64_t *lo, int64_t *hi);
+
+/* Counters of the last query. */
+int bkd_last_stats(const bkd_tree *tree, bkd_stats *out);
+
+/*
+ * Trace of the last query when BKD_FLAG_TRACE is set: for every
+ * ProcessAllBuffers call c, the (query, leaf) pairs fetched since the
+ * previous call in fetch order, entries call_off[c] .. call_off[c+1]-1;
+ * leaf -1 marks a query whose traversal finished.  bkd_trace_size gives the
+ * sizes; bkd_trace_get fills caller arrays of those sizes.
+ */
+int bkd_trace_size(const bkd_tree *tree, int64_t *ncalls, int64_t *length);
+int bkd_trace_get(const bkd_tree *tree, int64_t *call_off, int32_t *query, int32_t *leaf);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BKD_H */

@@ -50,6 +50,12 @@ def _load():
     lib.orc_brute_f32c.restype = ctypes.c_int
     lib.orc_kdtree_f64.argtypes = [P, i64, P, i64, i32, i32, i32, P, P, i32]
     lib.orc_kdtree_f64.restype = ctypes.c_int
+    lib.orc_kdtree_f64_build.argtypes = [P, i64, i32, i32, i32]
+    lib.orc_kdtree_f64_build.restype = P
+    lib.orc_kdtree_f64_query.argtypes = [P, P, i64, i32, P, P, i32]
+    lib.orc_kdtree_f64_query.restype = ctypes.c_int
+    lib.orc_kdtree_f64_free.argtypes = [P]
+    lib.orc_kdtree_f64_free.restype = None
     lib.orc_traverse_f32.argtypes = [P, i32, i32, P, P, P, P, i32, P, i64, P]
     lib.orc_traverse_f32.restype = i64
     lib.orc_traverse_many_f32.argtypes = [P, i32, i32, P, P, P, P, i64, i32, P, P, P, i32]
@@ -136,6 +142,31 @@ def kdtree_f64(P, Q, k: int, leaf_size: int = 32, threads: int = 0):
     if rc != 0:
         raise ValueError("orc_kdtree_f64 rejected its arguments")
     return idx, d2
+
+
+class KdTree64:
+    """Classical float64 k-d tree (leaves of about `leaf_size` points), built once."""
+
+    def __init__(self, P, leaf_size: int = 32, threads: int = 0):
+        self.P = _f32(P)  # the C tree refers to these points
+        self.d = self.P.shape[1]
+        self._h = _load().orc_kdtree_f64_build(_ptr(self.P), self.P.shape[0], self.d, leaf_size, threads)
+        if not self._h:
+            raise ValueError("orc_kdtree_f64_build failed")
+
+    def query(self, Q, k: int, threads: int = 0):
+        Q = _f32(Q)
+        m = Q.shape[0]
+        idx = np.zeros((m, k), dtype=np.int64)
+        d2 = np.zeros((m, k), dtype=np.float64)
+        if _load().orc_kdtree_f64_query(self._h, _ptr(Q), m, k, _ptr(idx), _ptr(d2), threads) != 0:
+            raise ValueError("orc_kdtree_f64_query failed")
+        return idx, d2
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _load().orc_kdtree_f64_free(self._h)
+            self._h = None
 
 
 def traverse_f32(P, tree: Tree, q, k: int, max_leaves: int = 1 << 16):

@@ -280,34 +280,70 @@ static void kd64_search(const kd64_t *t, int64_t v, const float *q, double *dl, 
 }
 
 /*
- * Builds its own canonical tree with leaves of about `leaf_size` points
- * (height floor(log2(n / leaf_size))), then answers every query.
+ * Classical k-d tree with leaves of about `leaf_size` points (height
+ * floor(log2(n / leaf_size))), built once, queried many times.
  */
-int orc_kdtree_f64(const float *P, int64_t n, const float *Q, int64_t m, int32_t d, int32_t k, int32_t leaf_size,
-                   int64_t *out_idx, double *out_d2, int32_t nthreads)
+typedef struct {
+    kd64_t t;
+    float *split;
+    int64_t *leaf_off;
+    int32_t *perm;
+} kd64_tree_t;
+
+void orc_kdtree_f64_free(kd64_tree_t *T)
 {
-    if (!P || !Q || n < 1 || m < 0 || d < 1 || k < 1 || k > n || leaf_size < 1) return -1;
+    if (!T) return;
+    free(T->split); free(T->leaf_off); free(T->perm); free(T);
+}
+
+kd64_tree_t *orc_kdtree_f64_build(const float *P, int64_t n, int32_t d, int32_t leaf_size, int32_t nthreads)
+{
+    if (!P || n < 1 || d < 1 || leaf_size < 1) return NULL;
     set_threads(nthreads);
     int h = 0;
     while (((int64_t)leaf_size << (h + 1)) <= n && h < 30) h++;
     int64_t nleaf = (int64_t)1 << h;
-    float *split = (float *)malloc(sizeof(float) * (size_t)(nleaf > 1 ? nleaf - 1 : 1));
-    int64_t *leaf_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nleaf + 1));
-    int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
-    if (!split || !leaf_off || !perm || orc_build(P, n, d, h, split, leaf_off, perm) != 0) {
-        free(split); free(leaf_off); free(perm);
-        return -1;
+    kd64_tree_t *T = (kd64_tree_t *)calloc(1, sizeof(kd64_tree_t));
+    if (!T) return NULL;
+    T->split = (float *)malloc(sizeof(float) * (size_t)(nleaf > 1 ? nleaf - 1 : 1));
+    T->leaf_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nleaf + 1));
+    T->perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!T->split || !T->leaf_off || !T->perm || orc_build(P, n, d, h, T->split, T->leaf_off, T->perm) != 0) {
+        orc_kdtree_f64_free(T);
+        return NULL;
     }
-    kd64_t t = {P, split, leaf_off, perm, nleaf - 1, d, k};
+    kd64_t t = {P, T->split, T->leaf_off, T->perm, nleaf - 1, d, 0};
+    T->t = t;
+    return T;
+}
+
+/* P must stay alive while the tree is used (the tree refers to it). */
+int orc_kdtree_f64_query(kd64_tree_t *T, const float *Q, int64_t m, int32_t k, int64_t *out_idx, double *out_d2,
+                         int32_t nthreads)
+{
+    if (!T || !Q || m < 0 || k < 1) return -1;
+    set_threads(nthreads);
+    kd64_t t = T->t;
+    t.k = k;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t qi = 0; qi < m; qi++) {
         double *dl = out_d2 + qi * k;
         int64_t *il = out_idx + qi * k;
         for (int i = 0; i < k; i++) { dl[i] = INFINITY; il[i] = INT64_MAX; }
-        kd64_search(&t, 0, Q + qi * d, dl, il);
+        kd64_search(&t, 0, Q + qi * t.d, dl, il);
     }
-    free(split); free(leaf_off); free(perm);
     return 0;
+}
+
+int orc_kdtree_f64(const float *P, int64_t n, const float *Q, int64_t m, int32_t d, int32_t k, int32_t leaf_size,
+                   int64_t *out_idx, double *out_d2, int32_t nthreads)
+{
+    if (!P || !Q || n < 1 || m < 0 || d < 1 || k < 1 || k > n || leaf_size < 1) return -1;
+    kd64_tree_t *T = orc_kdtree_f64_build(P, n, d, leaf_size, nthreads);
+    if (!T) return -1;
+    int rc = orc_kdtree_f64_query(T, Q, m, k, out_idx, out_d2, nthreads);
+    orc_kdtree_f64_free(T);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */

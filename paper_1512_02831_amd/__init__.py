@@ -1,0 +1,238 @@
+"""Python binding of the MI355X buffer k-d tree library (``libbkd.so``).
+
+Argument marshalling only: every step of a query runs in the library's HIP
+kernels.  The names follow the C ABI in ``include/bkd.h`` (``bkd_build`` ->
+``build``, ``bkd_query`` -> ``query`` ...).  Host arrays are numpy; device
+arrays are torch tensors on a HIP device (torch provides memory and streams
+only).  There is no CPU fallback: if the library has not been built, every
+entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbkd.so")
+
+OK, EINVAL, ENOMEM, EBUDGET, EDEVICE, EBUSY, ETIMEOUT, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7
+CHUNK_LEAF, CHUNK_POSITION = 0, 1
+FLAG_TRACE, FLAG_TIMING, FLAG_SQUARED = 1, 2, 4
+MAX_DIM, MAX_K, MAX_HEIGHT = 32, 64, 24
+
+_lib = None
+
+
+class BkdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"bkd error {code}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("buffer_size", ctypes.c_int64), ("fetch_size", ctypes.c_int64),
+                ("leaf_budget_bytes", ctypes.c_int64), ("chunk_mode", ctypes.c_int32),
+                ("num_chunks", ctypes.c_int32), ("device", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class TreeInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("buffer_size", ctypes.c_int64), ("fetch_size", ctypes.c_int64), ("num_chunks", ctypes.c_int32),
+                ("resident", ctypes.c_int32), ("leaf_bytes", ctypes.c_int64),
+                ("chunk_capacity_bytes", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("queries", ctypes.c_int64), ("fetches", ctypes.c_int64), ("calls", ctypes.c_int64),
+                ("pairs", ctypes.c_int64), ("visits", ctypes.c_int64), ("scan_launches", ctypes.c_int64),
+                ("chunk_copies", ctypes.c_int64), ("bytes_h2d", ctypes.c_int64), ("scan_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+# name -> (restype, argtypes)
+_V, _I64, _I32, _D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+_PROTOS = {
+    "bkd_last_error": (ctypes.c_char_p, []),
+    "bkd_version": (ctypes.c_char_p, []),
+    "bkd_default_options": (ctypes.c_int, [_I32, _V]),
+    "bkd_build": (ctypes.c_int, [_V, _I64, _I32, _I32, _V, _V]),
+    "bkd_free": (ctypes.c_int, [_V]),
+    "bkd_query": (ctypes.c_int, [_V, _V, _I64, _I32, _V, _V]),
+    "bkd_query_async": (ctypes.c_int, [_V, _V, _I64, _I32, _V, _V, _V]),
+    "bkd_tree_info_get": (ctypes.c_int, [_V, _V]),
+    "bkd_tree_export": (ctypes.c_int, [_V, _V, _V, _V]),
+    "bkd_chunk_plan": (ctypes.c_int, [_V, _V, _V]),
+    "bkd_last_stats": (ctypes.c_int, [_V, _V]),
+    "bkd_trace_size": (ctypes.c_int, [_V, _V, _V]),
+    "bkd_trace_get": (ctypes.c_int, [_V, _V, _V, _V]),
+}
+
+
+def exported_names():
+    return list(_PROTOS)
+
+
+def lib():
+    """Load ``libbkd.so``; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    try:  # share torch's HIP runtime when torch is present (one runtime per process)
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _PROTOS.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise BkdError(rc, lib().bkd_last_error().decode())
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def version() -> str:
+    return lib().bkd_version().decode()
+
+
+def default_options(height: int) -> Options:
+    o = Options()
+    _check(lib().bkd_default_options(height, ctypes.byref(o)))
+    return o
+
+
+def make_options(height: int, buffer_size=None, fetch_size=None, leaf_budget_bytes=None, chunk_mode=None,
+                 num_chunks=None, device=None, flags=None) -> Options:
+    o = default_options(height)
+    for name, val in (("buffer_size", buffer_size), ("fetch_size", fetch_size),
+                      ("leaf_budget_bytes", leaf_budget_bytes), ("chunk_mode", chunk_mode),
+                      ("num_chunks", num_chunks), ("device", device), ("flags", flags)):
+        if val is not None:
+            setattr(o, name, val)
+    return o
+
+
+class Tree:
+    """A built buffer k-d tree (owns a ``bkd_tree*``)."""
+
+    def __init__(self, handle, n, d, height):
+        self._h, self.n, self.d, self.height = handle, n, d, height
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("tree has been freed")
+        return self._h
+
+    def free(self):
+        if self._h:
+            _check(lib().bkd_free(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+
+def build(P, height: int, options: Options | None = None, **kw) -> Tree:
+    """``bkd_build``: P host float32 [n, d]."""
+    P = np.ascontiguousarray(P, dtype=np.float32)
+    if P.ndim != 2:
+        raise ValueError("P must be 2-D [n, d]")
+    n, d = P.shape
+    if options is None and kw:
+        options = make_options(height, **kw)
+    h = ctypes.c_void_p()
+    _check(lib().bkd_build(_p(P), n, d, height, ctypes.byref(options) if options is not None else None,
+                           ctypes.byref(h)))
+    return Tree(h.value, n, d, height)
+
+
+def query(tree: Tree, Q, k: int):
+    """``bkd_query``: host Q float32 [m, d] -> (idx int64 [m, k], dist float32 [m, k])."""
+    Q = np.ascontiguousarray(Q, dtype=np.float32)
+    if Q.ndim != 2 or Q.shape[1] != tree.d:
+        raise ValueError("Q must be [m, d] with the tree's d")
+    m = Q.shape[0]
+    idx = np.empty((m, k), dtype=np.int64)
+    dist = np.empty((m, k), dtype=np.float32)
+    _check(lib().bkd_query(tree.handle, _p(Q), m, k, _p(idx), _p(dist)))
+    return idx, dist
+
+
+def query_async(tree: Tree, dQ, k: int, d_idx, d_dist, stream=None):
+    """``bkd_query_async`` on torch device tensors: dQ [m, d] float32, d_idx [m, k] int64, d_dist [m, k] float32."""
+    import torch
+    for t, dt in ((dQ, torch.float32), (d_idx, torch.int64), (d_dist, torch.float32)):
+        if not (t.is_cuda and t.is_contiguous() and t.dtype == dt):
+            raise ValueError("device tensors must be contiguous HIP tensors of the documented dtypes")
+    m = dQ.shape[0]
+    if dQ.shape != (m, tree.d) or d_idx.shape != (m, k) or d_dist.shape != (m, k):
+        raise ValueError("shape mismatch")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().bkd_query_async(tree.handle, dQ.data_ptr(), m, k, d_idx.data_ptr(), d_dist.data_ptr(),
+                                 ctypes.c_void_p(s.cuda_stream)))
+
+
+def tree_info(tree: Tree) -> TreeInfo:
+    info = TreeInfo()
+    _check(lib().bkd_tree_info_get(tree.handle, ctypes.byref(info)))
+    return info
+
+
+def tree_export(tree: Tree):
+    """(split [2^h-1] float32, leaf_off [2^h+1] int64, perm [n] int32)."""
+    nleaf = 1 << tree.height
+    split = np.zeros(max(nleaf - 1, 1), dtype=np.float32)
+    leaf_off = np.zeros(nleaf + 1, dtype=np.int64)
+    perm = np.zeros(tree.n, dtype=np.int32)
+    _check(lib().bkd_tree_export(tree.handle, _p(split), _p(leaf_off), _p(perm)))
+    return split[: nleaf - 1], leaf_off, perm
+
+
+def chunk_plan(tree: Tree):
+    N = tree_info(tree).num_chunks
+    lo = np.zeros(N, dtype=np.int64)
+    hi = np.zeros(N, dtype=np.int64)
+    _check(lib().bkd_chunk_plan(tree.handle, _p(lo), _p(hi)))
+    return lo, hi
+
+
+def last_stats(tree: Tree) -> dict:
+    s = Stats()
+    _check(lib().bkd_last_stats(tree.handle, ctypes.byref(s)))
+    return s.as_dict()
+
+
+def trace(tree: Tree):
+    """(call_off int64 [calls+1], query int32 [len], leaf int32 [len]) of the last traced query."""
+    nc, ln = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().bkd_trace_size(tree.handle, ctypes.byref(nc), ctypes.byref(ln)))
+    off = np.zeros(nc.value + 1, dtype=np.int64)
+    q = np.zeros(max(ln.value, 1), dtype=np.int32)
+    leaf = np.zeros(max(ln.value, 1), dtype=np.int32)
+    _check(lib().bkd_trace_get(tree.handle, _p(off), _p(q), _p(leaf)))
+    return off, q[: ln.value], leaf[: ln.value]

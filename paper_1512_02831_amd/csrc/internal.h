@@ -1,0 +1,192 @@
+// internal.h -- shared host-side declarations of the bkd library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "../../include/bkd.h"
+
+namespace bkd {
+
+// ---------------------------------------------------------------------------
+// Errors: every failure becomes a BkdError caught at the ABI boundary.
+
+struct BkdError {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string &msg);
+void set_error(int code, const std::string &msg);
+void clear_error();
+
+#define BKD_HIP(call)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            ::bkd::fail(e_ == hipErrorOutOfMemory ? BKD_ENOMEM : BKD_EDEVICE,                      \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                        \
+    } while (0)
+
+// Parallel loop on host threads (no OpenMP runtime inside the library).
+void parallel_for(int64_t count, const std::function<void(int64_t, int64_t)> &body, int64_t grain = 1);
+int host_threads();
+
+// ---------------------------------------------------------------------------
+// Device buffers.
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void ensure(size_t need);  // grow (contents not preserved)
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(p); }
+    ~DevBuf() { release(); }
+};
+
+struct PinnedBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void ensure(size_t need);
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(p); }
+    ~PinnedBuf() { release(); }
+};
+
+// ---------------------------------------------------------------------------
+// Canonical tree on the host.
+
+struct HostTree {
+    int64_t n = 0;
+    int d = 0;
+    int h = 0;
+    std::vector<float> split;      // 2^h - 1
+    std::vector<int64_t> leaf_off; // 2^h + 1
+    std::vector<int32_t> perm;     // n
+};
+
+// Build the canonical tree of P (row-major n x d).
+void build_canonical(const float *P, int64_t n, int d, int h, HostTree &t);
+
+// One chunk of the leaf structure: positions [lo, hi) covering leaves [leaf_first, leaf_last].
+struct Chunk {
+    int64_t lo, hi;
+    int32_t leaf_first, leaf_last;
+    size_t host_offset;  // byte offset of its block in the pinned host structure
+    size_t bytes;        // d*(hi-lo) floats + (hi-lo) int32
+};
+
+// Device control words (one small array per tree, read back by the host).
+enum Ctl : int {
+    CTL_MAXCNT = 0,   // largest buffer fill since the last call
+    CTL_NVALID = 1,   // fetched entries that got a leaf since the last call
+    CTL_V = 2,        // buffered entries of the current call
+    CTL_T = 3,        // work items of the current call
+    CTL_BAD = 4,      // non-finite query coordinate seen
+    CTL_S = 5,        // sparse (one wave per buffered query) items of the current call
+    CTL_PAIRS_LO = 6, // 64-bit pairs counter (two words)
+    CTL_VISITS_LO = 8,
+    CTL_WORDS = 16
+};
+
+// Query-tile width of the dense leaf scan (queries per work item), and the
+// buffer fill below which a leaf is scanned with one wave per buffered query.
+constexpr int SCAN_QT = 256;
+constexpr int SCAN_DENSE_MIN = 32;
+
+struct Tree {
+    HostTree host;
+    bkd_options opt{};
+    int64_t B = 0, M = 0;  // effective; -1 = unlimited
+    int device = 0;
+    int nleaf = 1;
+
+    // device top tree and leaf bounds
+    DevBuf d_split, d_leaf_off;
+
+    // leaf structure
+    bool resident = true;
+    std::vector<Chunk> chunks;
+    size_t chunk_cap_bytes = 0;
+    int64_t chunk_cap_points = 0;
+    DevBuf d_chunk[2];     // resident: d_chunk[0] holds everything
+    int chunk_in[2] = {-1, -1};
+    PinnedBuf h_leaf;      // streaming: chunk-major pinned host structure
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t ev_copied[2] = {nullptr, nullptr};
+    hipEvent_t ev_used[2] = {nullptr, nullptr};
+
+    // query workspace
+    DevBuf d_Q, d_outi, d_outd;
+    DevBuf d_keys, d_node, d_ring, d_pleaf, d_pq, d_tleaf, d_tq, d_hist;
+    DevBuf d_cnt, d_off, d_tiles, d_ctl;
+    PinnedBuf h_ctl, h_tiles;
+
+    // results of the last query
+    bkd_stats stats{};
+    std::vector<int64_t> trace_off;
+    std::vector<int32_t> trace_q, trace_leaf;
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (kernels.hip, scan_*.hip).
+
+struct FetchSpec {
+    const int32_t *ring;  // reinsert ring
+    int64_t ring_head, ring_count, ring_cap;
+    int64_t in_start, in_count;  // input queue part: queries in_start .. in_start + in_count - 1
+};
+
+void launch_init_state(int32_t *node, uint64_t *keys, int64_t m, int K, hipStream_t s);
+void launch_check_finite(const float *Q, int64_t count, int32_t *ctl, hipStream_t s);
+void launch_find_leaf(const FetchSpec &f, const float *Q, int d, int32_t *node, const uint64_t *keys, int K, int k,
+                      const float *split, int h, uint32_t *pend_leaf, int32_t *pend_q, int64_t pend_base,
+                      int32_t *cnt, int32_t *ctl, hipStream_t s);
+// Stable sort of (leaf, query) pairs by leaf; returns which buffer holds the result (0: a, 1: b).
+int launch_sort_pairs(uint32_t *key_a, int32_t *val_a, uint32_t *key_b, int32_t *val_b, int64_t count, int key_bits,
+                      uint32_t *hist, hipStream_t s);
+size_t sort_hist_words(int64_t count);
+// tiles: [2][nleaf+1] -- dense work-item offsets, then sparse (per buffered query) offsets.
+void launch_leaf_offsets(const int32_t *cnt, const int32_t *leaf_off, int nleaf, int qt, int dense_min, int32_t *off,
+                         int32_t *tiles, int32_t *ctl, hipStream_t s);
+void launch_ring_append(int32_t *ring, int64_t cap, int64_t tail, const int32_t *src, int64_t count, hipStream_t s);
+void launch_finalize(const uint64_t *keys, int K, int k, int64_t m, int64_t *idx, float *dist, bool squared,
+                     hipStream_t s);
+void launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s);
+
+struct ScanArgs {
+    const int32_t *tiles;     // [nleaf+1] dense work-item offsets
+    const int32_t *sparse;    // [nleaf+1] sparse work-item offsets
+    const int32_t *off;       // [nleaf+1] buffer offsets
+    const int32_t *bufq;      // buffered query ids, leaf order
+    const int32_t *leaf_off;  // [nleaf+1] leaf positions
+    const float *X;           // chunk points, [d][pitch]
+    const int32_t *orig;      // chunk original indices, [pitch]
+    int64_t pitch;            // points per dimension row in the chunk
+    int64_t chunk_lo, chunk_hi;  // positions held by the chunk
+    int32_t item_first, item_count;    // dense items of this launch
+    int32_t sitem_first, sitem_count;  // sparse items of this launch
+    int32_t leaf_first, leaf_last;
+    const float *Q;           // [m][d]
+    int d;
+    uint64_t *keys;           // [m][K]
+};
+
+// Dispatch on padded dimension and key capacity.
+void launch_leaf_scan(const ScanArgs &a, int K, hipStream_t s);
+int padded_dim(int d);
+int key_capacity(int k);
+
+// ---------------------------------------------------------------------------
+// Host driver (query.cpp).
+
+void tree_build(Tree &t, const float *P, int64_t n, int d, int h, const bkd_options &opt);
+void tree_query_device(Tree &t, const float *dQ, int64_t m, int k, int64_t *d_idx, float *d_dist, hipStream_t s);
+
+}  // namespace bkd

@@ -1,0 +1,437 @@
+// kernels.hip -- integer and traversal kernels of the query loop (gfx950, wave64).
+//
+//   k_find_leaf     FindLeafBatch (Algorithm 1; search phases of Section 2.3)
+//   k_radix_*       stable buffer insertion: fetched (leaf, query) pairs are
+//                   grouped by leaf in fetch order (Algorithm 1, buffer insert)
+//   k_leaf_offsets  buffer offsets and work items of one ProcessAllBuffers call
+//   k_ring_append   reinsert queue append (Algorithm 1)
+//   k_finalize      keys -> (index, Euclidean distance)
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "internal.h"
+
+namespace bkd {
+
+namespace {
+
+constexpr int32_t NODE_FRESH = -2;
+constexpr int32_t NODE_DONE = -1;
+constexpr uint64_t EMPTY_KEY = 0x7F800000FFFFFFFFull;
+
+inline unsigned grid_for(int64_t count, int threads) { return (unsigned)((count + threads - 1) / threads); }
+
+__device__ inline uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
+
+// ---------------------------------------------------------------------------
+
+__global__ void k_init_state(int32_t *node, uint64_t *keys, int64_t m, int K)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) node[i] = NODE_FRESH;
+    int64_t total = m * K;
+    for (int64_t j = i; j < total; j += (int64_t)gridDim.x * blockDim.x) keys[j] = EMPTY_KEY;
+}
+
+__global__ void k_check_finite(const float *Q, int64_t count, int32_t *ctl)
+{
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        bad |= !isfinite(Q[i]);
+    if (__ballot(bad) != 0ull && __lane_id() == 0) atomicOr(&ctl[CTL_BAD], 1);
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t count)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+// Descend from heap node v at the given level to a leaf: left iff q[dim] < split.
+__device__ inline int32_t descend(const float *q, const float *split, int32_t v, int level, int h, int d)
+{
+    int dim = level % d;
+    while (level < h) {
+        v = (q[dim] < split[v]) ? 2 * v + 1 : 2 * v + 2;
+        level++;
+        dim = (dim + 1 == d) ? 0 : dim + 1;
+    }
+    return v;
+}
+
+// FindLeafBatch over one fetch.  State per query: FRESH, DONE or the heap
+// index of the last leaf visited.  After a visit the walk goes back up; at
+// a parent reached from its near child the far child is entered when the
+// float32 plane term (q[dim]-s)^2 does not exceed the current k-th squared
+// distance; reaching the root from above ends the traversal.
+__global__ __launch_bounds__(256) void k_find_leaf(FetchSpec f, const float *__restrict__ Q, int d,
+                                                   int32_t *__restrict__ node, const uint64_t *__restrict__ keys,
+                                                   int K, int k, const float *__restrict__ split, int h,
+                                                   uint32_t *__restrict__ pend_leaf, int32_t *__restrict__ pend_q,
+                                                   int64_t pend_base, int32_t *__restrict__ cnt,
+                                                   int32_t *__restrict__ ctl)
+{
+    const int64_t total = f.ring_count + f.in_count;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t first = (1 << h) - 1;
+    const uint32_t nleaf = 1u << h;
+    int32_t fill = 0;
+    bool valid = false;
+    uint32_t leaf = nleaf;
+    if (j < total) {
+        int32_t q = (j < f.ring_count) ? f.ring[(f.ring_head + j) % f.ring_cap]
+                                       : (int32_t)(f.in_start + (j - f.ring_count));
+        const float *qp = Q + (int64_t)q * d;
+        int32_t st = node[q];
+        int32_t v = NODE_DONE;
+        if (st == NODE_FRESH) {
+            v = descend(qp, split, 0, 0, h, d);
+        } else if (st != NODE_DONE) {
+            const float kth = __uint_as_float((uint32_t)(keys[(int64_t)q * K + (k - 1)] >> 32));
+            int32_t u = st;
+            int level = h;
+            while (u != 0) {
+                int32_t p = (u - 1) >> 1;
+                level--;
+                int dim = level % d;
+                float s = split[p];
+                float qd = qp[dim];
+                int32_t nearc = (qd < s) ? 2 * p + 1 : 2 * p + 2;
+                if (u == nearc) {
+                    float t = qd - s;
+                    float h2 = t * t;
+                    if (h2 <= kth) {
+                        int32_t sib = (nearc == 2 * p + 1) ? 2 * p + 2 : 2 * p + 1;
+                        v = descend(qp, split, sib, level + 1, h, d);
+                        break;
+                    }
+                }
+                u = p;
+            }
+        }
+        node[q] = v;
+        leaf = (v >= 0) ? (uint32_t)(v - first) : nleaf;
+        pend_leaf[pend_base + j] = leaf;
+        pend_q[pend_base + j] = q;
+        valid = v >= 0;
+    }
+    // Buffer fills: lanes bound for the same leaf are counted with one atomic
+    // (fetched queries arrive grouped by their previous leaf, so a wave holds
+    // few distinct leaves); each lane learns its fill for the trigger test.
+    uint64_t todo = __ballot(valid);
+    const uint64_t below = lanemask_lt();
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const uint32_t ll = (uint32_t)__builtin_amdgcn_readlane((int)leaf, leader);
+        const uint64_t grp = __ballot(valid && leaf == ll);
+        int32_t old = 0;
+        if (__lane_id() == leader) old = atomicAdd(&cnt[ll], (int32_t)__popcll(grp));
+        old = __builtin_amdgcn_readlane(old, leader);
+        if ((grp >> __lane_id()) & 1ull) fill = old + (int32_t)__popcll(grp & below) + 1;
+        todo &= ~grp;
+    }
+    int32_t mx = fill;
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
+    uint64_t vb = __ballot(valid);
+    if (__lane_id() == 0) {
+        if (mx > 0) atomicMax(&ctl[CTL_MAXCNT], mx);
+        if (vb) atomicAdd(&ctl[CTL_NVALID], (int32_t)__popcll(vb));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort of (leaf, query) pairs, 8-bit digits.
+
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_ROUNDS = 8;
+constexpr int SORT_TILE = SORT_THREADS * SORT_ROUNDS;
+
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t count,
+                                                             int shift, uint32_t *__restrict__ hist, int nblocks)
+{
+    __shared__ uint32_t hcount[256];
+    const int tid = threadIdx.x;
+    hcount[tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+    for (int r = 0; r < SORT_ROUNDS; r++) {
+        int64_t i = base + r * SORT_THREADS + tid;
+        if (i < count) atomicAdd(&hcount[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)tid * nblocks + blockIdx.x] = hcount[tid];
+}
+
+// Exclusive scan of n words with one workgroup of 1024 threads.
+template <class T> __device__ T block_exclusive_scan_1024(T v, T *lds, T *total)
+{
+    const int tid = threadIdx.x;
+    lds[tid] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        T add = (tid >= o) ? lds[tid - o] : T(0);
+        __syncthreads();
+        lds[tid] += add;
+        __syncthreads();
+    }
+    T incl = lds[tid];
+    if (total) *total = lds[1023];
+    __syncthreads();
+    return incl - v;
+}
+
+// Exclusive scan of each digit's column of the histogram (hist is digit-major:
+// hist[digit * nblocks + block]); totals[digit] receives the column sum.
+__global__ __launch_bounds__(256) void k_scan_columns(uint32_t *__restrict__ hist, int nblocks,
+                                                      uint32_t *__restrict__ totals)
+{
+    __shared__ uint32_t lds[256];
+    uint32_t *col = hist + (int64_t)blockIdx.x * nblocks;
+    const int tid = threadIdx.x;
+    uint32_t carry = 0;
+    for (int base = 0; base < nblocks; base += 256) {
+        const int i = base + tid;
+        const uint32_t v = i < nblocks ? col[i] : 0u;
+        lds[tid] = v;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            uint32_t add = tid >= o ? lds[tid - o] : 0u;
+            __syncthreads();
+            lds[tid] += add;
+            __syncthreads();
+        }
+        if (i < nblocks) col[i] = carry + lds[tid] - v;
+        carry += lds[255];
+        __syncthreads();
+    }
+    if (tid == 0) totals[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const uint32_t *__restrict__ kin,
+                                                                const int32_t *__restrict__ vin,
+                                                                uint32_t *__restrict__ kout,
+                                                                int32_t *__restrict__ vout, int64_t count, int shift,
+                                                                const uint32_t *__restrict__ hist, int nblocks,
+                                                                const uint32_t *__restrict__ totals)
+{
+    constexpr int W = SORT_THREADS / 64;
+    __shared__ uint32_t run[256];      // next output position per digit for this block
+    __shared__ uint32_t wcount[W][256];
+    __shared__ uint32_t wstart[W][256];
+    const int tid = threadIdx.x, wave = tid >> 6;
+    {
+        // digit base = exclusive scan of the column totals
+        const uint32_t tot = totals[tid];
+        run[tid] = tot;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            uint32_t add = tid >= o ? run[tid - o] : 0u;
+            __syncthreads();
+            run[tid] += add;
+            __syncthreads();
+        }
+        const uint32_t base = run[tid] - tot;
+        __syncthreads();
+        run[tid] = base + hist[(int64_t)tid * nblocks + blockIdx.x];
+    }
+    for (int w = 0; w < W; w++) wcount[w][tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+    for (int r = 0; r < SORT_ROUNDS; r++) {
+        const int64_t i = base + r * SORT_THREADS + tid;
+        const bool valid = i < count;
+        uint32_t key = valid ? kin[i] : 0u;
+        int32_t val = valid ? vin[i] : 0;
+        uint32_t digit = (key >> shift) & 255u;
+        uint64_t mask = __ballot(valid);
+        for (int b = 0; b < 8; b++) {
+            bool bit = (digit >> b) & 1u;
+            uint64_t bal = __ballot(valid && bit);
+            mask &= bit ? bal : ~bal;
+        }
+        uint32_t rank = (uint32_t)__popcll(mask & lanemask_lt());
+        if (valid && rank == 0) wcount[wave][digit] = (uint32_t)__popcll(mask);
+        __syncthreads();
+        {
+            uint32_t p = run[tid];
+            for (int w = 0; w < W; w++) {
+                uint32_t c = wcount[w][tid];
+                wstart[w][tid] = p;
+                wcount[w][tid] = 0;
+                p += c;
+            }
+            run[tid] = p;
+        }
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = wstart[wave][digit] + rank;
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+
+// Buffer offsets (exclusive scan of the fills), work items of one call and
+// the pair / visit counters.  A leaf holding at least dense_min buffered
+// queries is scanned in tiles of `qt` queries (one lane per query); a leaf
+// holding fewer gets one wave per buffered query (lanes over points).
+__global__ __launch_bounds__(1024) void k_leaf_offsets(const int32_t *__restrict__ cnt,
+                                                       const int32_t *__restrict__ leaf_off, int nleaf, int qt,
+                                                       int dense_min, int32_t *__restrict__ off,
+                                                       int32_t *__restrict__ tiles, int32_t *__restrict__ ctl)
+{
+    __shared__ long long lds[1024];
+    int32_t *sparse = tiles + nleaf + 1;
+    const int tid = threadIdx.x;
+    const int seg = (nleaf + 1023) / 1024;
+    const int lo = min(nleaf, tid * seg), hi = min(nleaf, lo + seg);
+    long long sc = 0, st = 0, ss = 0, sp = 0;
+    for (int l = lo; l < hi; l++) {
+        int c = cnt[l];
+        sc += c;
+        if (c >= dense_min) st += (c + qt - 1) / qt;
+        else ss += c;
+        sp += (long long)c * (leaf_off[l + 1] - leaf_off[l]);
+    }
+    long long tc, tt, ts;
+    long long rc = block_exclusive_scan_1024<long long>(sc, lds, &tc);
+    long long rt = block_exclusive_scan_1024<long long>(st, lds, &tt);
+    long long rs = block_exclusive_scan_1024<long long>(ss, lds, &ts);
+    for (int l = lo; l < hi; l++) {
+        int c = cnt[l];
+        off[l] = (int32_t)rc;
+        tiles[l] = (int32_t)rt;
+        sparse[l] = (int32_t)rs;
+        rc += c;
+        if (c >= dense_min) rt += (c + qt - 1) / qt;
+        else rs += c;
+    }
+    for (int o = 32; o > 0; o >>= 1) sp += __shfl_xor(sp, o);
+    if (__lane_id() == 0 && sp) atomicAdd((unsigned long long *)(ctl + CTL_PAIRS_LO), (unsigned long long)sp);
+    if (tid == 0) {
+        off[nleaf] = (int32_t)tc;
+        tiles[nleaf] = (int32_t)tt;
+        sparse[nleaf] = (int32_t)ts;
+        ctl[CTL_V] = (int32_t)tc;
+        ctl[CTL_T] = (int32_t)tt;
+        ctl[CTL_S] = (int32_t)ts;
+        atomicAdd((unsigned long long *)(ctl + CTL_VISITS_LO), (unsigned long long)tc);
+    }
+}
+
+__global__ void k_ring_append(int32_t *ring, int64_t cap, int64_t tail, const int32_t *src, int64_t count)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) ring[(tail + i) % cap] = src[i];
+}
+
+__global__ void k_finalize(const uint64_t *__restrict__ keys, int K, int k, int64_t m, int64_t *__restrict__ idx,
+                           float *__restrict__ dist, int squared)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m * k) return;
+    int64_t q = i / k;
+    int s = (int)(i - q * k);
+    uint64_t key = keys[q * K + s];
+    idx[i] = (int64_t)(uint32_t)key;
+    float d2 = __uint_as_float((uint32_t)(key >> 32));
+    dist[i] = squared ? d2 : sqrtf(d2);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers.
+
+static void check_launch()
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) fail(BKD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+void launch_init_state(int32_t *node, uint64_t *keys, int64_t m, int K, hipStream_t s)
+{
+    if (m <= 0) return;
+    k_init_state<<<grid_for(m, 256), 256, 0, s>>>(node, keys, m, K);
+    check_launch();
+}
+
+void launch_check_finite(const float *Q, int64_t count, int32_t *ctl, hipStream_t s)
+{
+    if (count <= 0) return;
+    unsigned g = (unsigned)std::min<int64_t>(grid_for(count, 256), 4096);
+    k_check_finite<<<g, 256, 0, s>>>(Q, count, ctl);
+    check_launch();
+}
+
+void launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return;
+    k_fill_i32<<<grid_for(count, 256), 256, 0, s>>>(p, v, count);
+    check_launch();
+}
+
+void launch_find_leaf(const FetchSpec &f, const float *Q, int d, int32_t *node, const uint64_t *keys, int K, int k,
+                      const float *split, int h, uint32_t *pend_leaf, int32_t *pend_q, int64_t pend_base,
+                      int32_t *cnt, int32_t *ctl, hipStream_t s)
+{
+    int64_t total = f.ring_count + f.in_count;
+    if (total <= 0) return;
+    k_find_leaf<<<grid_for(total, 256), 256, 0, s>>>(f, Q, d, node, keys, K, k, split, h, pend_leaf, pend_q,
+                                                     pend_base, cnt, ctl);
+    check_launch();
+}
+
+size_t sort_hist_words(int64_t count)
+{
+    int64_t nblocks = (count + SORT_TILE - 1) / SORT_TILE;
+    return (size_t)(std::max<int64_t>(nblocks, 1) + 1) * 256;  // histogram + column totals
+}
+
+int launch_sort_pairs(uint32_t *key_a, int32_t *val_a, uint32_t *key_b, int32_t *val_b, int64_t count, int key_bits,
+                      uint32_t *hist, hipStream_t s)
+{
+    if (count <= 1) return 0;
+    int nblocks = (int)((count + SORT_TILE - 1) / SORT_TILE);
+    int passes = (key_bits + 7) / 8;
+    uint32_t *kin = key_a, *kout = key_b;
+    int32_t *vin = val_a, *vout = val_b;
+    for (int p = 0; p < passes; p++) {
+        int shift = 8 * p;
+        uint32_t *totals = hist + (size_t)nblocks * 256;
+        k_radix_hist<<<nblocks, SORT_THREADS, 0, s>>>(kin, count, shift, hist, nblocks);
+        k_scan_columns<<<256, 256, 0, s>>>(hist, nblocks, totals);
+        k_radix_scatter<<<nblocks, SORT_THREADS, 0, s>>>(kin, vin, kout, vout, count, shift, hist, nblocks, totals);
+        check_launch();
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    return (passes & 1) ? 1 : 0;
+}
+
+void launch_leaf_offsets(const int32_t *cnt, const int32_t *leaf_off, int nleaf, int qt, int dense_min, int32_t *off,
+                         int32_t *tiles, int32_t *ctl, hipStream_t s)
+{
+    k_leaf_offsets<<<1, 1024, 0, s>>>(cnt, leaf_off, nleaf, qt, dense_min, off, tiles, ctl);
+    check_launch();
+}
+
+void launch_ring_append(int32_t *ring, int64_t cap, int64_t tail, const int32_t *src, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return;
+    k_ring_append<<<grid_for(count, 256), 256, 0, s>>>(ring, cap, tail, src, count);
+    check_launch();
+}
+
+void launch_finalize(const uint64_t *keys, int K, int k, int64_t m, int64_t *idx, float *dist, bool squared,
+                     hipStream_t s)
+{
+    if (m <= 0) return;
+    k_finalize<<<grid_for(m * k, 256), 256, 0, s>>>(keys, K, k, m, idx, dist, squared ? 1 : 0);
+    check_launch();
+}
+
+}  // namespace bkd

@@ -1,0 +1,191 @@
+// leaf_scan.h -- ProcessAllBuffers leaf scan (Section 2.4, Section 3.2), gfx950.
+//
+// Dense leaves (many buffered queries): one workgroup of 256 lanes takes one
+// work item, up to 256 buffered queries of one leaf, one query per lane.  The leaf's points (the part held by the
+// current chunk) stream through LDS in tiles of 256 points, stored point-major
+// with the coordinates padded to a multiple of four, so that every lane reads
+// the same point with a broadcast ds_read_b128.  Each lane keeps its query in
+// registers and its K best keys as a sorted register list; a point enters
+// through a compare-exchange cascade only when its key beats the K-th best
+// (a wave-uniform branch, skipped when no lane qualifies).
+//
+// Squared distances follow the float32 reading: t = q_j - x_j rounded, then
+// acc = fma(t, t, acc) for j = 0..d-1 from +0.  Padding dimensions hold zero in
+// both the query and the point and leave acc unchanged.  The key of a point
+// is (bits of acc) << 32 | original index, so the sorted list breaks exact
+// ties by smaller index.  Keys are merged into the query's list as a set:
+// the result does not depend on tiling, chunking or processing order.
+//
+// Sparse leaves (few buffered queries, typical of the late rounds): one wave
+// per buffered query.  The query sits in scalar registers, the 64 lanes walk
+// the leaf's points 64 at a time with coalesced loads straight from the
+// leaf structure, and the query's K best keys are spread over the lanes (lane
+// i holds the i-th smallest).  A point whose key beats the K-th best is
+// inserted with a ballot for its rank and a one-lane shift of the list.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace bkd {
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_PT = 256;  // points per LDS tile
+
+template <int K> __device__ inline void key_insert(uint64_t (&lst)[K], uint64_t c)
+{
+#pragma unroll
+    for (int s = 0; s < K; s++) {
+        uint64_t a = lst[s];
+        bool lt = c < a;
+        lst[s] = lt ? c : a;
+        c = lt ? a : c;
+    }
+}
+
+__device__ inline int xcd_item(int b, int grid)
+{
+    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+    // contiguous range of items so that a leaf's tiles share one L2.
+    int per = grid >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
+{
+    constexpr int DS = (D + 3) & ~3;
+    __shared__ float4 xs[SCAN_PT * DS / 4];
+    __shared__ int32_t os[SCAN_PT];
+
+    int item = xcd_item(blockIdx.x, gridDim.x);
+    if (item >= a.item_count) return;
+    item += a.item_first;
+
+    // leaf of the item: largest L in [leaf_first, leaf_last] with tiles[L] <= item
+    int lo = a.leaf_first, hi = a.leaf_last;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (a.tiles[mid] <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    const int L = lo;
+    const int qbase = a.off[L] + (item - a.tiles[L]) * SCAN_QT;
+    const int qcnt = min(SCAN_QT, a.off[L + 1] - qbase);
+    const int64_t p0 = max((int64_t)a.leaf_off[L], a.chunk_lo);
+    const int64_t p1 = min((int64_t)a.leaf_off[L + 1], a.chunk_hi);
+
+    const int tid = threadIdx.x;
+    const bool act = tid < qcnt;
+    const bool wave_busy = (tid & ~63) < qcnt;
+    const int32_t q = act ? a.bufq[qbase + tid] : 0;
+    float qv[D];
+#pragma unroll
+    for (int j = 0; j < D; j++) qv[j] = (act && j < a.d) ? a.Q[(int64_t)q * a.d + j] : 0.0f;
+    uint64_t lst[K];
+#pragma unroll
+    for (int s = 0; s < K; s++) lst[s] = act ? a.keys[(int64_t)q * K + s] : 0ull;  // 0: nothing enters
+
+    for (int64_t pt = p0; pt < p1; pt += SCAN_PT) {
+        const int np = (int)min((int64_t)SCAN_PT, p1 - pt);
+        __syncthreads();
+        if (tid < np) {
+            const int64_t cp = pt - a.chunk_lo + tid;
+            float *row = reinterpret_cast<float *>(xs) + tid * DS;
+#pragma unroll
+            for (int j = 0; j < DS; j++) row[j] = (j < a.d) ? a.X[(int64_t)j * a.pitch + cp] : 0.0f;
+            os[tid] = a.orig[cp];
+        }
+        __syncthreads();
+        if (!wave_busy) continue;  // whole wave without queries: only helps staging
+#pragma unroll 2
+        for (int i = 0; i < np; i++) {
+            const float4 *xp = xs + i * (DS / 4);
+            float acc = 0.0f;
+#pragma unroll
+            for (int c = 0; c < DS / 4; c++) {
+                float4 x4 = xp[c];
+                float xe[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    if (4 * c + e < D) {
+                        float t = qv[4 * c + e] - xe[e];
+                        acc = fmaf(t, t, acc);
+                    }
+                }
+            }
+            uint64_t key = ((uint64_t)__float_as_uint(acc) << 32) | (uint32_t)os[i];
+            if (key < lst[K - 1]) key_insert<K>(lst, key);
+        }
+    }
+    if (act) {
+#pragma unroll
+        for (int s = 0; s < K; s++) a.keys[(int64_t)q * K + s] = lst[s];
+    }
+}
+
+__device__ inline uint64_t readlane_u64(uint64_t v, int lane)
+{
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan_sparse(ScanArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    int s = __builtin_amdgcn_readfirstlane(xcd_item(blockIdx.x, gridDim.x) * (SCAN_THREADS / 64) +
+                                           (int)(threadIdx.x >> 6));
+    if (s >= a.sitem_count) return;
+    s += a.sitem_first;
+    int lo = a.leaf_first, hi = a.leaf_last;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (a.sparse[mid] <= s) lo = mid;
+        else hi = mid - 1;
+    }
+    const int L = lo;
+    const int32_t q = __builtin_amdgcn_readfirstlane(a.bufq[a.off[L] + (s - a.sparse[L])]);
+    const float *qp = a.Q + (int64_t)q * a.d;
+    float qv[D];
+#pragma unroll
+    for (int j = 0; j < D; j++) qv[j] = (j < a.d) ? qp[j] : 0.0f;
+    uint64_t *kp = a.keys + (int64_t)q * K;
+    uint64_t li = (lane < K) ? kp[lane] : ~0ull;
+    uint64_t kth = readlane_u64(li, K - 1);
+
+    const int64_t p0 = max((int64_t)a.leaf_off[L], a.chunk_lo);
+    const int64_t p1 = min((int64_t)a.leaf_off[L + 1], a.chunk_hi);
+    for (int64_t base = p0; base < p1; base += 64) {
+        const int64_t p = base + lane;
+        const bool valid = p < p1;
+        const int64_t cp = valid ? p - a.chunk_lo : 0;
+        float acc = 0.0f;
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            float x = (valid && j < a.d) ? a.X[(int64_t)j * a.pitch + cp] : 0.0f;
+            float t = qv[j] - x;
+            acc = fmaf(t, t, acc);
+        }
+        const uint64_t key = valid ? (((uint64_t)__float_as_uint(acc) << 32) | (uint32_t)a.orig[cp]) : ~0ull;
+        uint64_t cand = __ballot(key < kth);
+        while (cand) {
+            const int c = __ffsll((unsigned long long)cand) - 1;
+            cand &= cand - 1;
+            const uint64_t ck = readlane_u64(key, c);
+            if (ck < kth) {
+                const uint64_t moved = __ballot(li > ck);  // entries at and after the insertion rank
+                const int pos = __ffsll((unsigned long long)moved) - 1;
+                const uint64_t up = __shfl_up(li, 1);
+                li = (lane < pos) ? li : (lane == pos ? ck : up);
+                if (lane >= K) li = ~0ull;
+                kth = readlane_u64(li, K - 1);
+            }
+        }
+    }
+    if (lane < K) kp[lane] = li;
+}
+
+template <int D> void launch_leaf_scan_d(const ScanArgs &a, int K, hipStream_t s);
+
+}  // namespace bkd

@@ -1,0 +1,29 @@
+// scan_inst.h -- instantiation of the leaf scan for one padded dimension D over all key capacities.
+#pragma once
+#include "leaf_scan.h"
+
+#define BKD_SCAN_CASE(D, KK)                                                                        \
+    case KK:                                                                                        \
+        if (a.item_count > 0) k_leaf_scan<D, KK><<<grid, SCAN_THREADS, 0, s>>>(a);                 \
+        if (a.sitem_count > 0) k_leaf_scan_sparse<D, KK><<<sgrid, SCAN_THREADS, 0, s>>>(a);        \
+        break;
+
+#define BKD_SCAN_INSTANTIATE(D)                                                                     \
+    template <> void launch_leaf_scan_d<D>(const ScanArgs &a, int K, hipStream_t s)                \
+    {                                                                                               \
+        unsigned grid = (unsigned)(((int64_t)a.item_count + 7) / 8 * 8);                            \
+        unsigned sgrid = (unsigned)(((int64_t)a.sitem_count + 31) / 32 * 8);                        \
+        switch (K) {                                                                                \
+            BKD_SCAN_CASE(D, 1)                                                                     \
+            BKD_SCAN_CASE(D, 2)                                                                     \
+            BKD_SCAN_CASE(D, 4)                                                                     \
+            BKD_SCAN_CASE(D, 5)                                                                     \
+            BKD_SCAN_CASE(D, 8)                                                                     \
+            BKD_SCAN_CASE(D, 10)                                                                    \
+            BKD_SCAN_CASE(D, 16)                                                                    \
+            BKD_SCAN_CASE(D, 32)                                                                    \
+            BKD_SCAN_CASE(D, 64)                                                                    \
+        default:                                                                                    \
+            fail(BKD_EINVAL, "unsupported key capacity");                                           \
+        }                                                                                           \
+    }
