@@ -9,6 +9,8 @@ queries resident in HBM before the timed region starts.  Prints one JSON line.
 Workloads (seeded synthetic stand-ins for the paper's catalogues, Section 4.1):
   ondevice  n = m = 2^22, d = 10, 16-component Gaussian mixture, k = 10, height 10 (default)
   small     n = 2^15, m = 2^12, d = 10 uniform on [0,1]^10, k = 10, height 6
+  streamed  n = 2^28, m = 2^24, same mixture, k = 10, height 14, leaf structure streamed
+            through a 2 GB device budget (Section 3.2); also times the same tree resident
 """
 from __future__ import annotations
 
@@ -34,7 +36,41 @@ FP32_NONPACKED_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12  # 256 CU x 64 lanes x FMA x
 WORKLOADS = {
     "ondevice": dict(n=1 << 22, m=1 << 22, d=10, k=10, h=10, kind="mixture", comps=16),
     "small": dict(n=1 << 15, m=1 << 12, d=10, k=10, h=6, kind="uniform", comps=0),
+    "streamed": dict(n=1 << 28, m=1 << 24, d=10, k=10, h=14, kind="mixture", comps=16, budget=2_000_000_000),
 }
+
+
+def h2d_rate_gbs(torch, nbytes=1 << 30):
+    """Pinned host-to-device copy rate of this machine (one 1 GiB copy after a warm-up)."""
+    src = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dst.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    return nbytes / (time.perf_counter() - t0) / 1e9
+
+
+def timed_steps(bkd, torch, tree, dQ, k, di, dd, stream, steps, warmup):
+    for _ in range(warmup):
+        bkd.query_async(tree, dQ, k, di, dd, stream=stream)
+    torch.cuda.synchronize()
+    keys = ("dense_ms", "dense_launches", "dense_pairs", "sparse_ms", "sparse_launches", "sparse_pairs", "pairs",
+            "calls", "chunk_copies", "bytes_h2d")
+    acc = {key: 0 for key in keys}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        bkd.query_async(tree, dQ, k, di, dd, stream=stream)
+        st = bkd.last_stats(tree)
+        for key in acc:
+            acc[key] += st[key]
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return acc, time.perf_counter() - t0, ev0.elapsed_time(ev1)
 
 
 def make_inputs(w, seed):
@@ -97,40 +133,40 @@ def main():
     n, m, d, k, h = w["n"], w["m"], w["d"], w["k"], w["h"]
     P, Q = make_inputs(w, args.seed)
     # lock-step rounds: every active query is fetched each iteration (results do not depend on B, M)
-    tree = bkd.build(P, h, buffer_size=-1, fetch_size=-1, flags=bkd.FLAG_TIMING)
+    budget = w.get("budget", 0)
+    tree = bkd.build(P, h, buffer_size=-1, fetch_size=-1, flags=bkd.FLAG_TIMING, leaf_budget_bytes=budget)
     dQ = torch.from_numpy(Q).to("cuda")
     di = torch.empty((m, k), dtype=torch.int64, device="cuda")
     dd = torch.empty((m, k), dtype=torch.float32, device="cuda")
     stream = torch.cuda.Stream()
-
-    for _ in range(args.warmup):
-        bkd.query_async(tree, dQ, k, di, dd, stream=stream)
-    torch.cuda.synchronize()
-
-    scan_ms, launches, pairs, calls = 0.0, 0, 0, 0
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        bkd.query_async(tree, dQ, k, di, dd, stream=stream)
-        st = bkd.last_stats(tree)
-        scan_ms += st["scan_ms"]
-        launches += st["scan_launches"]
-        pairs += st["pairs"]
-        calls += st["calls"]
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
+    acc, wall, gpu_ms = timed_steps(bkd, torch, tree, dQ, k, di, dd, stream, args.steps, args.warmup)
+    streaming = None
+    if budget:
+        info = bkd.tree_info(tree)
+        tree.free()
+        res = bkd.build(P, h, buffer_size=-1, fetch_size=-1)
+        racc, rwall, _ = timed_steps(bkd, torch, res, dQ, k, di, dd, stream, args.steps, args.warmup)
+        res.free()
+        streaming = {"leaf_budget_bytes": budget, "chunks": info.num_chunks,
+                     "chunk_capacity_bytes": info.chunk_capacity_bytes, "leaf_structure_bytes": info.leaf_bytes,
+                     "bytes_h2d_per_step": acc["bytes_h2d"] // args.steps,
+                     "structure_copies_per_step": round(acc["bytes_h2d"] / args.steps / info.leaf_bytes, 3),
+                     "chunk_copies_per_step": acc["chunk_copies"] / args.steps,
+                     "h2d_rate_gbs_achieved": round(acc["bytes_h2d"] / wall / 1e9, 2),
+                     "h2d_rate_gbs_pinned_copy": round(h2d_rate_gbs(torch), 2),
+                     "resident_ms_per_step": round(rwall * 1e3 / args.steps, 3),
+                     "t_streamed_over_t_resident": round(wall / rwall, 4),
+                     "schedule": "lock-step rounds, chunk sweep (each resident chunk drained before the next)"}
 
     ms_per_step = wall * 1e3 / args.steps
     value = m * args.steps / wall
-    # dominant kernel: the leaf scan; algorithmic work = 3d flops per (query, point) pair
-    flops = 3.0 * d * pairs
-    achieved = flops / (scan_ms * 1e-3) / 1e12 if scan_ms > 0 else 0.0
+    # Dominant kernel: the dense leaf scan (one lane per buffered query).  Its algorithmic
+    # work is 3d flops per (query, leaf point) pair: d subtractions and d fused multiply-adds.
+    flops = 3.0 * d * acc["dense_pairs"]
+    dense_s = acc["dense_ms"] * 1e-3
+    achieved = flops / dense_s / 1e12 if dense_s > 0 else 0.0
     roofline = {
-        "kernel": "k_leaf_scan",
+        "kernel": f"k_leaf_scan<{d},{k}> (dense leaf scan)",
         "bound": "alu",
         "achieved": round(achieved, 3),
         "peak": FP32_VECTOR_PEAK_TFLOPS,
@@ -139,11 +175,15 @@ def main():
         "traffic": None,
         "peak_nonpacked": round(FP32_NONPACKED_TFLOPS, 1),
         "frac_nonpacked": round(achieved / FP32_NONPACKED_TFLOPS, 4),
-        "avg_launch_ms": round(scan_ms / max(launches, 1), 4),
-        "launches_per_step": launches / args.steps,
-        "pairs_per_step": pairs // args.steps,
+        "avg_launch_ms": round(acc["dense_ms"] / max(acc["dense_launches"], 1), 4),
+        "launches_per_step": acc["dense_launches"] / args.steps,
+        "pairs_per_launch": acc["dense_pairs"] // max(acc["dense_launches"], 1),
         "flops_per_pair": 3 * d,
-        "scan_share_of_step": round(scan_ms / max(gpu_ms, 1e-9), 4),
+        "share_of_step": round(acc["dense_ms"] / max(gpu_ms, 1e-9), 4),
+        "sparse_scan": {"launches_per_step": acc["sparse_launches"] / args.steps,
+                        "avg_launch_ms": round(acc["sparse_ms"] / max(acc["sparse_launches"], 1), 4),
+                        "tflops": round(3.0 * d * acc["sparse_pairs"] / max(acc["sparse_ms"] * 1e-3, 1e-12) / 1e12, 3),
+                        "share_of_step": round(acc["sparse_ms"] / max(gpu_ms, 1e-9), 4)},
     }
     out = {
         "metric": "kNN queries/s (d=10,k=10)",
@@ -160,13 +200,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: n={n} m={m} d={d} k={k} height={h} "
                                f"{'16-component Gaussian mixture' if w['kind'] == 'mixture' else 'uniform [0,1]^d'}, "
-                               f"seed {args.seed}, lock-step rounds",
-                   "n": n, "m": m, "d": d, "k": k, "height": h, "rounds_per_step": calls / args.steps},
+                               f"seed {args.seed}, lock-step rounds"
+                               + (f", leaf structure streamed through a {budget / 1e9:g} GB budget" if budget else ""),
+                   "n": n, "m": m, "d": d, "k": k, "height": h, "rounds_per_step": acc["calls"] / args.steps,
+                   "streaming": streaming,
+                   "pairs_per_query": acc["pairs"] / (args.steps * m)},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, Q, k, args.cpu_seconds)
-    tree.free()
+    if not budget:
+        tree.free()
     print(json.dumps(out), flush=True)
 
 

@@ -108,16 +108,20 @@ typedef struct bkd_tree_info {
 
 /* Counters of the last query on a tree. */
 typedef struct bkd_stats {
-    int64_t queries;      /* m                                                 */
-    int64_t fetches;      /* FindLeafBatch invocations                         */
-    int64_t calls;        /* ProcessAllBuffers invocations                     */
-    int64_t pairs;        /* (query, leaf point) pairs scanned                 */
-    int64_t visits;       /* (query, leaf) visits                              */
-    int64_t scan_launches;/* leaf-scan kernel launches                         */
-    int64_t chunk_copies; /* host-to-device chunk copies                       */
-    int64_t bytes_h2d;    /* bytes of those copies                             */
-    double scan_ms;       /* sum of leaf-scan launch durations (BKD_FLAG_TIMING)*/
-    double total_ms;      /* wall time of the query call on the host           */
+    int64_t queries;        /* m                                                  */
+    int64_t fetches;        /* FindLeafBatch invocations                          */
+    int64_t calls;          /* ProcessAllBuffers invocations                      */
+    int64_t pairs;          /* (query, leaf point) pairs scanned                  */
+    int64_t visits;         /* (query, leaf) visits                               */
+    int64_t dense_launches; /* launches of the dense leaf scan (lane per query)    */
+    int64_t dense_pairs;    /* pairs scanned by it                                */
+    int64_t sparse_launches;/* launches of the sparse leaf scan (wave per query)  */
+    int64_t sparse_pairs;   /* pairs scanned by it                                */
+    int64_t chunk_copies;   /* host-to-device chunk copies                        */
+    int64_t bytes_h2d;      /* bytes of those copies                              */
+    double dense_ms;        /* sum of dense-scan launch durations (BKD_FLAG_TIMING)  */
+    double sparse_ms;       /* sum of sparse-scan launch durations (BKD_FLAG_TIMING) */
+    double total_ms;        /* wall time of the query call on the host            */
 } bkd_stats;
 
 /* Thread-local description of the last error on this thread ("" if none). */

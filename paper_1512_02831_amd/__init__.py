@@ -46,9 +46,10 @@ class TreeInfo(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("queries", ctypes.c_int64), ("fetches", ctypes.c_int64), ("calls", ctypes.c_int64),
-                ("pairs", ctypes.c_int64), ("visits", ctypes.c_int64), ("scan_launches", ctypes.c_int64),
-                ("chunk_copies", ctypes.c_int64), ("bytes_h2d", ctypes.c_int64), ("scan_ms", ctypes.c_double),
-                ("total_ms", ctypes.c_double)]
+                ("pairs", ctypes.c_int64), ("visits", ctypes.c_int64), ("dense_launches", ctypes.c_int64),
+                ("dense_pairs", ctypes.c_int64), ("sparse_launches", ctypes.c_int64),
+                ("sparse_pairs", ctypes.c_int64), ("chunk_copies", ctypes.c_int64), ("bytes_h2d", ctypes.c_int64),
+                ("dense_ms", ctypes.c_double), ("sparse_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -74,12 +74,17 @@ struct HostTree {
 // Build the canonical tree of P (row-major n x d).
 void build_canonical(const float *P, int64_t n, int d, int h, HostTree &t);
 
-// One chunk of the leaf structure: positions [lo, hi) covering leaves [leaf_first, leaf_last].
+// Leaf-block layout of the leaf structure: leaf l occupies 4-byte words
+// [blk[l], blk[l+1]): d rows of len_l float32 coordinates (row j holds
+// coordinate j of the leaf's points in position order), then len_l int32
+// original indices.  Any run of consecutive leaves is one contiguous range.
+//
+// One chunk of the streaming plan: it serves positions [lo, hi) and holds the
+// whole blocks of leaves [leaf_first, leaf_last] (host words [word_lo, word_hi)).
 struct Chunk {
     int64_t lo, hi;
     int32_t leaf_first, leaf_last;
-    size_t host_offset;  // byte offset of its block in the pinned host structure
-    size_t bytes;        // d*(hi-lo) floats + (hi-lo) int32
+    int64_t word_lo, word_hi;
 };
 
 // Device control words (one small array per tree, read back by the host).
@@ -90,8 +95,9 @@ enum Ctl : int {
     CTL_T = 3,        // work items of the current call
     CTL_BAD = 4,      // non-finite query coordinate seen
     CTL_S = 5,        // sparse (one wave per buffered query) items of the current call
-    CTL_PAIRS_LO = 6, // 64-bit pairs counter (two words)
-    CTL_VISITS_LO = 8,
+    CTL_VISITS_LO = 6, // 64-bit counters (two words each)
+    CTL_DPAIRS_LO = 8,
+    CTL_SPAIRS_LO = 10,
     CTL_WORDS = 16
 };
 
@@ -111,13 +117,15 @@ struct Tree {
     DevBuf d_split, d_leaf_off;
 
     // leaf structure
+    std::vector<int64_t> leaf_blk; // [nleaf+1] word offsets of the leaf blocks
+    DevBuf d_leaf_blk;
     bool resident = true;
+    bool sweep = false;            // streaming with the chunk-sweep schedule
     std::vector<Chunk> chunks;
     size_t chunk_cap_bytes = 0;
-    int64_t chunk_cap_points = 0;
     DevBuf d_chunk[2];     // resident: d_chunk[0] holds everything
     int chunk_in[2] = {-1, -1};
-    PinnedBuf h_leaf;      // streaming: chunk-major pinned host structure
+    PinnedBuf h_leaf;      // streaming: pinned host copy of the leaf structure
     hipStream_t copy_stream = nullptr;
     hipEvent_t ev_copied[2] = {nullptr, nullptr};
     hipEvent_t ev_used[2] = {nullptr, nullptr};
@@ -126,7 +134,7 @@ struct Tree {
     DevBuf d_Q, d_outi, d_outd;
     DevBuf d_keys, d_node, d_ring, d_pleaf, d_pq, d_tleaf, d_tq, d_hist;
     DevBuf d_cnt, d_off, d_tiles, d_ctl;
-    PinnedBuf h_ctl, h_tiles;
+    PinnedBuf h_ctl, h_tiles;  // h_tiles: dense tiles, sparse items, buffer offsets (3 x (nleaf+1))
 
     // results of the last query
     bkd_stats stats{};
@@ -155,6 +163,8 @@ size_t sort_hist_words(int64_t count);
 // tiles: [2][nleaf+1] -- dense work-item offsets, then sparse (per buffered query) offsets.
 void launch_leaf_offsets(const int32_t *cnt, const int32_t *leaf_off, int nleaf, int qt, int dense_min, int32_t *off,
                          int32_t *tiles, int32_t *ctl, hipStream_t s);
+void launch_count_work(const int32_t *off, const int32_t *leaf_off, int lf, int ll, int dense_min, int32_t *ctl,
+                       hipStream_t s);
 void launch_ring_append(int32_t *ring, int64_t cap, int64_t tail, const int32_t *src, int64_t count, hipStream_t s);
 void launch_finalize(const uint64_t *keys, int K, int k, int64_t m, int64_t *idx, float *dist, bool squared,
                      hipStream_t s);
@@ -166,10 +176,10 @@ struct ScanArgs {
     const int32_t *off;       // [nleaf+1] buffer offsets
     const int32_t *bufq;      // buffered query ids, leaf order
     const int32_t *leaf_off;  // [nleaf+1] leaf positions
-    const float *X;           // chunk points, [d][pitch]
-    const int32_t *orig;      // chunk original indices, [pitch]
-    int64_t pitch;            // points per dimension row in the chunk
-    int64_t chunk_lo, chunk_hi;  // positions held by the chunk
+    const float *base;        // device buffer holding the leaf blocks of this launch
+    const int64_t *blk;       // [nleaf+1] word offsets of the leaf blocks in the whole structure
+    int64_t blk_shift;        // added to blk[l] to address the buffer (minus the buffer's first word)
+    int64_t chunk_lo, chunk_hi;  // positions served by this launch
     int32_t item_first, item_count;    // dense items of this launch
     int32_t sitem_first, sitem_count;  // sparse items of this launch
     int32_t leaf_first, leaf_last;
@@ -178,8 +188,8 @@ struct ScanArgs {
     uint64_t *keys;           // [m][K]
 };
 
-// Dispatch on padded dimension and key capacity.
-void launch_leaf_scan(const ScanArgs &a, int K, hipStream_t s);
+// Dispatch on padded dimension and key capacity; sparse = 0: dense items, 1: sparse items.
+void launch_leaf_scan(const ScanArgs &a, int K, int sparse, hipStream_t s);
 int padded_dim(int d);
 int key_capacity(int k);
 

@@ -288,13 +288,12 @@ __global__ __launch_bounds__(1024) void k_leaf_offsets(const int32_t *__restrict
     const int tid = threadIdx.x;
     const int seg = (nleaf + 1023) / 1024;
     const int lo = min(nleaf, tid * seg), hi = min(nleaf, lo + seg);
-    long long sc = 0, st = 0, ss = 0, sp = 0;
+    long long sc = 0, st = 0, ss = 0;
     for (int l = lo; l < hi; l++) {
         int c = cnt[l];
         sc += c;
         if (c >= dense_min) st += (c + qt - 1) / qt;
         else ss += c;
-        sp += (long long)c * (leaf_off[l + 1] - leaf_off[l]);
     }
     long long tc, tt, ts;
     long long rc = block_exclusive_scan_1024<long long>(sc, lds, &tc);
@@ -309,8 +308,6 @@ __global__ __launch_bounds__(1024) void k_leaf_offsets(const int32_t *__restrict
         if (c >= dense_min) rt += (c + qt - 1) / qt;
         else rs += c;
     }
-    for (int o = 32; o > 0; o >>= 1) sp += __shfl_xor(sp, o);
-    if (__lane_id() == 0 && sp) atomicAdd((unsigned long long *)(ctl + CTL_PAIRS_LO), (unsigned long long)sp);
     if (tid == 0) {
         off[nleaf] = (int32_t)tc;
         tiles[nleaf] = (int32_t)tt;
@@ -318,7 +315,31 @@ __global__ __launch_bounds__(1024) void k_leaf_offsets(const int32_t *__restrict
         ctl[CTL_V] = (int32_t)tc;
         ctl[CTL_T] = (int32_t)tt;
         ctl[CTL_S] = (int32_t)ts;
-        atomicAdd((unsigned long long *)(ctl + CTL_VISITS_LO), (unsigned long long)tc);
+    }
+}
+
+// Visits and (query, point) pairs of the leaves [lf, ll] about to be scanned, split by scan kernel.
+__global__ __launch_bounds__(256) void k_count_work(const int32_t *__restrict__ off,
+                                                    const int32_t *__restrict__ leaf_off, int lf, int ll,
+                                                    int dense_min, int32_t *__restrict__ ctl)
+{
+    long long v = 0, pd = 0, ps = 0;
+    for (int l = lf + threadIdx.x; l <= ll; l += blockDim.x) {
+        const int c = off[l + 1] - off[l];
+        const long long pr = (long long)c * (leaf_off[l + 1] - leaf_off[l]);
+        v += c;
+        if (c >= dense_min) pd += pr;
+        else ps += pr;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        v += __shfl_xor(v, o);
+        pd += __shfl_xor(pd, o);
+        ps += __shfl_xor(ps, o);
+    }
+    if (__lane_id() == 0) {
+        if (v) atomicAdd((unsigned long long *)(ctl + CTL_VISITS_LO), (unsigned long long)v);
+        if (pd) atomicAdd((unsigned long long *)(ctl + CTL_DPAIRS_LO), (unsigned long long)pd);
+        if (ps) atomicAdd((unsigned long long *)(ctl + CTL_SPAIRS_LO), (unsigned long long)ps);
     }
 }
 
@@ -416,6 +437,13 @@ void launch_leaf_offsets(const int32_t *cnt, const int32_t *leaf_off, int nleaf,
                          int32_t *tiles, int32_t *ctl, hipStream_t s)
 {
     k_leaf_offsets<<<1, 1024, 0, s>>>(cnt, leaf_off, nleaf, qt, dense_min, off, tiles, ctl);
+    check_launch();
+}
+
+void launch_count_work(const int32_t *off, const int32_t *leaf_off, int lf, int ll, int dense_min, int32_t *ctl,
+                       hipStream_t s)
+{
+    k_count_work<<<1, 256, 0, s>>>(off, leaf_off, lf, ll, dense_min, ctl);
     check_launch();
 }
 

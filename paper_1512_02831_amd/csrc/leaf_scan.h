@@ -72,8 +72,12 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
     const int L = lo;
     const int qbase = a.off[L] + (item - a.tiles[L]) * SCAN_QT;
     const int qcnt = min(SCAN_QT, a.off[L + 1] - qbase);
-    const int64_t p0 = max((int64_t)a.leaf_off[L], a.chunk_lo);
-    const int64_t p1 = min((int64_t)a.leaf_off[L + 1], a.chunk_hi);
+    const int64_t l0 = a.leaf_off[L];
+    const int len = a.leaf_off[L + 1] - a.leaf_off[L];
+    const int64_t p0 = max(l0, a.chunk_lo);
+    const int64_t p1 = min(l0 + len, a.chunk_hi);
+    const float *X = a.base + (a.blk[L] + a.blk_shift);
+    const int32_t *orig = reinterpret_cast<const int32_t *>(X) + (int64_t)a.d * len;
 
     const int tid = threadIdx.x;
     const bool act = tid < qcnt;
@@ -90,11 +94,11 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
         const int np = (int)min((int64_t)SCAN_PT, p1 - pt);
         __syncthreads();
         if (tid < np) {
-            const int64_t cp = pt - a.chunk_lo + tid;
+            const int i = (int)(pt - l0) + tid;
             float *row = reinterpret_cast<float *>(xs) + tid * DS;
 #pragma unroll
-            for (int j = 0; j < DS; j++) row[j] = (j < a.d) ? a.X[(int64_t)j * a.pitch + cp] : 0.0f;
-            os[tid] = a.orig[cp];
+            for (int j = 0; j < DS; j++) row[j] = (j < a.d) ? X[j * len + i] : 0.0f;
+            os[tid] = orig[i];
         }
         __syncthreads();
         if (!wave_busy) continue;  // whole wave without queries: only helps staging
@@ -154,20 +158,24 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
     uint64_t li = (lane < K) ? kp[lane] : ~0ull;
     uint64_t kth = readlane_u64(li, K - 1);
 
-    const int64_t p0 = max((int64_t)a.leaf_off[L], a.chunk_lo);
-    const int64_t p1 = min((int64_t)a.leaf_off[L + 1], a.chunk_hi);
-    for (int64_t base = p0; base < p1; base += 64) {
-        const int64_t p = base + lane;
+    const int64_t l0 = a.leaf_off[L];
+    const int len = a.leaf_off[L + 1] - a.leaf_off[L];
+    const int64_t p0 = max(l0, a.chunk_lo);
+    const int64_t p1 = min(l0 + len, a.chunk_hi);
+    const float *X = a.base + (a.blk[L] + a.blk_shift);
+    const int32_t *orig = reinterpret_cast<const int32_t *>(X) + (int64_t)a.d * len;
+    for (int64_t pb = p0; pb < p1; pb += 64) {
+        const int64_t p = pb + lane;
         const bool valid = p < p1;
-        const int64_t cp = valid ? p - a.chunk_lo : 0;
+        const int i = valid ? (int)(p - l0) : 0;
         float acc = 0.0f;
 #pragma unroll
         for (int j = 0; j < D; j++) {
-            float x = (valid && j < a.d) ? a.X[(int64_t)j * a.pitch + cp] : 0.0f;
+            float x = (valid && j < a.d) ? X[j * len + i] : 0.0f;
             float t = qv[j] - x;
             acc = fmaf(t, t, acc);
         }
-        const uint64_t key = valid ? (((uint64_t)__float_as_uint(acc) << 32) | (uint32_t)a.orig[cp]) : ~0ull;
+        const uint64_t key = valid ? (((uint64_t)__float_as_uint(acc) << 32) | (uint32_t)orig[i]) : ~0ull;
         uint64_t cand = __ballot(key < kth);
         while (cand) {
             const int c = __ffsll((unsigned long long)cand) - 1;
@@ -186,6 +194,6 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
     if (lane < K) kp[lane] = li;
 }
 
-template <int D> void launch_leaf_scan_d(const ScanArgs &a, int K, hipStream_t s);
+template <int D> void launch_leaf_scan_d(const ScanArgs &a, int K, int sparse, hipStream_t s);
 
 }  // namespace bkd

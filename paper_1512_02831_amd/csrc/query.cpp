@@ -1,23 +1,31 @@
-// query.cpp -- tree upload, streaming plan and the query loop of Algorithm 1.
+// query.cpp -- tree upload, streaming plan and the two query schedules.
 //
-// The loop keeps the paper's queues on the device: `input` is the range of
-// not yet fetched query ids, `reinsert` a FIFO ring.  Each iteration fetches
-// up to M ids (reinsert first), runs FindLeafBatch, appends the (leaf, query)
-// pairs to the pending list (the pooled buffers, in fetch order), and reads
-// back the largest buffer fill.  When a buffer is half-full or both queues are
-// empty, ProcessAllBuffers runs: a stable sort groups the pending pairs by
-// leaf (the buffers' contents in insertion order), one leaf-scan launch per
-// needed chunk updates every buffered query's list, and the buffered ids are
-// appended to reinsert in ascending leaf order.
+// Algorithm 1 schedule (fetch_size >= 0).  The paper's queues live on the
+// device: `input` is the range of not yet fetched query ids, `reinsert` a
+// FIFO ring.  Each iteration fetches up to M ids (reinsert first), runs
+// FindLeafBatch, appends the (leaf, query) pairs to the pending list (the
+// pooled buffers, in fetch order) and reads back the largest buffer fill.
+// When a buffer is half-full or both queues are empty, ProcessAllBuffers
+// runs: a stable sort groups the pending pairs by leaf (the buffers' contents
+// in insertion order), the leaf scans update every buffered query's list and
+// the buffered ids are appended to reinsert in ascending leaf order.  With a
+// streamed leaf structure every call walks the chunks holding a buffered leaf
+// in order (Section 3.2): the copy of the next chunk runs on a second stream
+// while the scan of the current chunk runs on the caller's stream, events
+// order each copy after the last scan that read its buffer and each scan after
+// its copy (Brute / Copy / Wait on two queues, without blocking the host), and
+// after the last chunk of a call the first chunk is prefetched for the next.
 //
-// Streaming (Section 3.2): with a leaf budget, the leaf structure stays in
-// pinned host memory in chunk-major blocks and passes through two device
-// chunk buffers.  The copy of the next chunk runs on a second stream while
-// the scan of the current chunk runs on the caller's stream; events order
-// each copy after the last scan that read its buffer and each scan after its
-// copy (the paper's Brute / Copy / Wait with two command queues, without
-// blocking the host).  Chunks holding no buffered leaf are skipped, and after
-// the last chunk of a call the first chunk is prefetched for the next call.
+// Lock-step schedule (fetch_size < 0).  Every iteration is one round over all
+// active queries: sort the pending pairs by leaf, scan, FindLeafBatch on the
+// scanned queries.  With a leaf-aligned streamed structure a round covers one
+// resident chunk at a time: the chunk is drained (its queries scanned and
+// routed again, round after round, while their next leaf stays inside it)
+// before the sweep moves on to the next chunk holding pending queries, whose
+// copy was prefetched meanwhile.  A query's leaf sequence depends only on its
+// own data, so both schedules visit the same (query, leaf) pairs and give the
+// same results; the sweep copies each chunk once per pass instead of once per
+// round.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -38,10 +46,16 @@ static void plan_chunks(Tree &t)
 {
     const HostTree &H = t.host;
     const int64_t n = H.n;
-    const size_t bpp = (size_t)(4 * H.d + 4);
-    const size_t total = (size_t)n * bpp;
+    const int d = H.d;
+    t.leaf_blk.assign((size_t)t.nleaf + 1, 0);
     int64_t maxleaf = 0;
-    for (int l = 0; l < t.nleaf; l++) maxleaf = std::max(maxleaf, H.leaf_off[l + 1] - H.leaf_off[l]);
+    for (int l = 0; l < t.nleaf; l++) {
+        const int64_t len = H.leaf_off[l + 1] - H.leaf_off[l];
+        t.leaf_blk[(size_t)l + 1] = t.leaf_blk[(size_t)l] + (int64_t)(d + 1) * len;
+        maxleaf = std::max(maxleaf, len);
+    }
+    const size_t bpp = (size_t)(4 * d + 4);
+    const size_t total = (size_t)n * bpp;
     const int64_t budget = t.opt.leaf_budget_bytes;
     if (budget < 0) fail(BKD_EINVAL, "leaf_budget_bytes must be >= 0");
     if (t.opt.num_chunks < 0) fail(BKD_EINVAL, "num_chunks must be >= 0");
@@ -50,8 +64,7 @@ static void plan_chunks(Tree &t)
     t.chunks.clear();
     t.resident = (t.opt.num_chunks == 0) && (budget == 0 || (size_t)budget >= total);
     if (t.resident) {
-        t.chunks.push_back(Chunk{0, n, 0, t.nleaf - 1, 0, total});
-        t.chunk_cap_points = n;
+        t.chunks.push_back(Chunk{0, n, 0, t.nleaf - 1, 0, t.leaf_blk.back()});
         t.chunk_cap_bytes = total;
         return;
     }
@@ -61,23 +74,30 @@ static void plan_chunks(Tree &t)
     const size_t cap_bytes = budget > 0 ? (size_t)budget / 2 : total;
     std::vector<std::pair<int64_t, int64_t>> ranges;  // positions
     if (t.opt.chunk_mode == BKD_CHUNK_POSITION) {
-        int64_t N = t.opt.num_chunks > 0 ? t.opt.num_chunks
-                                         : (int64_t)((total + cap_bytes - 1) / cap_bytes);
+        // chunk j of N: positions [ceil((j-1) n / N), ceil(j n / N)); a leaf crossing a bound is
+        // held whole by both chunks, each scanning only its own positions
+        int64_t N = t.opt.num_chunks;
+        if (N == 0) {
+            N = (int64_t)((total + cap_bytes - 1) / cap_bytes);
+            for (;; N++) {  // the leaf blocks a chunk holds may exceed its positions
+                bool fits = true;
+                for (int64_t j = 1; j <= N && fits; j++) {
+                    int64_t lo = ((j - 1) * n + N - 1) / N, hi = (j * n + N - 1) / N;
+                    int64_t a = std::upper_bound(H.leaf_off.begin(), H.leaf_off.end(), lo) - H.leaf_off.begin() - 1;
+                    int64_t b = std::upper_bound(H.leaf_off.begin(), H.leaf_off.end(), hi - 1) - H.leaf_off.begin();
+                    fits = (size_t)(H.leaf_off[b] - H.leaf_off[a]) * bpp <= cap_bytes;
+                }
+                if (fits || N >= n) break;
+            }
+        }
         N = std::max<int64_t>(1, std::min<int64_t>(N, n));
         for (int64_t j = 1; j <= N; j++) ranges.emplace_back(((j - 1) * n + N - 1) / N, (j * n + N - 1) / N);
-        if (budget > 0) {
-            for (auto &r : ranges)
-                if ((size_t)(r.second - r.first) * bpp > cap_bytes)
-                    fail(BKD_EBUDGET, "forced chunk count exceeds the leaf budget");
-        }
     } else if (t.opt.num_chunks > 0) {
         // whole leaves, the leaf index range split by the same ceiling rule
         int64_t N = std::min<int64_t>(t.opt.num_chunks, t.nleaf);
         for (int64_t j = 1; j <= N; j++) {
             int64_t a = ((j - 1) * t.nleaf + N - 1) / N, b = (j * t.nleaf + N - 1) / N;
             ranges.emplace_back(H.leaf_off[a], H.leaf_off[b]);
-            if (budget > 0 && (size_t)(H.leaf_off[b] - H.leaf_off[a]) * bpp > cap_bytes)
-                fail(BKD_EBUDGET, "forced chunk count exceeds the leaf budget");
         }
     } else {
         // greedy: as many whole leaves as fit the chunk capacity
@@ -89,40 +109,43 @@ static void plan_chunks(Tree &t)
             l = e;
         }
     }
-    size_t off = 0;
-    int64_t cap = 0;
+    size_t cap = 0;
     for (auto &r : ranges) {
         Chunk c;
         c.lo = r.first;
         c.hi = r.second;
-        // leaves overlapping [lo, hi)
         c.leaf_first = (int32_t)(std::upper_bound(H.leaf_off.begin(), H.leaf_off.end(), c.lo) - H.leaf_off.begin() - 1);
-        c.leaf_last = (int32_t)(std::upper_bound(H.leaf_off.begin(), H.leaf_off.end(), c.hi - 1) - H.leaf_off.begin() - 1);
-        c.host_offset = off;
-        c.bytes = (size_t)(c.hi - c.lo) * bpp;
-        off += (c.bytes + 255) & ~(size_t)255;
-        cap = std::max(cap, c.hi - c.lo);
+        c.leaf_last =
+            (int32_t)(std::upper_bound(H.leaf_off.begin(), H.leaf_off.end(), c.hi - 1) - H.leaf_off.begin() - 1);
+        c.word_lo = t.leaf_blk[(size_t)c.leaf_first];
+        c.word_hi = t.leaf_blk[(size_t)c.leaf_last + 1];
+        cap = std::max(cap, (size_t)(c.word_hi - c.word_lo) * 4);
         t.chunks.push_back(c);
     }
-    t.chunk_cap_points = cap;
-    t.chunk_cap_bytes = (size_t)cap * bpp;
+    if (budget > 0 && cap > cap_bytes) fail(BKD_EBUDGET, "chunk count too small for the leaf budget");
+    t.chunk_cap_bytes = cap;
 }
 
-// Write positions [lo, hi) of the leaf structure as [d][hi-lo] floats then [hi-lo] int32.
-static void gather_block(const float *P, const HostTree &H, int64_t lo, int64_t hi, void *dst)
+// Write the blocks of leaves [lf, ll] to dst (word 0 = first word of leaf lf).
+static void gather_leaves(const float *P, const Tree &t, int lf, int ll, void *dst)
 {
+    const HostTree &H = t.host;
     const int d = H.d;
-    const int64_t len = hi - lo;
-    float *X = static_cast<float *>(dst);
-    int32_t *orig = reinterpret_cast<int32_t *>(X + (size_t)d * len);
-    parallel_for(len, [&](int64_t b, int64_t e) {
-        for (int64_t i = b; i < e; i++) {
-            int32_t o = H.perm[(size_t)(lo + i)];
-            const float *p = P + (int64_t)o * d;
-            for (int j = 0; j < d; j++) X[(size_t)j * len + i] = p[j];
-            orig[i] = o;
+    float *out = static_cast<float *>(dst) - t.leaf_blk[(size_t)lf];
+    parallel_for(ll - lf + 1, [&](int64_t b, int64_t e) {
+        for (int64_t x = b; x < e; x++) {
+            const int l = lf + (int)x;
+            const int64_t a = H.leaf_off[(size_t)l], len = H.leaf_off[(size_t)l + 1] - a;
+            float *X = out + t.leaf_blk[(size_t)l];
+            int32_t *orig = reinterpret_cast<int32_t *>(X + (size_t)d * len);
+            for (int64_t i = 0; i < len; i++) {
+                const int32_t o = H.perm[(size_t)(a + i)];
+                const float *p = P + (int64_t)o * d;
+                for (int j = 0; j < d; j++) X[(size_t)j * len + i] = p[j];
+                orig[i] = o;
+            }
         }
-    }, 4096);
+    });
 }
 
 void tree_build(Tree &t, const float *P, int64_t n, int d, int h, const bkd_options &opt)
@@ -137,6 +160,7 @@ void tree_build(Tree &t, const float *P, int64_t n, int d, int h, const bkd_opti
 
     build_canonical(P, n, d, h, t.host);
     plan_chunks(t);
+    t.sweep = !t.resident && t.opt.chunk_mode == BKD_CHUNK_LEAF;
 
     const HostTree &H = t.host;
     t.d_split.ensure(sizeof(float) * std::max<size_t>(1, H.split.size()));
@@ -146,17 +170,19 @@ void tree_build(Tree &t, const float *P, int64_t n, int d, int h, const bkd_opti
     for (size_t i = 0; i < lo32.size(); i++) lo32[i] = (int32_t)H.leaf_off[i];
     t.d_leaf_off.ensure(sizeof(int32_t) * lo32.size());
     BKD_HIP(hipMemcpy(t.d_leaf_off.p, lo32.data(), sizeof(int32_t) * lo32.size(), hipMemcpyHostToDevice));
+    t.d_leaf_blk.ensure(sizeof(int64_t) * t.leaf_blk.size());
+    BKD_HIP(hipMemcpy(t.d_leaf_blk.p, t.leaf_blk.data(), sizeof(int64_t) * t.leaf_blk.size(), hipMemcpyHostToDevice));
 
+    const size_t total_bytes = (size_t)t.leaf_blk.back() * 4;
     if (t.resident) {
-        std::vector<char> blk(t.chunks[0].bytes);
-        gather_block(P, H, 0, n, blk.data());
-        t.d_chunk[0].ensure(blk.size());
-        BKD_HIP(hipMemcpy(t.d_chunk[0].p, blk.data(), blk.size(), hipMemcpyHostToDevice));
+        std::vector<float> blk((size_t)t.leaf_blk.back());
+        gather_leaves(P, t, 0, t.nleaf - 1, blk.data());
+        t.d_chunk[0].ensure(total_bytes);
+        BKD_HIP(hipMemcpy(t.d_chunk[0].p, blk.data(), total_bytes, hipMemcpyHostToDevice));
         t.chunk_in[0] = 0;
     } else {
-        const Chunk &lastc = t.chunks.back();
-        t.h_leaf.ensure(lastc.host_offset + lastc.bytes);
-        for (const Chunk &c : t.chunks) gather_block(P, H, c.lo, c.hi, static_cast<char *>(t.h_leaf.p) + c.host_offset);
+        t.h_leaf.ensure(total_bytes);
+        gather_leaves(P, t, 0, t.nleaf - 1, t.h_leaf.p);
         t.d_chunk[0].ensure(t.chunk_cap_bytes);
         t.d_chunk[1].ensure(t.chunk_cap_bytes);
         BKD_HIP(hipStreamCreateWithFlags(&t.copy_stream, hipStreamNonBlocking));
@@ -212,18 +238,299 @@ struct Timer {
     }
 };
 
-// Copy chunk j into device buffer b on the copy stream, after the last scan that read b.
-void issue_copy(Tree &t, int b, int j)
-{
-    const Chunk &c = t.chunks[(size_t)j];
-    BKD_HIP(hipStreamWaitEvent(t.copy_stream, t.ev_used[b], 0));
-    BKD_HIP(hipMemcpyAsync(t.d_chunk[b].p, static_cast<char *>(t.h_leaf.p) + c.host_offset, c.bytes,
-                           hipMemcpyHostToDevice, t.copy_stream));
-    BKD_HIP(hipEventRecord(t.ev_copied[b], t.copy_stream));
-    t.chunk_in[b] = j;
-    t.stats.chunk_copies++;
-    t.stats.bytes_h2d += (int64_t)c.bytes;
-}
+// Per-query-call state shared by both schedules.
+struct Run {
+    Tree &t;
+    hipStream_t s;
+    const float *dQ;
+    int64_t m;
+    int k, K, d, h, nleaf, kbits;
+    bool tracing;
+    int32_t *ctl, *hctl, *cnt;
+    uint32_t *leafbuf[2];
+    int32_t *qbuf[2];
+    int cur = 0;  // pair holding the pending list
+    Timer tdense, tsparse;
+    std::vector<int32_t> tr_q, tr_l;
+
+    Run(Tree &t_, hipStream_t s_, const float *dQ_, int64_t m_, int k_)
+        : t(t_), s(s_), dQ(dQ_), m(m_), k(k_), K(key_capacity(k_)), d(t_.host.d), h(t_.host.h), nleaf(t_.nleaf),
+          kbits(key_bits_for(t_.nleaf)), tracing((t_.opt.flags & BKD_FLAG_TRACE) != 0)
+    {
+        t.d_keys.ensure(sizeof(uint64_t) * (size_t)m * K);
+        t.d_node.ensure(sizeof(int32_t) * (size_t)m);
+        t.d_ring.ensure(sizeof(int32_t) * (size_t)m);
+        t.d_pleaf.ensure(sizeof(uint32_t) * (size_t)m);
+        t.d_pq.ensure(sizeof(int32_t) * (size_t)m);
+        t.d_tleaf.ensure(sizeof(uint32_t) * (size_t)m);
+        t.d_tq.ensure(sizeof(int32_t) * (size_t)m);
+        t.d_hist.ensure(sizeof(uint32_t) * sort_hist_words(m));
+        t.d_cnt.ensure(sizeof(int32_t) * (size_t)nleaf);
+        t.d_off.ensure(sizeof(int32_t) * (size_t)(nleaf + 1));
+        t.d_tiles.ensure(sizeof(int32_t) * 2 * (size_t)(nleaf + 1));
+        if (!t.resident) t.h_tiles.ensure(sizeof(int32_t) * 3 * (size_t)(nleaf + 1));
+        ctl = t.d_ctl.as<int32_t>();
+        hctl = t.h_ctl.as<int32_t>();
+        cnt = t.d_cnt.as<int32_t>();
+        leafbuf[0] = t.d_pleaf.as<uint32_t>();
+        leafbuf[1] = t.d_tleaf.as<uint32_t>();
+        qbuf[0] = t.d_pq.as<int32_t>();
+        qbuf[1] = t.d_tq.as<int32_t>();
+        tdense.on = tsparse.on = (t.opt.flags & BKD_FLAG_TIMING) != 0;
+    }
+
+    const int32_t *htiles() const { return t.h_tiles.as<int32_t>(); }
+    const int32_t *hsparse() const { return t.h_tiles.as<int32_t>() + nleaf + 1; }
+    const int32_t *hoff() const { return t.h_tiles.as<int32_t>() + 2 * (nleaf + 1); }
+
+    void readback()
+    {
+        BKD_HIP(hipMemcpyAsync(hctl, ctl, sizeof(int32_t) * CTL_WORDS, hipMemcpyDeviceToHost, s));
+        BKD_HIP(hipStreamSynchronize(s));
+        if (hctl[CTL_BAD]) fail(BKD_EINVAL, "query coordinates must be finite");
+    }
+
+    void find_leaf(const FetchSpec &f, int64_t base)
+    {
+        launch_find_leaf(f, dQ, d, t.d_node.as<int32_t>(), t.d_keys.as<uint64_t>(), K, k, t.d_split.as<float>(), h,
+                         leafbuf[cur], qbuf[cur], base, cnt, ctl, s);
+        t.stats.fetches++;
+        const int64_t F = f.ring_count + f.in_count;
+        if (tracing && F > 0) {
+            tr_q.resize((size_t)F);
+            tr_l.resize((size_t)F);
+            BKD_HIP(hipMemcpyAsync(tr_q.data(), qbuf[cur] + base, sizeof(int32_t) * F, hipMemcpyDeviceToHost, s));
+            BKD_HIP(hipMemcpyAsync(tr_l.data(), leafbuf[cur] + base, sizeof(int32_t) * F, hipMemcpyDeviceToHost, s));
+            BKD_HIP(hipStreamSynchronize(s));
+            for (int64_t j = 0; j < F; j++) {
+                t.trace_q.push_back(tr_q[(size_t)j]);
+                t.trace_leaf.push_back(tr_l[(size_t)j] == (uint32_t)nleaf ? -1 : (int32_t)tr_l[(size_t)j]);
+            }
+        }
+    }
+
+    // Sort the pending list, compute buffer offsets and work items, read the counters back.
+    void sort_and_offsets(int64_t count)
+    {
+        int which = launch_sort_pairs(leafbuf[cur], qbuf[cur], leafbuf[1 - cur], qbuf[1 - cur], count, kbits,
+                                      t.d_hist.as<uint32_t>(), s);
+        if (which) cur = 1 - cur;
+        launch_leaf_offsets(cnt, t.d_leaf_off.as<int32_t>(), nleaf, SCAN_QT, SCAN_DENSE_MIN, t.d_off.as<int32_t>(),
+                            t.d_tiles.as<int32_t>(), ctl, s);
+        if (!t.resident) {
+            BKD_HIP(hipMemcpyAsync(t.h_tiles.p, t.d_tiles.p, sizeof(int32_t) * 2 * (size_t)(nleaf + 1),
+                                   hipMemcpyDeviceToHost, s));
+            BKD_HIP(hipMemcpyAsync(t.h_tiles.as<int32_t>() + 2 * (nleaf + 1), t.d_off.p,
+                                   sizeof(int32_t) * (size_t)(nleaf + 1), hipMemcpyDeviceToHost, s));
+        }
+        readback();
+    }
+
+    ScanArgs scan_args(const float *base, int64_t shift) const
+    {
+        ScanArgs a{};
+        a.tiles = t.d_tiles.as<int32_t>();
+        a.sparse = a.tiles + nleaf + 1;
+        a.off = t.d_off.as<int32_t>();
+        a.bufq = qbuf[cur];
+        a.leaf_off = t.d_leaf_off.as<int32_t>();
+        a.base = base;
+        a.blk = t.d_leaf_blk.as<int64_t>();
+        a.blk_shift = shift;
+        a.Q = dQ;
+        a.d = d;
+        a.keys = t.d_keys.as<uint64_t>();
+        return a;
+    }
+
+    void run_scan(const ScanArgs &a)
+    {
+        if (a.item_count > 0) {
+            tdense.begin(s);
+            launch_leaf_scan(a, K, 0, s);
+            tdense.end(s);
+            t.stats.dense_launches++;
+        }
+        if (a.sitem_count > 0) {
+            tsparse.begin(s);
+            launch_leaf_scan(a, K, 1, s);
+            tsparse.end(s);
+            t.stats.sparse_launches++;
+        }
+    }
+
+    void count_work(int lf, int ll)
+    {
+        launch_count_work(t.d_off.as<int32_t>(), t.d_leaf_off.as<int32_t>(), lf, ll, SCAN_DENSE_MIN, ctl, s);
+    }
+
+    // Scan every buffered query of a resident structure.
+    void scan_resident()
+    {
+        count_work(0, nleaf - 1);
+        ScanArgs a = scan_args(t.d_chunk[0].as<float>(), 0);
+        a.chunk_lo = 0;
+        a.chunk_hi = t.host.n;
+        a.item_first = 0;
+        a.item_count = hctl[CTL_T];
+        a.sitem_first = 0;
+        a.sitem_count = hctl[CTL_S];
+        a.leaf_first = 0;
+        a.leaf_last = nleaf - 1;
+        run_scan(a);
+    }
+
+    int64_t chunk_items(int j) const
+    {
+        const Chunk &c = t.chunks[(size_t)j];
+        return (htiles()[c.leaf_last + 1] - htiles()[c.leaf_first]) + (hsparse()[c.leaf_last + 1] - hsparse()[c.leaf_first]);
+    }
+
+    void issue_copy(int b, int j)
+    {
+        const Chunk &c = t.chunks[(size_t)j];
+        const size_t bytes = (size_t)(c.word_hi - c.word_lo) * 4;
+        BKD_HIP(hipStreamWaitEvent(t.copy_stream, t.ev_used[b], 0));
+        BKD_HIP(hipMemcpyAsync(t.d_chunk[b].p, t.h_leaf.as<float>() + c.word_lo, bytes, hipMemcpyHostToDevice,
+                               t.copy_stream));
+        BKD_HIP(hipEventRecord(t.ev_copied[b], t.copy_stream));
+        t.chunk_in[b] = j;
+        t.stats.chunk_copies++;
+        t.stats.bytes_h2d += (int64_t)bytes;
+    }
+
+    // Scan the buffered queries of chunk j's leaves; prefetch chunk nj (-1: none) into the other buffer.
+    void scan_chunk(int j, int nj)
+    {
+        int b = (t.chunk_in[0] == j) ? 0 : (t.chunk_in[1] == j) ? 1 : -1;
+        if (b < 0) {
+            b = (t.chunk_in[0] == nj) ? 1 : 0;
+            issue_copy(b, j);
+        }
+        BKD_HIP(hipStreamWaitEvent(s, t.ev_copied[b], 0));
+        const Chunk &c = t.chunks[(size_t)j];
+        ScanArgs a = scan_args(t.d_chunk[b].as<float>(), -c.word_lo);
+        a.chunk_lo = c.lo;
+        a.chunk_hi = c.hi;
+        a.leaf_first = c.leaf_first;
+        a.leaf_last = c.leaf_last;
+        a.item_first = htiles()[c.leaf_first];
+        a.item_count = htiles()[c.leaf_last + 1] - htiles()[c.leaf_first];
+        a.sitem_first = hsparse()[c.leaf_first];
+        a.sitem_count = hsparse()[c.leaf_last + 1] - hsparse()[c.leaf_first];
+        run_scan(a);
+        BKD_HIP(hipEventRecord(t.ev_used[b], s));
+        if (nj >= 0 && nj != j && t.chunk_in[1 - b] != nj) issue_copy(1 - b, nj);
+    }
+
+    // ProcessAllBuffers over a streamed structure: every chunk holding a buffered leaf, in order.
+    void scan_all_chunks()
+    {
+        count_work(0, nleaf - 1);
+        std::vector<int> active;
+        for (int j = 0; j < (int)t.chunks.size(); j++)
+            if (chunk_items(j) > 0) active.push_back(j);
+        for (size_t ai = 0; ai < active.size(); ai++)
+            scan_chunk(active[ai], ai + 1 < active.size() ? active[ai + 1] : 0);
+    }
+
+    void end_call()
+    {
+        t.stats.calls++;
+        if (tracing) t.trace_off.push_back((int64_t)t.trace_q.size());
+    }
+
+    // ---------------------------------------------------------------- Algorithm 1
+    void algorithm1()
+    {
+        const int64_t M = t.M < 0 ? INT64_MAX : t.M;
+        const int64_t half = t.B > 0 ? (t.B + 1) / 2 : INT64_MAX;
+        int64_t in_head = 0, re_head = 0, re_len = 0, pend = 0;
+        while (in_head < m || re_len > 0) {
+            const int64_t take_re = std::min(M, re_len);
+            const int64_t take_in = std::min(M - take_re, m - in_head);
+            FetchSpec f{t.d_ring.as<int32_t>(), re_head, take_re, m, in_head, take_in};
+            find_leaf(f, pend);
+            pend += take_re + take_in;
+            re_head = (re_head + take_re) % m;
+            re_len -= take_re;
+            in_head += take_in;
+            const bool queues_empty = (in_head == m && re_len == 0);
+            bool trigger = queues_empty;
+            if (!trigger) {
+                readback();
+                trigger = hctl[CTL_MAXCNT] >= half;
+            }
+            if (!trigger) continue;
+            // ---- ProcessAllBuffers ----
+            sort_and_offsets(pend);
+            const int64_t V = hctl[CTL_V];
+            if (hctl[CTL_T] + hctl[CTL_S] > 0) {
+                if (t.resident) scan_resident();
+                else scan_all_chunks();
+            }
+            launch_ring_append(t.d_ring.as<int32_t>(), m, (re_head + re_len) % m, qbuf[cur], V, s);
+            re_len += V;
+            launch_fill_i32(cnt, 0, nleaf, s);
+            launch_fill_i32(ctl + CTL_MAXCNT, 0, 2, s);
+            pend = 0;
+            end_call();
+        }
+    }
+
+    // ---------------------------------------------------------------- lock-step rounds / chunk sweep
+    void lockstep()
+    {
+        // first round: every query descends from the root
+        FetchSpec f0{nullptr, 0, 0, 1, 0, m};
+        find_leaf(f0, 0);
+        int64_t P = m;  // pending entries (leaf order after each sort; finished ones sort last)
+        int cur_chunk = -1;
+        const int nchunks = (int)t.chunks.size();
+        for (;;) {
+            sort_and_offsets(P);
+            P = hctl[CTL_V];
+            if (P == 0) {
+                end_call();
+                break;
+            }
+            int lf = 0, ll = nleaf - 1;
+            if (t.resident) {
+                scan_resident();
+            } else if (!t.sweep) {
+                scan_all_chunks();
+            } else {
+                // drain the current chunk, else move to the next chunk holding pending queries
+                auto has = [&](int j) { return j >= 0 && chunk_items(j) > 0; };
+                int c = has(cur_chunk) ? cur_chunk : -1;
+                for (int x = 1; c < 0 && x <= nchunks; x++) {
+                    int j = (cur_chunk + x + nchunks) % nchunks;
+                    if (has(j)) c = j;
+                }
+                int nc = -1;
+                for (int x = 1; nc < 0 && x < nchunks; x++) {
+                    int j = (c + x) % nchunks;
+                    if (has(j)) nc = j;
+                }
+                count_work(t.chunks[(size_t)c].leaf_first, t.chunks[(size_t)c].leaf_last);
+                scan_chunk(c, nc);
+                cur_chunk = c;
+                lf = t.chunks[(size_t)c].leaf_first;
+                ll = t.chunks[(size_t)c].leaf_last;
+            }
+            end_call();
+            // route the scanned queries again; entries of other chunks keep their leaf
+            int64_t a = 0, e = P;
+            if (t.sweep) {
+                a = hoff()[lf];
+                e = hoff()[ll + 1];
+            }
+            launch_fill_i32(cnt + lf, 0, ll - lf + 1, s);
+            FetchSpec f{qbuf[cur] + a, 0, e - a, std::max<int64_t>(e - a, 1), 0, 0};
+            find_leaf(f, a);
+        }
+    }
+};
 
 }  // namespace
 
@@ -236,182 +543,25 @@ void tree_query_device(Tree &t, const float *dQ, int64_t m, int k, int64_t *d_id
     t.trace_off.assign(1, 0);
     t.trace_q.clear();
     t.trace_leaf.clear();
-    const bool tracing = (t.opt.flags & BKD_FLAG_TRACE) != 0;
     if (m == 0) return;
 
-    const HostTree &H = t.host;
-    const int d = H.d, h = H.h, nleaf = t.nleaf;
-    const int K = key_capacity(k);
-    t.d_keys.ensure(sizeof(uint64_t) * (size_t)m * K);
-    t.d_node.ensure(sizeof(int32_t) * (size_t)m);
-    t.d_ring.ensure(sizeof(int32_t) * (size_t)m);
-    t.d_pleaf.ensure(sizeof(uint32_t) * (size_t)m);
-    t.d_pq.ensure(sizeof(int32_t) * (size_t)m);
-    t.d_tleaf.ensure(sizeof(uint32_t) * (size_t)m);
-    t.d_tq.ensure(sizeof(int32_t) * (size_t)m);
-    t.d_hist.ensure(sizeof(uint32_t) * sort_hist_words(m));
-    t.d_cnt.ensure(sizeof(int32_t) * (size_t)nleaf);
-    t.d_off.ensure(sizeof(int32_t) * (size_t)(nleaf + 1));
-    t.d_tiles.ensure(sizeof(int32_t) * 2 * (size_t)(nleaf + 1));
-    if (!t.resident) t.h_tiles.ensure(sizeof(int32_t) * 2 * (size_t)(nleaf + 1));
-
-    int32_t *ctl = t.d_ctl.as<int32_t>();
-    int32_t *hctl = t.h_ctl.as<int32_t>();
-    int32_t *cnt = t.d_cnt.as<int32_t>();
-    launch_fill_i32(ctl, 0, CTL_WORDS, s);
-    launch_fill_i32(cnt, 0, nleaf, s);
-    launch_check_finite(dQ, m * d, ctl, s);
-    launch_init_state(t.d_node.as<int32_t>(), t.d_keys.as<uint64_t>(), m, K, s);
-
-    Timer timer;
-    timer.on = (t.opt.flags & BKD_FLAG_TIMING) != 0;
-    const int64_t M = t.M < 0 ? INT64_MAX : t.M;
-    const int64_t half = t.B > 0 ? (t.B + 1) / 2 : INT64_MAX;
-    const int kbits = key_bits_for(nleaf);
-    const size_t bpp = (size_t)(4 * d + 4);
-
-    auto readback = [&](size_t words) {
-        BKD_HIP(hipMemcpyAsync(hctl, ctl, sizeof(int32_t) * words, hipMemcpyDeviceToHost, s));
-        BKD_HIP(hipStreamSynchronize(s));
-        if (hctl[CTL_BAD]) fail(BKD_EINVAL, "query coordinates must be finite");
-    };
-
-    int64_t in_head = 0, re_head = 0, re_len = 0, pend = 0;
-    std::vector<int32_t> tr_q, tr_l;
-    while (in_head < m || re_len > 0) {
-        const int64_t take_re = std::min(M, re_len);
-        const int64_t take_in = std::min(M - take_re, m - in_head);
-        const int64_t F = take_re + take_in;
-        FetchSpec f{t.d_ring.as<int32_t>(), re_head, take_re, m, in_head, take_in};
-        launch_find_leaf(f, dQ, d, t.d_node.as<int32_t>(), t.d_keys.as<uint64_t>(), K, k, t.d_split.as<float>(), h,
-                         t.d_pleaf.as<uint32_t>(), t.d_pq.as<int32_t>(), pend, cnt, ctl, s);
-        t.stats.fetches++;
-        if (tracing && F > 0) {
-            tr_q.resize((size_t)F);
-            tr_l.resize((size_t)F);
-            BKD_HIP(hipMemcpyAsync(tr_q.data(), t.d_pq.as<int32_t>() + pend, sizeof(int32_t) * F,
-                                   hipMemcpyDeviceToHost, s));
-            BKD_HIP(hipMemcpyAsync(tr_l.data(), t.d_pleaf.as<uint32_t>() + pend, sizeof(int32_t) * F,
-                                   hipMemcpyDeviceToHost, s));
-            BKD_HIP(hipStreamSynchronize(s));
-            for (int64_t j = 0; j < F; j++) {
-                t.trace_q.push_back(tr_q[(size_t)j]);
-                t.trace_leaf.push_back(tr_l[(size_t)j] == (uint32_t)nleaf ? -1 : tr_l[(size_t)j]);
-            }
-        }
-        pend += F;
-        re_head = (re_head + take_re) % m;
-        re_len -= take_re;
-        in_head += take_in;
-        const bool queues_empty = (in_head == m && re_len == 0);
-        bool trigger = queues_empty;
-        if (!trigger) {
-            readback(CTL_WORDS);
-            trigger = hctl[CTL_MAXCNT] >= half;
-        }
-        if (!trigger) continue;
-
-        // ---- ProcessAllBuffers ----
-        int which = launch_sort_pairs(t.d_pleaf.as<uint32_t>(), t.d_pq.as<int32_t>(), t.d_tleaf.as<uint32_t>(),
-                                      t.d_tq.as<int32_t>(), pend, kbits, t.d_hist.as<uint32_t>(), s);
-        const int32_t *bufq = which ? t.d_tq.as<int32_t>() : t.d_pq.as<int32_t>();
-        launch_leaf_offsets(cnt, t.d_leaf_off.as<int32_t>(), nleaf, SCAN_QT, SCAN_DENSE_MIN, t.d_off.as<int32_t>(),
-                            t.d_tiles.as<int32_t>(), ctl, s);
-        if (!t.resident)
-            BKD_HIP(hipMemcpyAsync(t.h_tiles.p, t.d_tiles.p, sizeof(int32_t) * 2 * (size_t)(nleaf + 1),
-                                   hipMemcpyDeviceToHost, s));
-        readback(CTL_WORDS);
-        const int64_t V = hctl[CTL_V];
-        const int64_t T = hctl[CTL_T];
-        const int64_t S = hctl[CTL_S];
-        if (T + S > 0) {
-            ScanArgs a{};
-            a.tiles = t.d_tiles.as<int32_t>();
-            a.sparse = a.tiles + nleaf + 1;
-            a.off = t.d_off.as<int32_t>();
-            a.bufq = bufq;
-            a.leaf_off = t.d_leaf_off.as<int32_t>();
-            a.Q = dQ;
-            a.d = d;
-            a.keys = t.d_keys.as<uint64_t>();
-            if (t.resident) {
-                a.X = t.d_chunk[0].as<float>();
-                a.orig = reinterpret_cast<const int32_t *>(a.X + (size_t)d * H.n);
-                a.pitch = H.n;
-                a.chunk_lo = 0;
-                a.chunk_hi = H.n;
-                a.item_first = 0;
-                a.item_count = (int32_t)T;
-                a.sitem_first = 0;
-                a.sitem_count = (int32_t)S;
-                a.leaf_first = 0;
-                a.leaf_last = nleaf - 1;
-                timer.begin(s);
-                launch_leaf_scan(a, K, s);
-                timer.end(s);
-                t.stats.scan_launches++;
-            } else {
-                const int32_t *tiles = t.h_tiles.as<int32_t>();
-                const int32_t *sparse = tiles + nleaf + 1;
-                std::vector<int> active;
-                for (int j = 0; j < (int)t.chunks.size(); j++) {
-                    const Chunk &c = t.chunks[(size_t)j];
-                    if (tiles[c.leaf_last + 1] > tiles[c.leaf_first] || sparse[c.leaf_last + 1] > sparse[c.leaf_first])
-                        active.push_back(j);
-                }
-                for (size_t ai = 0; ai < active.size(); ai++) {
-                    const int j = active[ai];
-                    const Chunk &c = t.chunks[(size_t)j];
-                    int b = (t.chunk_in[0] == j) ? 0 : (t.chunk_in[1] == j) ? 1 : -1;
-                    if (b < 0) {
-                        // not prefetched: take the buffer that the next chunk does not need
-                        int nj = ai + 1 < active.size() ? active[ai + 1] : -1;
-                        b = (t.chunk_in[0] == nj) ? 1 : 0;
-                        issue_copy(t, b, j);
-                    }
-                    BKD_HIP(hipStreamWaitEvent(s, t.ev_copied[b], 0));
-                    a.X = t.d_chunk[b].as<float>();
-                    const int64_t len = c.hi - c.lo;
-                    a.orig = reinterpret_cast<const int32_t *>(a.X + (size_t)d * len);
-                    a.pitch = len;
-                    a.chunk_lo = c.lo;
-                    a.chunk_hi = c.hi;
-                    a.leaf_first = c.leaf_first;
-                    a.leaf_last = c.leaf_last;
-                    a.item_first = tiles[c.leaf_first];
-                    a.item_count = tiles[c.leaf_last + 1] - tiles[c.leaf_first];
-                    a.sitem_first = sparse[c.leaf_first];
-                    a.sitem_count = sparse[c.leaf_last + 1] - sparse[c.leaf_first];
-                    timer.begin(s);
-                    launch_leaf_scan(a, K, s);
-                    timer.end(s);
-                    t.stats.scan_launches++;
-                    BKD_HIP(hipEventRecord(t.ev_used[b], s));
-                    // prefetch: the next active chunk, or chunk 0 for the next call
-                    const int nj = ai + 1 < active.size() ? active[ai + 1] : 0;
-                    const int nb = 1 - b;
-                    if (t.chunk_in[nb] != nj && t.chunk_in[b] != nj) issue_copy(t, nb, nj);
-                }
-            }
-        }
-        (void)bpp;
-        // reinsert the processed ids (ascending leaf, buffer order)
-        launch_ring_append(t.d_ring.as<int32_t>(), m, (re_head + re_len) % m, bufq, V, s);
-        re_len += V;
-        launch_fill_i32(cnt, 0, nleaf, s);
-        launch_fill_i32(ctl + CTL_MAXCNT, 0, 2, s);
-        pend = 0;
-        t.stats.calls++;
-        if (tracing) t.trace_off.push_back((int64_t)t.trace_q.size());
+    Run r(t, s, dQ, m, k);
+    launch_fill_i32(r.ctl, 0, CTL_WORDS, s);
+    launch_fill_i32(r.cnt, 0, t.nleaf, s);
+    launch_check_finite(dQ, m * t.host.d, r.ctl, s);
+    launch_init_state(t.d_node.as<int32_t>(), t.d_keys.as<uint64_t>(), m, r.K, s);
+    if (t.M < 0) r.lockstep();
+    else r.algorithm1();
+    launch_finalize(t.d_keys.as<uint64_t>(), r.K, k, m, d_idx, d_dist, (t.opt.flags & BKD_FLAG_SQUARED) != 0, s);
+    r.readback();
+    std::memcpy(&t.stats.visits, r.hctl + CTL_VISITS_LO, 8);
+    std::memcpy(&t.stats.dense_pairs, r.hctl + CTL_DPAIRS_LO, 8);
+    std::memcpy(&t.stats.sparse_pairs, r.hctl + CTL_SPAIRS_LO, 8);
+    t.stats.pairs = t.stats.dense_pairs + t.stats.sparse_pairs;
+    if (r.tdense.on) {
+        t.stats.dense_ms = r.tdense.total_ms();
+        t.stats.sparse_ms = r.tsparse.total_ms();
     }
-    launch_finalize(t.d_keys.as<uint64_t>(), K, k, m, d_idx, d_dist, (t.opt.flags & BKD_FLAG_SQUARED) != 0, s);
-    readback(CTL_WORDS);
-    int64_t pairs, visits;
-    std::memcpy(&pairs, hctl + CTL_PAIRS_LO, 8);
-    std::memcpy(&visits, hctl + CTL_VISITS_LO, 8);
-    t.stats.pairs = pairs;
-    t.stats.visits = visits;
-    if (timer.on) t.stats.scan_ms = timer.total_ms();
     t.stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 

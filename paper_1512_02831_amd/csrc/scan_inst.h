@@ -4,12 +4,12 @@
 
 #define BKD_SCAN_CASE(D, KK)                                                                        \
     case KK:                                                                                        \
-        if (a.item_count > 0) k_leaf_scan<D, KK><<<grid, SCAN_THREADS, 0, s>>>(a);                 \
-        if (a.sitem_count > 0) k_leaf_scan_sparse<D, KK><<<sgrid, SCAN_THREADS, 0, s>>>(a);        \
+        if (!sparse && a.item_count > 0) k_leaf_scan<D, KK><<<grid, SCAN_THREADS, 0, s>>>(a);      \
+        if (sparse && a.sitem_count > 0) k_leaf_scan_sparse<D, KK><<<sgrid, SCAN_THREADS, 0, s>>>(a); \
         break;
 
 #define BKD_SCAN_INSTANTIATE(D)                                                                     \
-    template <> void launch_leaf_scan_d<D>(const ScanArgs &a, int K, hipStream_t s)                \
+    template <> void launch_leaf_scan_d<D>(const ScanArgs &a, int K, int sparse, hipStream_t s)                \
     {                                                                                               \
         unsigned grid = (unsigned)(((int64_t)a.item_count + 7) / 8 * 8);                            \
         unsigned sgrid = (unsigned)(((int64_t)a.sitem_count + 31) / 32 * 8);                        \
