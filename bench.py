@@ -11,6 +11,12 @@ Workloads (seeded synthetic stand-ins for the paper's catalogues, Section 4.1):
   small     n = 2^15, m = 2^12, d = 10 uniform on [0,1]^10, k = 10, height 6
   streamed  n = 2^28, m = 2^24, same mixture, k = 10, height 14, leaf structure streamed
             through a 2 GB device budget (Section 3.2); also times the same tree resident
+  batched   1024 instances, n = 2^U(10,18), m = 2^U(8,16), d in {3,5,10,15}, k in {1,5,10,32},
+            4-component mixtures, height floor(log2(n/64)), one persistent graph launch;
+            also times the plain per-instance loop on the same GPU
+  served    two resident trees (n = 2^27, d = 10, height 14; n = 2^25, d = 15, height 12),
+            Poisson requests of m = 2^U(0,16) queries, k in {1,10,32}: saturated throughput
+            (closed loop), then p50/p99 latency at 0.5 and 0.8 of it (open loop)
 """
 from __future__ import annotations
 
@@ -109,12 +115,165 @@ def cpu_baseline(P, Q, k, budget_s):
                       f"leaf size 32, OpenMP over queries ({threads} threads, {cpu_model()})"}
 
 
+def run_batched(args, torch, bkd):
+    shapes = datagen.batch_shapes(args.seed)
+    inst = []
+    for i, sh in enumerate(shapes):
+        P, Q = datagen.batch_instance(args.seed, i, sh["n"], sh["m"], sh["d"])
+        inst.append((P, Q, sh["k"], sh["h"]))
+    total_m = sum(len(x[1]) for x in inst)
+    stream = torch.cuda.Stream()
+    b = bkd.batch_create(inst)
+    best, best_ms = bkd.batch_autotune(b)
+    for _ in range(args.warmup):
+        bkd.batch_run(b, stream=stream)
+    torch.cuda.synchronize()
+    run_ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bkd.batch_run(b, stream=stream)
+        stream.synchronize()
+        st = bkd.batch_stats(b)
+        run_ms += st["run_ms"]
+        if st["error"]:
+            raise RuntimeError(f"batched launch stopped early: {st}")
+    wall = time.perf_counter() - t0
+    b.free()
+    # the plain per-instance loop: one tree and one query call per instance, queries resident
+    trees = [bkd.build(P, h, buffer_size=-1, fetch_size=-1) for (P, Q, k, h) in inst]
+    dev = [(torch.from_numpy(Q).to("cuda"), torch.empty((len(Q), k), dtype=torch.int64, device="cuda"),
+            torch.empty((len(Q), k), dtype=torch.float32, device="cuda")) for (P, Q, k, h) in inst]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for t, (P, Q, k, h), (dq, di, dd) in zip(trees, inst, dev):
+        if len(Q):
+            bkd.query_async(t, dq, k, di, dd, stream=stream)
+    stream.synchronize()
+    loop_s = time.perf_counter() - t1
+    for t in trees:
+        t.free()
+    value = total_m * args.steps / wall
+    flops = st["flops"]
+    achieved = flops / (st["run_ms"] * 1e-3) / 1e12
+    return {
+        "metric": "kNN queries/s (batched form, 1024 instances)",
+        "value": round(value, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched: 1024 instances, seed {args.seed}, n=2^U(10,18) m=2^U(8,16) "
+                               "d in {3,5,10,15} k in {1,5,10,32}, 4-component mixtures, height floor(log2(n/64)), "
+                               "one persistent hipGraph launch per step",
+                   "queries": total_m, "points": sum(len(x[0]) for x in inst),
+                   "tuning": {"leaves_per_task": best.leaves_per_task, "groups_per_cu": best.groups_per_cu,
+                              "solo_max": best.solo_max, "tuned_ms": round(best_ms, 3)},
+                   "rounds": st["rounds"], "tasks": st["tasks"], "pairs": st["pairs"],
+                   "plain_loop_queries_per_s": round(total_m / loop_s, 1),
+                   "speedup_vs_plain_loop": round((total_m / (wall / args.steps)) / (total_m / loop_s), 2)},
+        "roofline": {"kernel": "k_batch (persistent)", "bound": "alu", "achieved": round(achieved, 3),
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                     "peak_nonpacked": round(FP32_NONPACKED_TFLOPS, 1),
+                     "frac_nonpacked": round(achieved / FP32_NONPACKED_TFLOPS, 4),
+                     "avg_launch_ms": round(run_ms / args.steps, 4), "flops_per_launch": flops},
+    }
+
+
+def run_served(args, torch, bkd):
+    import threading
+
+    specs = [dict(n=1 << 27, d=10, h=14), dict(n=1 << 25, d=15, h=12)]
+    trees, params = [], []
+    for t, sp in enumerate(specs):
+        seed = args.seed + 100 * (t + 1)
+        pr = datagen.mixture_params(seed, sp["d"], 16)
+        P = datagen.mixture(seed, datagen.STREAM_P, sp["n"], sp["d"], 16, pr)
+        trees.append(bkd.build(P, sp["h"], buffer_size=-1, fetch_size=-1))
+        params.append((seed, pr))
+        del P
+    srv = bkd.server_create(slots_per_session=1 << 21)
+    tids = [bkd.server_add_tree(srv, t) for t in trees]
+
+    def request_queries(trace):
+        out = []
+        for i, r in enumerate(trace):
+            seed, pr = params[r["tree"]]
+            g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 7, i])))
+            means, stds = pr
+            c = g.integers(0, len(means), size=r["m"])
+            Q = (means[c] + stds[c] * g.standard_normal((r["m"], specs[r["tree"]]["d"]))).astype(np.float32)
+            out.append(Q)
+        return out
+
+    def replay(trace, Qs, open_loop):
+        hs = [None] * len(trace)
+        t0 = time.perf_counter()
+        for i, (r, Q) in enumerate(zip(trace, Qs)):
+            if open_loop:
+                delay = r["t"] - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+            hs[i] = bkd.submit(srv, tids[r["tree"]], Q, r["k"])
+        for h in hs:
+            bkd.wait(srv, h)
+        wall = time.perf_counter() - t0
+        lat = np.array([bkd.request_times(srv, h)[2] - bkd.request_times(srv, h)[0] for h in hs])
+        for h in hs:
+            bkd.release(srv, h)
+        return wall, lat
+
+    # warm-up: one request per session (creates the sessions)
+    warm = datagen.request_trace(args.seed + 1, 12, 1e9)
+    replay(warm, request_queries(warm), False)
+    # saturated throughput: every request submitted at once
+    closed = datagen.request_trace(args.seed + 2, 600, 1e9)
+    Qc = request_queries(closed)
+    qc = sum(r["m"] for r in closed)
+    wall_c, lat_c = replay(closed, Qc, False)
+    x_sat = qc / wall_c
+    # the plain per-batch loop: one query call per request, one after another
+    t1 = time.perf_counter()
+    for r, Q in zip(closed, Qc):
+        bkd.query(trees[r["tree"]], Q, r["k"])
+    loop_qps = qc / (time.perf_counter() - t1)
+    mean_m = (2 ** 16 - 1) / (16 * np.log(2))
+    levels = {}
+    for frac in (0.5, 0.8):
+        rate = frac * x_sat / mean_m
+        trace = datagen.request_trace(args.seed + int(frac * 10), args.served_requests, rate)
+        Qs = request_queries(trace)
+        wall, lat = replay(trace, Qs, True)
+        levels[str(frac)] = {"offered_requests_per_s": round(rate, 2),
+                             "offered_queries_per_s": round(frac * x_sat, 1),
+                             "achieved_queries_per_s": round(sum(r["m"] for r in trace) / wall, 1),
+                             "requests": len(trace), "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3)}
+    srv.destroy()
+    for t in trees:
+        t.free()
+    return {
+        "metric": "kNN queries/s (served form) + p50/p99 latency at fixed offered load",
+        "value": round(x_sat, 1), "unit": "queries/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(wall_c * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "served: trees n=2^27 d=10 h=14 and n=2^25 d=15 h=12 (16-component mixtures), "
+                               "requests m=floor(2^U(0,16)), k in {1,10,32}, tree uniform; saturated throughput "
+                               f"from {len(closed)} requests submitted at once, latency from Poisson arrivals",
+                   "closed_loop_requests": len(closed), "closed_loop_queries": qc,
+                   "closed_loop_p50_ms": round(float(np.percentile(lat_c, 50)) * 1e3, 3),
+                   "closed_loop_p99_ms": round(float(np.percentile(lat_c, 99)) * 1e3, 3),
+                   "plain_loop_queries_per_s": round(loop_qps, 1),
+                   "speedup_vs_plain_loop": round(x_sat / loop_qps, 2),
+                   "open_loop": levels},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ondevice", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="ondevice", choices=sorted(WORKLOADS) + ["batched", "served"])
+    ap.add_argument("--served-requests", type=int, default=2000, help="requests per open-loop level")
     ap.add_argument("--seed", type=int, default=datagen.DEFAULT_SEED)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU baseline sample size in seconds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -129,6 +288,12 @@ def main():
     import torch
     import paper_1512_02831_amd as bkd
 
+    if args.workload == "batched":
+        print(json.dumps(run_batched(args, torch, bkd)), flush=True)
+        return
+    if args.workload == "served":
+        print(json.dumps(run_served(args, torch, bkd)), flush=True)
+        return
     w = WORKLOADS[args.workload]
     n, m, d, k, h = w["n"], w["m"], w["d"], w["k"], w["h"]
     P, Q = make_inputs(w, args.seed)

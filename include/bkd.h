@@ -205,6 +205,143 @@ int bkd_last_stats(const bkd_tree *tree, bkd_stats *out);
 int bkd_trace_size(const bkd_tree *tree, int64_t *ncalls, int64_t *length);
 int bkd_trace_get(const bkd_tree *tree, int64_t *call_off, int32_t *query, int32_t *leaf);
 
+/* ------------------------------------------------------------------------ */
+/* Batched form: many independent instances in one persistent launch.       */
+/*                                                                          */
+/* Every instance is a complete problem of Section 2.2 with its own P, Q, d, */
+/* k and height, answered by the buffered search of Algorithm 1 in lock-step */
+/* rounds.  All instances run inside one persistent kernel, captured in a    */
+/* HIP graph: a device task queue hands out routing tasks (FindLeafBatch and */
+/* buffer insertion of one instance, one workgroup) and scan tasks (the leaf */
+/* scans of a group of that instance's buffered leaves), and each instance   */
+/* advances to its next round as soon as its own scans are done, with no    */
+/* barrier across instances.  Within a leaf the order of buffered queries is */
+/* unspecified in this form; results are the same as bkd_query's.           */
+
+typedef struct bkd_instance {
+    const float *P;     /* host [n][d] float32, finite                              */
+    int64_t n;          /* 1 <= n <= 2^31 - 1                                       */
+    const float *Q;     /* host [m][d] float32, finite                              */
+    int64_t m;          /* 0 <= m <= 2^31 - 1                                       */
+    int32_t d;          /* 1 <= d <= BKD_MAX_DIM                                    */
+    int32_t k;          /* 1 <= k <= min(n, BKD_MAX_K)                              */
+    int32_t height;     /* 0 <= h <= 12 and 2^h <= n                                */
+    int64_t *out_idx;   /* host [m][k], filled by bkd_batch_results                 */
+    float *out_dist;    /* host [m][k], filled by bkd_batch_results                 */
+} bkd_instance;
+
+/* Schedule of the persistent launch (results do not depend on it). */
+typedef struct bkd_tuning {
+    int32_t leaves_per_task; /* buffered leaves per scan task (1..256); 0: default 8          */
+    int32_t groups_per_cu;   /* persistent workgroups per compute unit (1..16); 0: default 4  */
+    int32_t solo_max;        /* rounds with at most this many active queries of an instance  */
+                             /* run whole inside one workgroup; 0: default 2048             */
+} bkd_tuning;
+
+typedef struct bkd_batch_stats {
+    int64_t instances, queries;
+    int64_t tasks;      /* tasks executed by the last run                          */
+    int64_t rounds;     /* sum over instances of lock-step rounds                   */
+    int64_t pairs;      /* (query, leaf point) pairs scanned                        */
+    int64_t flops;      /* 3 d flops per pair, summed over instances                */
+    double run_ms;      /* device time of the last run (graph launch)               */
+    int32_t error;      /* nonzero: the last run stopped early (queue overflow or   */
+                        /* stall guard); its results are not valid                  */
+} bkd_batch_stats;
+
+typedef struct bkd_batch bkd_batch;
+
+/*
+ * Build every instance's tree on the host (Section 3.1) and upload trees and
+ * queries to `device`.  The library copies P and Q; the out_* pointers are
+ * kept and written by bkd_batch_results.  flags: BKD_FLAG_SQUARED or 0.
+ * Errors: BKD_EINVAL (any instance's arguments, with its index in the
+ * message), BKD_ENOMEM, BKD_EDEVICE.
+ */
+int bkd_batch_create(const bkd_instance *inst, int32_t count, int32_t device, int32_t flags, bkd_batch **out);
+
+/*
+ * Answer every instance: one launch of the captured graph (state reset, then
+ * the persistent kernel) on `stream` (a hipStream_t; NULL = null stream).
+ * tune NULL: the tuning chosen by bkd_batch_autotune, else the defaults.
+ * Results stay in device memory; the call returns once the graph is launched.
+ */
+int bkd_batch_run(bkd_batch *batch, const bkd_tuning *tune, void *stream);
+
+/* Synchronise and copy every instance's results to its out_idx / out_dist. */
+int bkd_batch_results(bkd_batch *batch);
+
+/*
+ * Time a set of candidate tunings on this batch (each run in full, after one
+ * warm-up run) and keep the fastest for later bkd_batch_run(batch, NULL, ...).
+ * *best and *best_ms (either may be NULL) receive the winner.
+ */
+int bkd_batch_autotune(bkd_batch *batch, bkd_tuning *best, double *best_ms);
+
+int bkd_batch_stats_get(const bkd_batch *batch, bkd_batch_stats *out);
+int bkd_batch_free(bkd_batch *batch);
+
+/* ------------------------------------------------------------------------ */
+/* Served form: resident trees, continuous batching of query requests.      */
+/*                                                                          */
+/* A server answers requests (a batch of m queries, its own k, on one of its */
+/* trees) as they arrive.  Each (tree, key capacity) pair is served by a    */
+/* session that runs lock-step rounds of Algorithm 1 continuously on its own */
+/* stream; between two rounds it admits waiting requests, in arrival order, */
+/* whose queries fit into its free query slots (on-the-fly insertion of new */
+/* indices, Section 3.2).  Admitted queries share the leaf buffers of every */
+/* query already in flight on that tree.  A request completes when its last */
+/* query finishes; its results are then copied to the caller's arrays.     */
+/* Results are the same as bkd_query's, alone or in any mix of requests.    */
+
+#define BKD_REQ_WAITING 0
+#define BKD_REQ_RUNNING 1
+#define BKD_REQ_DONE 2
+#define BKD_REQ_CANCELLED 3
+
+typedef struct bkd_server_opts {
+    int64_t slots_per_session; /* query slots of one session (its memory: 4d + 8K + 36 bytes     */
+                               /* per slot, K = key capacity >= k); 0: 2^20                       */
+    int32_t max_requests;      /* requests in flight per session; 0: 4096                        */
+    int32_t device;            /* HIP device of the server (trees must live there)               */
+    int32_t flags;             /* BKD_FLAG_SQUARED or 0                                          */
+} bkd_server_opts;
+
+typedef struct bkd_server bkd_server;
+
+int bkd_server_create(const bkd_server_opts *opts, bkd_server **out);
+
+/* Serve a built, resident tree (leaf_budget_bytes 0); the tree must outlive the server. */
+int bkd_server_add_tree(bkd_server *srv, bkd_tree *tree, int32_t *tree_id);
+
+/*
+ * Submit a request: Q host [m][d] (copied), 1 <= m <= slots_per_session,
+ * 1 <= k <= min(n, 64); out_idx [m][k] and out_dist [m][k] are host arrays the
+ * caller keeps valid until the request is done.  Returns at once with
+ * *req_id.  Errors: BKD_EINVAL, BKD_ENOTFOUND (tree id), BKD_EBUSY (m larger
+ * than a session's slots: it could never be admitted), BKD_EDEVICE.
+ */
+int bkd_submit(bkd_server *srv, int32_t tree_id, const float *Q, int64_t m, int32_t k, int64_t *out_idx,
+               float *out_dist, int64_t *req_id);
+
+/* Request state: BKD_REQ_*. */
+int bkd_poll(bkd_server *srv, int64_t req_id, int32_t *state);
+
+/* Block until the request is done or cancelled; timeout_us < 0 waits forever (else BKD_ETIMEOUT). */
+int bkd_wait(bkd_server *srv, int64_t req_id, int64_t timeout_us);
+
+/* Cancel a request: a waiting request is dropped; a running one completes with state CANCELLED. */
+int bkd_cancel(bkd_server *srv, int64_t req_id);
+
+/* Host steady-clock times (seconds) of submission, admission and completion. */
+int bkd_request_times(bkd_server *srv, int64_t req_id, double *submit_s, double *admit_s, double *done_s);
+
+/* Forget a finished request (its id becomes unknown). */
+int bkd_release(bkd_server *srv, int64_t req_id);
+
+/* Stop every session and free the server (trees are not freed). */
+int bkd_server_destroy(bkd_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

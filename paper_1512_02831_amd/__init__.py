@@ -71,6 +71,21 @@ _PROTOS = {
     "bkd_last_stats": (ctypes.c_int, [_V, _V]),
     "bkd_trace_size": (ctypes.c_int, [_V, _V, _V]),
     "bkd_trace_get": (ctypes.c_int, [_V, _V, _V, _V]),
+    "bkd_batch_create": (ctypes.c_int, [_V, _I32, _I32, _I32, _V]),
+    "bkd_batch_run": (ctypes.c_int, [_V, _V, _V]),
+    "bkd_batch_results": (ctypes.c_int, [_V]),
+    "bkd_batch_autotune": (ctypes.c_int, [_V, _V, _V]),
+    "bkd_batch_stats_get": (ctypes.c_int, [_V, _V]),
+    "bkd_batch_free": (ctypes.c_int, [_V]),
+    "bkd_server_create": (ctypes.c_int, [_V, _V]),
+    "bkd_server_add_tree": (ctypes.c_int, [_V, _V, _V]),
+    "bkd_submit": (ctypes.c_int, [_V, _I32, _V, _I64, _I32, _V, _V, _V]),
+    "bkd_poll": (ctypes.c_int, [_V, _I64, _V]),
+    "bkd_wait": (ctypes.c_int, [_V, _I64, _I64]),
+    "bkd_cancel": (ctypes.c_int, [_V, _I64]),
+    "bkd_request_times": (ctypes.c_int, [_V, _I64, _V, _V, _V]),
+    "bkd_release": (ctypes.c_int, [_V, _I64]),
+    "bkd_server_destroy": (ctypes.c_int, [_V]),
 }
 
 
@@ -237,3 +252,194 @@ def trace(tree: Tree):
     leaf = np.zeros(max(ln.value, 1), dtype=np.int32)
     _check(lib().bkd_trace_get(tree.handle, _p(off), _p(q), _p(leaf)))
     return off, q[: ln.value], leaf[: ln.value]
+
+
+# ---------------------------------------------------------------------------
+# Batched form
+
+class Instance(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_void_p), ("n", ctypes.c_int64), ("Q", ctypes.c_void_p), ("m", ctypes.c_int64),
+                ("d", ctypes.c_int32), ("k", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("out_idx", ctypes.c_void_p), ("out_dist", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("leaves_per_task", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32), ("solo_max", ctypes.c_int32)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("instances", ctypes.c_int64), ("queries", ctypes.c_int64), ("tasks", ctypes.c_int64),
+                ("rounds", ctypes.c_int64), ("pairs", ctypes.c_int64), ("flops", ctypes.c_int64),
+                ("run_ms", ctypes.c_double), ("error", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Batch:
+    """Handle of ``bkd_batch_create``; keeps the host arrays it refers to alive."""
+
+    def __init__(self, handle, arrays, outputs):
+        self._h, self._arrays, self.outputs = handle, arrays, outputs
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("batch has been freed")
+        return self._h
+
+    def free(self):
+        if self._h:
+            _check(lib().bkd_batch_free(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+
+def batch_create(instances, device: int = 0, flags: int = 0) -> Batch:
+    """``bkd_batch_create``: instances = iterable of (P [n,d], Q [m,d], k, height)."""
+    inst = (Instance * max(1, len(instances)))()
+    arrays, outputs = [], []
+    for i, (P, Q, k, h) in enumerate(instances):
+        P = np.ascontiguousarray(P, dtype=np.float32)
+        Q = np.ascontiguousarray(Q, dtype=np.float32)
+        m = Q.shape[0]
+        oi = np.zeros((m, k), dtype=np.int64)
+        od = np.zeros((m, k), dtype=np.float32)
+        arrays += [P, Q]
+        outputs.append((oi, od))
+        inst[i] = Instance(P.ctypes.data, P.shape[0], Q.ctypes.data, m, P.shape[1], k, h, oi.ctypes.data,
+                           od.ctypes.data)
+    h = ctypes.c_void_p()
+    _check(lib().bkd_batch_create(ctypes.cast(inst, ctypes.c_void_p), len(instances), device, flags,
+                                  ctypes.byref(h)))
+    return Batch(h.value, arrays, outputs)
+
+
+def batch_run(batch: Batch, tuning: Tuning | None = None, stream=None):
+    s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+    _check(lib().bkd_batch_run(batch.handle, ctypes.byref(tuning) if tuning is not None else None, s))
+
+
+def batch_results(batch: Batch):
+    """``bkd_batch_results``: list of (idx [m,k], dist [m,k]) per instance."""
+    _check(lib().bkd_batch_results(batch.handle))
+    return batch.outputs
+
+
+def batch_autotune(batch: Batch):
+    t = Tuning()
+    ms = ctypes.c_double()
+    _check(lib().bkd_batch_autotune(batch.handle, ctypes.byref(t), ctypes.byref(ms)))
+    return t, ms.value
+
+
+def batch_stats(batch: Batch) -> dict:
+    st = BatchStats()
+    _check(lib().bkd_batch_stats_get(batch.handle, ctypes.byref(st)))
+    return st.as_dict()
+
+
+# ---------------------------------------------------------------------------
+# Served form
+
+REQ_WAITING, REQ_RUNNING, REQ_DONE, REQ_CANCELLED = 0, 1, 2, 3
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("slots_per_session", ctypes.c_int64), ("max_requests", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+class Request:
+    def __init__(self, rid, Q, idx, dist):
+        self.id, self._Q, self.idx, self.dist = rid, Q, idx, dist
+
+
+class Server:
+    """Handle of ``bkd_server_create``; keeps served trees and request arrays alive."""
+
+    def __init__(self, handle):
+        self._h, self.trees = handle, []
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("server has been destroyed")
+        return self._h
+
+    def destroy(self):
+        if self._h:
+            _check(lib().bkd_server_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+
+def server_create(slots_per_session: int = 0, max_requests: int = 0, device: int = 0, flags: int = 0) -> Server:
+    o = ServerOpts(slots_per_session, max_requests, device, flags)
+    h = ctypes.c_void_p()
+    _check(lib().bkd_server_create(ctypes.byref(o), ctypes.byref(h)))
+    return Server(h.value)
+
+
+def server_add_tree(srv: Server, tree: Tree) -> int:
+    tid = ctypes.c_int32()
+    _check(lib().bkd_server_add_tree(srv.handle, tree.handle, ctypes.byref(tid)))
+    srv.trees.append(tree)
+    return tid.value
+
+
+def submit(srv: Server, tree_id: int, Q, k: int) -> Request:
+    Q = np.ascontiguousarray(Q, dtype=np.float32)
+    m = Q.shape[0]
+    idx = np.zeros((m, k), dtype=np.int64)
+    dist = np.zeros((m, k), dtype=np.float32)
+    rid = ctypes.c_int64()
+    _check(lib().bkd_submit(srv.handle, tree_id, _p(Q), m, k, _p(idx), _p(dist), ctypes.byref(rid)))
+    return Request(rid.value, Q, idx, dist)
+
+
+def wait(srv: Server, req: Request, timeout_us: int = -1):
+    _check(lib().bkd_wait(srv.handle, req.id, timeout_us))
+    return req.idx, req.dist
+
+
+def poll(srv: Server, req: Request) -> int:
+    st = ctypes.c_int32()
+    _check(lib().bkd_poll(srv.handle, req.id, ctypes.byref(st)))
+    return st.value
+
+
+def cancel(srv: Server, req: Request):
+    _check(lib().bkd_cancel(srv.handle, req.id))
+
+
+def request_times(srv: Server, req: Request):
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().bkd_request_times(srv.handle, req.id, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def release(srv: Server, req: Request):
+    _check(lib().bkd_release(srv.handle, req.id))

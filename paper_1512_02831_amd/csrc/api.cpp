@@ -4,13 +4,13 @@
 
 #include "internal.h"
 
-struct bkd_tree {
-    bkd::Tree t;
-    hipStream_t stream = nullptr;  // stream of the host-pointer entry point
-};
-
 namespace bkd {
 const char *last_error_cstr();
+}
+
+namespace bkd {
+// The boundary's exception guard, shared with the batched and served forms.
+int guarded_call(const std::function<void()> &f);
 }
 
 namespace {
@@ -35,6 +35,12 @@ template <class F> int guarded(F &&f)
         return BKD_EDEVICE;
     }
 }
+
+}  // namespace
+
+int bkd::guarded_call(const std::function<void()> &f) { return guarded(f); }
+
+namespace {
 
 void require(bool ok, const char *msg)
 {

@@ -1,0 +1,960 @@
+// batch.hip -- batched form: many independent instances in one persistent launch.
+//
+// Every instance runs the buffered search of Algorithm 1 in lock-step rounds
+// (Section 2.4).  One persistent kernel serves all instances from a device
+// task queue; a round of instance i is three phases of tasks:
+//   FIND(i, j0, j1)  FindLeafBatch for a slice of i's active queries, with the
+//                    buffer fills counted by per-leaf atomics;
+//   ORGANIZE(i)      one workgroup: buffer offsets, the list of buffered
+//                    leaves and the scatter of the queries into buffer order;
+//                    an instance whose queries have all finished is done;
+//   SCAN(i, e0, e1)  one wave per buffered leaf: the leaf's points sit in
+//                    registers (lanes over points) while the wave walks the
+//                    leaf's buffered queries; each query's k best keys are
+//                    spread over the lanes and merged with ballots.
+// The last task of a phase enqueues the next phase of the same instance.
+// Instances therefore advance independently; nothing waits for a global
+// round.  Tasks are published with release stores of a per-slot sequence word
+// and taken with acquire loads; every wait has a wall-clock guard that stops
+// the whole launch with an error flag instead of spinning forever.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <tuple>
+#include <memory>
+#include <numeric>
+
+#include "internal.h"
+#include "traverse.h"
+
+struct bkd_batch;
+
+namespace bkd {
+
+namespace {
+
+constexpr int BT = 256;
+constexpr int QCAP_LOG = 20;
+constexpr unsigned long long QCAP = 1ull << QCAP_LOG;
+constexpr int BATCH_MAX_LEAVES = 4096;  // height <= 12
+constexpr int TASK_FIND = 1;
+constexpr int TASK_ORGANIZE = 2;
+constexpr int TASK_SCAN = 3;
+constexpr int TASK_SOLO = 4;
+constexpr int FIND_CHUNK = 2048;  // active queries per FIND task
+
+struct BInst {
+    int32_t d, k, h, nleaf, m, n;
+    int64_t split_off, leaf_off_off, blk_off, pts_off, q_off, key_off, node_off, buf_off, tmp_off, loff_off, ne_off,
+        cnt_off;
+};
+
+struct BState {
+    int32_t round, V, E, pending;
+};
+
+struct BQueue {
+    unsigned long long head, tail;
+    int32_t done, error, active, pad;
+    unsigned long long tasks, pairs, flops, rounds;
+};
+
+struct BatchArgs {
+    const BInst *inst;
+    BState *state;
+    BQueue *q;
+    int4 *tasks;
+    unsigned long long *seq;
+    const float *split;
+    const int32_t *leaf_off;
+    const int32_t *blk;
+    const float *pts;
+    const float *Q;
+    uint64_t *keys;
+    int32_t *node;
+    int32_t *buf;
+    int32_t *tmp;
+    int32_t *loff;
+    int32_t *ne;
+    int32_t *cnt;
+    int32_t leaves_per_task;
+    int32_t solo_max;  // rounds with at most this many active queries run inside one workgroup
+    int32_t count;
+    unsigned long long spin_ticks;
+};
+
+__device__ inline unsigned long long ld_acq(unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_rel(unsigned long long *p, unsigned long long v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline int ld_flag(int32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+// Polling load: coherent at agent scope but without the cache invalidation of
+// an acquire (an acquire fence follows once the awaited value is seen), so
+// idle workgroups do not flush the L1 of busy ones on the same CU.
+__device__ inline unsigned long long ld_poll(unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline uint64_t rdlane64(uint64_t v, int lane)
+{
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Publish `count` tasks made by make(j); every thread of the workgroup calls it.
+template <class F> __device__ __forceinline__ void push_tasks(const BatchArgs &a, int count, F make, unsigned long long *lds_base)
+{
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) *lds_base = atomicAdd(&a.q->tail, (unsigned long long)count);
+    __syncthreads();
+    const unsigned long long base = *lds_base;
+    for (int j = threadIdx.x; j < count; j += BT) {
+        const unsigned long long idx = base + j;
+        const unsigned long long slot = idx & (QCAP - 1);
+        const unsigned long long fr = 2 * (idx >> QCAP_LOG);
+        const unsigned long long t0 = wall_clock64();
+        bool ok = true;
+        while (ld_poll(&a.seq[slot]) != fr) {  // slot still holds an older task (capacity exceeded)
+            if (wall_clock64() - t0 > a.spin_ticks || ld_flag(&a.q->error)) {
+                atomicOr(&a.q->error, 1);
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+        }
+        if (!ok) continue;
+        a.tasks[slot] = make(j);
+        st_rel(&a.seq[slot], fr + 1);
+    }
+    __syncthreads();
+}
+
+// Exclusive scan of lds[0..n) in place by one workgroup (segments of contiguous entries).
+__device__ __forceinline__ int32_t block_scan_lds(int32_t *lds, int n, int32_t *part)
+{
+    const int tid = threadIdx.x;
+    const int seg = (n + BT - 1) / BT;
+    const int lo = min(n, tid * seg), hi = min(n, lo + seg);
+    int32_t s = 0;
+    for (int i = lo; i < hi; i++) s += lds[i];
+    part[tid] = s;
+    __syncthreads();
+    for (int o = 1; o < BT; o <<= 1) {
+        int32_t add = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += add;
+        __syncthreads();
+    }
+    int32_t run = part[tid] - s;
+    const int32_t total = part[BT - 1];
+    for (int i = lo; i < hi; i++) {
+        int32_t x = lds[i];
+        lds[i] = run;
+        run += x;
+    }
+    __syncthreads();
+    return total;
+}
+
+struct RouteLds {
+    int32_t hist[BATCH_MAX_LEAVES];
+    int32_t cur[BATCH_MAX_LEAVES];
+    int32_t part[BT];
+    unsigned long long red[BT / 64];
+    unsigned long long base;
+    int32_t E;
+};
+
+// FindLeafBatch over active entries [j0, j1) of instance i's current round.
+__device__ __forceinline__ void find_task(const BatchArgs &a, int i, int j0, int j1)
+{
+    const BInst I = a.inst[i];
+    const int round = a.state[i].round;
+    const int32_t *inb = a.buf + I.buf_off + (int64_t)(round & 1) * I.m;
+    const float *split = a.split + I.split_off;
+    int32_t *tmp = a.tmp + I.tmp_off;
+    int32_t *node = a.node + I.node_off;
+    int32_t *cnt = a.cnt + I.cnt_off;
+    const uint64_t *keys = a.keys + I.key_off;
+    const float *Q = a.Q + I.q_off;
+    const int first = I.nleaf - 1;
+    for (int jb = j0; jb < j1; jb += BT) {
+        const int j = jb + (int)threadIdx.x;
+        int32_t lf = -1;
+        if (j < j1) {
+            const int32_t q = round == 0 ? j : inb[j];
+            const int32_t v =
+                next_leaf(node[q], Q + (int64_t)q * I.d, keys + (int64_t)q * I.k + (I.k - 1), split, I.h, I.d);
+            node[q] = v;
+            lf = v >= 0 ? v - first : -1;
+            tmp[j] = lf;
+        }
+        // one atomic per (wave, leaf): queries arrive grouped by their previous leaf
+        uint64_t todo = __ballot(lf >= 0);
+        while (todo) {
+            const int leader = __ffsll((unsigned long long)todo) - 1;
+            const int32_t ll = __builtin_amdgcn_readlane(lf, leader);
+            const uint64_t grp = __ballot(lf == ll);
+            if ((int)__lane_id() == leader) atomicAdd(&cnt[ll], (int32_t)__popcll(grp));
+            todo &= ~grp;
+        }
+    }
+}
+
+// Buffer offsets, buffered-leaf list and scatter of instance i's round.  The
+// buffer fills are in the global counters (pipeline) or already in L.hist
+// (solo round).  Returns the number of buffered queries V; an instance with
+// V = 0 is finished.  On V > 0 the instance state moves to the next round.
+__device__ __forceinline__ int organize_core(const BatchArgs &a, int i, RouteLds &L, bool fills_in_lds)
+{
+    const BInst I = a.inst[i];
+    BState *st = a.state + i;
+    const int tid = threadIdx.x;
+    const int round = st->round;
+    const int nleaf = I.nleaf;
+    const int A = round == 0 ? I.m : st->V;
+    const int32_t *inb = a.buf + I.buf_off + (int64_t)(round & 1) * I.m;
+    int32_t *outb = a.buf + I.buf_off + (int64_t)((round + 1) & 1) * I.m;
+    const int32_t *loffs = a.leaf_off + I.leaf_off_off;
+    const int32_t *tmp = a.tmp + I.tmp_off;
+    int32_t *cnt = a.cnt + I.cnt_off;
+    int32_t *loff = a.loff + I.loff_off;
+    int32_t *ne = a.ne + I.ne_off;
+
+    unsigned long long pr = 0;
+    for (int l = tid; l < nleaf; l += BT) {
+        int32_t c;
+        if (fills_in_lds) {
+            c = L.hist[l];
+        } else {
+            c = cnt[l];
+            cnt[l] = 0;
+        }
+        L.cur[l] = c;
+        pr += (unsigned long long)c * (unsigned)(loffs[l + 1] - loffs[l]);
+    }
+    for (int o = 32; o > 0; o >>= 1) pr += __shfl_xor(pr, o);
+    if ((tid & 63) == 0) L.red[tid >> 6] = pr;
+    __syncthreads();
+    const int32_t V = block_scan_lds(L.cur, nleaf, L.part);
+    for (int l = tid; l < nleaf; l += BT) loff[l] = L.cur[l];
+    if (tid == 0) loff[nleaf] = V;
+    // buffered leaves: positions by a scan of the "fill > 0" flags (each flag is re-derived
+    // from the offsets, which stay in L.cur)
+    for (int l = tid; l < nleaf; l += BT) L.hist[l] = ((l + 1 < nleaf ? L.cur[l + 1] : V) > L.cur[l]) ? 1 : 0;
+    __syncthreads();
+    const int32_t E = block_scan_lds(L.hist, nleaf, L.part);
+    for (int l = tid; l < nleaf; l += BT)
+        if ((l + 1 < nleaf ? L.cur[l + 1] : V) > L.cur[l]) ne[L.hist[l]] = l;
+    __syncthreads();
+    for (int j = tid; j < A; j += BT) {
+        const int32_t lf = tmp[j];
+        if (lf >= 0) outb[atomicAdd(&L.cur[lf], 1)] = round == 0 ? j : inb[j];
+    }
+    if (tid == 0) {
+        unsigned long long p = 0;
+        for (int w = 0; w < BT / 64; w++) p += L.red[w];
+        if (p) {
+            atomicAdd(&a.q->pairs, p);
+            atomicAdd(&a.q->flops, p * 3ull * (unsigned)I.d);
+        }
+        L.E = E;
+    }
+    __threadfence();
+    __syncthreads();
+    if (V == 0) {
+        if (tid == 0 && atomicSub(&a.q->active, 1) == 1)
+            __hip_atomic_store(&a.q->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        return 0;
+    }
+    if (tid == 0) {
+        st->V = V;
+        st->E = E;
+        st->round = round + 1;
+        atomicAdd(&a.q->rounds, 1ull);
+    }
+    __threadfence();
+    __syncthreads();
+    return V;
+}
+
+__device__ __forceinline__ void organize_task(const BatchArgs &a, int i, RouteLds &L)
+{
+    if (organize_core(a, i, L, false) == 0) return;
+    const int E = L.E;
+    const int lpt = a.leaves_per_task;
+    const int T = (E + lpt - 1) / lpt;
+    if (threadIdx.x == 0) a.state[i].pending = T;
+    push_tasks(a, T, [&](int j) { return make_int4(TASK_SCAN, i, j * lpt, min(E, (j + 1) * lpt)); }, &L.base);
+}
+
+__device__ __forceinline__ void scan_task(const BatchArgs &a, int i, int e0, int e1);
+
+// Whole rounds of a small instance inside one workgroup: FindLeafBatch with the
+// fills counted in LDS, buffer organisation, and the scan of every buffered
+// leaf (one wave per leaf), until the instance is finished.
+__device__ __forceinline__ void solo_task(const BatchArgs &a, int i, RouteLds &L)
+{
+    const BInst I = a.inst[i];
+    BState *st = a.state + i;
+    const int tid = threadIdx.x;
+    const int first = I.nleaf - 1;
+    const float *split = a.split + I.split_off;
+    int32_t *tmp = a.tmp + I.tmp_off;
+    int32_t *node = a.node + I.node_off;
+    const uint64_t *keys = a.keys + I.key_off;
+    const float *Q = a.Q + I.q_off;
+    for (;;) {
+        const int round = st->round;
+        const int A = round == 0 ? I.m : st->V;
+        const int32_t *inb = a.buf + I.buf_off + (int64_t)(round & 1) * I.m;
+        for (int l = tid; l < I.nleaf; l += BT) L.hist[l] = 0;
+        __syncthreads();
+        for (int j = tid; j < A; j += BT) {
+            const int32_t q = round == 0 ? j : inb[j];
+            const int32_t v =
+                next_leaf(node[q], Q + (int64_t)q * I.d, keys + (int64_t)q * I.k + (I.k - 1), split, I.h, I.d);
+            node[q] = v;
+            const int32_t lf = v >= 0 ? v - first : -1;
+            tmp[j] = lf;
+            if (lf >= 0) atomicAdd(&L.hist[lf], 1);
+        }
+        __threadfence();
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // other waves' tmp[] writes
+        if (organize_core(a, i, L, true) == 0) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        scan_task(a, i, 0, L.E);
+        __threadfence();
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+}
+
+// One wave per buffered leaf; G groups of 64 points per pass held in registers.
+template <int D, int G> __device__ __forceinline__ void scan_leaves(const BatchArgs &a, int i, int e0, int e1)
+{
+    const BInst I = a.inst[i];
+    const int round = a.state[i].round;
+    const int32_t *buf = a.buf + I.buf_off + (int64_t)(round & 1) * I.m;
+    const int32_t *loff = a.loff + I.loff_off;
+    const int32_t *ne = a.ne + I.ne_off;
+    const int32_t *lo_pos = a.leaf_off + I.leaf_off_off;
+    const int32_t *blk = a.blk + I.blk_off;
+    const float *pts = a.pts + I.pts_off;
+    const float *Q = a.Q + I.q_off;
+    uint64_t *keys = a.keys + I.key_off;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int d = I.d, k = I.k;
+    for (int e = e0 + wave; e < e1; e += BT / 64) {
+        const int Lf = __builtin_amdgcn_readfirstlane(ne[e]);
+        const int qs = loff[Lf], qe = loff[Lf + 1];
+        const int len = lo_pos[Lf + 1] - lo_pos[Lf];
+        const float *X = pts + blk[Lf];
+        const int32_t *orig = reinterpret_cast<const int32_t *>(X) + (int64_t)d * len;
+        for (int gb = 0; gb < len; gb += 64 * G) {
+            float x[G][D];
+            uint32_t o[G];
+            bool v[G];
+#pragma unroll
+            for (int g = 0; g < G; g++) {
+                const int p = gb + 64 * g + lane;
+                v[g] = p < len;
+#pragma unroll
+                for (int j = 0; j < D; j++) x[g][j] = (v[g] && j < d) ? X[j * len + p] : 0.0f;
+                o[g] = v[g] ? (uint32_t)orig[p] : 0u;
+            }
+            for (int jq = qs; jq < qe; jq++) {
+                const int32_t q = __builtin_amdgcn_readfirstlane(buf[jq]);
+                const float *qp = Q + (int64_t)q * d;
+                float acc[G];
+#pragma unroll
+                for (int g = 0; g < G; g++) acc[g] = 0.0f;
+#pragma unroll
+                for (int j = 0; j < D; j++) {
+                    const float qj = j < d ? qp[j] : 0.0f;
+#pragma unroll
+                    for (int g = 0; g < G; g++) {
+                        const float t = qj - x[g][j];
+                        acc[g] = fmaf(t, t, acc[g]);
+                    }
+                }
+                uint64_t *kp = keys + (int64_t)q * k;
+                uint64_t li = lane < k ? kp[lane] : ~0ull;
+                uint64_t kth = rdlane64(li, k - 1);
+                bool dirty = false;
+#pragma unroll
+                for (int g = 0; g < G; g++) {
+                    const uint64_t key = v[g] ? (((uint64_t)__float_as_uint(acc[g]) << 32) | o[g]) : ~0ull;
+                    uint64_t cand = __ballot(key < kth);
+                    while (cand) {
+                        const int c = __ffsll((unsigned long long)cand) - 1;
+                        cand &= cand - 1;
+                        const uint64_t ck = rdlane64(key, c);
+                        if (ck < kth) {
+                            const uint64_t moved = __ballot(li > ck);
+                            const int pos = __ffsll((unsigned long long)moved) - 1;
+                            const uint64_t up = __shfl_up(li, 1);
+                            li = (lane < pos) ? li : (lane == pos ? ck : up);
+                            if (lane >= k) li = ~0ull;
+                            kth = rdlane64(li, k - 1);
+                            dirty = true;
+                        }
+                    }
+                }
+                if (dirty && lane < k) kp[lane] = li;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void scan_task(const BatchArgs &a, int i, int e0, int e1)
+{
+    switch (a.inst[i].d <= 2 ? 2 : a.inst[i].d <= 3 ? 3 : a.inst[i].d <= 4 ? 4 : a.inst[i].d <= 5 ? 5
+            : a.inst[i].d <= 6 ? 6 : a.inst[i].d <= 8 ? 8 : a.inst[i].d <= 10 ? 10 : a.inst[i].d <= 12 ? 12
+            : a.inst[i].d <= 15 ? 15 : a.inst[i].d <= 16 ? 16 : a.inst[i].d <= 20 ? 20 : a.inst[i].d <= 24 ? 24 : 32) {
+    case 2: scan_leaves<2, 2>(a, i, e0, e1); break;
+    case 3: scan_leaves<3, 2>(a, i, e0, e1); break;
+    case 4: scan_leaves<4, 2>(a, i, e0, e1); break;
+    case 5: scan_leaves<5, 2>(a, i, e0, e1); break;
+    case 6: scan_leaves<6, 2>(a, i, e0, e1); break;
+    case 8: scan_leaves<8, 2>(a, i, e0, e1); break;
+    case 10: scan_leaves<10, 2>(a, i, e0, e1); break;
+    case 12: scan_leaves<12, 2>(a, i, e0, e1); break;
+    case 15: scan_leaves<15, 2>(a, i, e0, e1); break;
+    case 16: scan_leaves<16, 2>(a, i, e0, e1); break;
+    case 20: scan_leaves<20, 1>(a, i, e0, e1); break;
+    case 24: scan_leaves<24, 1>(a, i, e0, e1); break;
+    default: scan_leaves<32, 1>(a, i, e0, e1); break;
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_batch(BatchArgs a)
+{
+    __shared__ RouteLds L;
+    __shared__ int4 task;
+    __shared__ int quit;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) {
+            quit = 0;
+            const unsigned long long idx = atomicAdd(&a.q->head, 1ull);
+            const unsigned long long slot = idx & (QCAP - 1);
+            const unsigned long long want = 2 * (idx >> QCAP_LOG) + 1;
+            const unsigned long long t0 = wall_clock64();
+            while (ld_poll(&a.seq[slot]) != want) {
+                if (ld_flag(&a.q->done) || ld_flag(&a.q->error)) {
+                    quit = 1;
+                    break;
+                }
+                if (wall_clock64() - t0 > a.spin_ticks) {
+                    atomicOr(&a.q->error, 2);
+                    quit = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+            if (!quit) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                task = a.tasks[slot];
+                st_rel(&a.seq[slot], want + 1);
+                atomicAdd(&a.q->tasks, 1ull);
+            }
+        }
+        __syncthreads();
+        if (quit) break;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int4 t = task;
+        __syncthreads();
+        if (t.x == TASK_ORGANIZE) {
+            organize_task(a, t.y, L);
+        } else if (t.x == TASK_SOLO) {
+            solo_task(a, t.y, L);
+        } else {
+            if (t.x == TASK_FIND) find_task(a, t.y, t.z, t.w);
+            else scan_task(a, t.y, t.z, t.w);
+            // the last task of the phase starts the next phase of this instance
+            __threadfence();
+            __syncthreads();
+            if (tid == 0) quit = atomicSub(&a.state[t.y].pending, 1) == 1 ? 1 : 0;
+            __syncthreads();
+            if (quit) {
+                if (t.x == TASK_FIND) {
+                    push_tasks(a, 1, [&](int) { return make_int4(TASK_ORGANIZE, t.y, 0, 0); }, &L.base);
+                } else {
+                    const int V = a.state[t.y].V;
+                    if (V <= a.solo_max) {
+                        push_tasks(a, 1, [&](int) { return make_int4(TASK_SOLO, t.y, 0, 0); }, &L.base);
+                    } else {
+                        const int F = (V + FIND_CHUNK - 1) / FIND_CHUNK;
+                        if (tid == 0) a.state[t.y].pending = F;
+                        push_tasks(a, F, [&](int j) {
+                            return make_int4(TASK_FIND, t.y, j * FIND_CHUNK, min(V, (j + 1) * FIND_CHUNK));
+                        }, &L.base);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Reset: keys EMPTY, queries FRESH, queue empty, one ROUTE task per instance with queries.
+__global__ void k_batch_reset_u64(unsigned long long *p, unsigned long long v, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_batch_reset_i32(int32_t *p, int32_t v, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_batch_seed(BatchArgs a, const int4 *seed, int nseed, int nlive)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < a.count) {
+        const int m = a.inst[j].m;
+        a.state[j] = BState{0, 0, 0, (m + FIND_CHUNK - 1) / FIND_CHUNK};
+    }
+    if (j < nseed) {
+        a.tasks[j] = seed[j];
+        a.seq[j] = 1;
+    }
+    if (j == 0) {
+        a.q->head = 0;
+        a.q->tail = (unsigned long long)nseed;
+        a.q->done = nlive == 0 ? 1 : 0;
+        a.q->error = 0;
+        a.q->active = nlive;
+        a.q->tasks = a.q->pairs = a.q->flops = a.q->rounds = 0;
+    }
+}
+__global__ void k_batch_finalize(const uint64_t *keys, int64_t count, int64_t *idx, float *dist, int squared)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = keys[i];
+        const float d2 = __uint_as_float((uint32_t)(key >> 32));
+        idx[i] = (int64_t)(uint32_t)key;
+        dist[i] = squared ? d2 : sqrtf(d2);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host side.
+
+struct Batch {
+    int device = 0;
+    int count = 0;
+    int flags = 0;
+    struct Graph {
+        hipGraphExec_t exec = nullptr;
+        DevBuf seed;
+    };
+    std::vector<bkd_instance> inst;
+    std::vector<BInst> desc;
+    std::vector<int32_t> live;
+    int64_t keys_total = 0;
+    DevBuf d_inst, d_state, d_q, d_tasks, d_seq, d_split, d_leaf_off, d_blk, d_pts, d_Q, d_keys, d_node, d_buf, d_tmp,
+        d_loff, d_ne, d_cnt, d_oidx, d_odist;
+    hipStream_t cap_stream = nullptr;
+    std::map<std::tuple<int, int, int>, std::unique_ptr<Graph>> graphs;
+    bkd_tuning tuned{};
+    bool have_tuned = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool ran = false;
+    int cus = 256;
+    unsigned long long spin_ticks = 0;
+    ~Batch()
+    {
+        for (auto &g : graphs) (void)hipGraphExecDestroy(g.second->exec);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+    }
+};
+
+static void batch_validate(const bkd_instance *in, int32_t count)
+{
+    if (!in || count < 0) fail(BKD_EINVAL, "instances must be a non-NULL array and count >= 0");
+    for (int i = 0; i < count; i++) {
+        const bkd_instance &x = in[i];
+        auto bad = [&](const char *what) { fail(BKD_EINVAL, "instance " + std::to_string(i) + ": " + what); };
+        if (!x.P || x.n < 1 || x.n > INT32_MAX) bad("P must be non-NULL with 1 <= n <= 2^31-1");
+        if (x.d < 1 || x.d > BKD_MAX_DIM) bad("d must be in [1, 32]");
+        if (x.height < 0 || x.height > 12 || (int64_t(1) << x.height) > x.n) bad("height must be in [0, 12] with 2^h <= n");
+        if (x.k < 1 || x.k > BKD_MAX_K || x.k > x.n) bad("k must be in [1, min(n, 64)]");
+        if (x.m < 0 || x.m > INT32_MAX) bad("m must be in [0, 2^31-1]");
+        if (x.m > 0 && (!x.Q || !x.out_idx || !x.out_dist)) bad("Q and outputs must be non-NULL");
+        for (int64_t j = 0; j < x.n * x.d; j++)
+            if (!std::isfinite(x.P[j])) bad("reference coordinates must be finite");
+        for (int64_t j = 0; j < x.m * x.d; j++)
+            if (!std::isfinite(x.Q[j])) bad("query coordinates must be finite");
+    }
+}
+
+template <class T> static void upload(DevBuf &b, const std::vector<T> &v)
+{
+    b.ensure(sizeof(T) * std::max<size_t>(1, v.size()));
+    if (!v.empty()) BKD_HIP(hipMemcpy(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+}
+
+Batch *batch_create(const bkd_instance *in, int32_t count, int32_t device, int32_t flags)
+{
+    batch_validate(in, count);
+    int ndev = 0;
+    BKD_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) fail(BKD_EINVAL, "device ordinal out of range");
+    BKD_HIP(hipSetDevice(device));
+    auto b = std::make_unique<Batch>();
+    b->device = device;
+    b->count = count;
+    b->flags = flags;
+    b->inst.assign(in, in + count);
+    // trees, built in parallel over instances
+    std::vector<HostTree> trees((size_t)count);
+    parallel_for(count, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; i++)
+            build_canonical(in[i].P, in[i].n, in[i].d, in[i].height, trees[(size_t)i], false);
+    });
+    b->desc.resize((size_t)count);
+    int64_t o_split = 0, o_lo = 0, o_blk = 0, o_pts = 0, o_q = 0, o_key = 0, o_m = 0, o_loff = 0, o_ne = 0, o_cnt = 0;
+    for (int i = 0; i < count; i++) {
+        const bkd_instance &x = in[i];
+        BInst &D = b->desc[(size_t)i];
+        const int nleaf = 1 << x.height;
+        D.d = x.d;
+        D.k = x.k;
+        D.h = x.height;
+        D.nleaf = nleaf;
+        D.m = (int32_t)x.m;
+        D.n = (int32_t)x.n;
+        D.split_off = o_split;
+        D.leaf_off_off = o_lo;
+        D.blk_off = o_blk;
+        D.pts_off = o_pts;
+        D.q_off = o_q;
+        D.key_off = o_key;
+        D.node_off = o_m;
+        D.buf_off = 2 * o_m;
+        D.tmp_off = o_m;
+        D.loff_off = o_loff;
+        D.ne_off = o_ne;
+        D.cnt_off = o_cnt;
+        o_cnt += nleaf;
+        o_split += nleaf - 1;
+        o_lo += nleaf + 1;
+        o_blk += nleaf + 1;
+        o_pts += (int64_t)(x.d + 1) * x.n;
+        o_q += x.m * x.d;
+        o_key += x.m * x.k;
+        o_m += x.m;
+        o_loff += nleaf + 1;
+        o_ne += nleaf;
+        if (x.m > 0) b->live.push_back(i);
+    }
+    b->keys_total = o_key;
+    std::vector<float> split((size_t)o_split), pts((size_t)o_pts), Q((size_t)o_q);
+    std::vector<int32_t> leaf_off((size_t)o_lo), blk((size_t)o_blk);
+    parallel_for(count, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; i++) {
+            const bkd_instance &x = in[i];
+            const BInst &D = b->desc[(size_t)i];
+            const HostTree &H = trees[(size_t)i];
+            std::copy(H.split.begin(), H.split.end(), split.begin() + D.split_off);
+            int32_t w = 0;
+            for (int l = 0; l <= D.nleaf; l++) {
+                leaf_off[(size_t)(D.leaf_off_off + l)] = (int32_t)H.leaf_off[(size_t)l];
+                blk[(size_t)(D.blk_off + l)] = w;
+                if (l < D.nleaf) w += (int32_t)((x.d + 1) * (H.leaf_off[(size_t)l + 1] - H.leaf_off[(size_t)l]));
+            }
+            for (int l = 0; l < D.nleaf; l++) {
+                const int64_t a0 = H.leaf_off[(size_t)l], len = H.leaf_off[(size_t)l + 1] - a0;
+                float *X = pts.data() + D.pts_off + blk[(size_t)(D.blk_off + l)];
+                int32_t *orig = reinterpret_cast<int32_t *>(X + (size_t)x.d * len);
+                for (int64_t p = 0; p < len; p++) {
+                    const int32_t o = H.perm[(size_t)(a0 + p)];
+                    for (int j = 0; j < x.d; j++) X[(size_t)j * len + p] = x.P[(int64_t)o * x.d + j];
+                    orig[p] = o;
+                }
+            }
+            if (x.m > 0) std::copy(x.Q, x.Q + x.m * x.d, Q.begin() + D.q_off);
+        }
+    });
+    upload(b->d_inst, b->desc);
+    upload(b->d_split, split);
+    upload(b->d_leaf_off, leaf_off);
+    upload(b->d_blk, blk);
+    upload(b->d_pts, pts);
+    upload(b->d_Q, Q);
+    b->d_state.ensure(sizeof(BState) * std::max(1, count));
+    b->d_q.ensure(sizeof(BQueue));
+    b->d_tasks.ensure(sizeof(int4) * QCAP);
+    b->d_seq.ensure(sizeof(unsigned long long) * QCAP);
+    b->d_keys.ensure(sizeof(uint64_t) * std::max<int64_t>(1, o_key));
+    b->d_node.ensure(sizeof(int32_t) * std::max<int64_t>(1, o_m));
+    b->d_buf.ensure(sizeof(int32_t) * std::max<int64_t>(1, 2 * o_m));
+    b->d_tmp.ensure(sizeof(int32_t) * std::max<int64_t>(1, o_m));
+    b->d_loff.ensure(sizeof(int32_t) * std::max<int64_t>(1, o_loff));
+    b->d_ne.ensure(sizeof(int32_t) * std::max<int64_t>(1, o_ne));
+    b->d_cnt.ensure(sizeof(int32_t) * std::max<int64_t>(1, o_cnt));
+    b->d_oidx.ensure(sizeof(int64_t) * std::max<int64_t>(1, o_key));
+    b->d_odist.ensure(sizeof(float) * std::max<int64_t>(1, o_key));
+    BKD_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    BKD_HIP(hipEventCreate(&b->ev0));
+    BKD_HIP(hipEventCreate(&b->ev1));
+    hipDeviceProp_t prop;
+    BKD_HIP(hipGetDeviceProperties(&prop, device));
+    b->cus = prop.multiProcessorCount;
+    int rate_khz = 0;
+    BKD_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device));
+    b->spin_ticks = (unsigned long long)std::max(rate_khz, 1) * 1000ull * 60ull;  // 60 s guard
+    BKD_HIP(hipDeviceSynchronize());
+    return b.release();
+}
+
+static BatchArgs batch_args(Batch &b, const bkd_tuning &tu)
+{
+    BatchArgs a{};
+    a.inst = b.d_inst.as<BInst>();
+    a.state = b.d_state.as<BState>();
+    a.q = b.d_q.as<BQueue>();
+    a.tasks = b.d_tasks.as<int4>();
+    a.seq = b.d_seq.as<unsigned long long>();
+    a.split = b.d_split.as<float>();
+    a.leaf_off = b.d_leaf_off.as<int32_t>();
+    a.blk = b.d_blk.as<int32_t>();
+    a.pts = b.d_pts.as<float>();
+    a.Q = b.d_Q.as<float>();
+    a.keys = b.d_keys.as<uint64_t>();
+    a.node = b.d_node.as<int32_t>();
+    a.buf = b.d_buf.as<int32_t>();
+    a.tmp = b.d_tmp.as<int32_t>();
+    a.loff = b.d_loff.as<int32_t>();
+    a.ne = b.d_ne.as<int32_t>();
+    a.cnt = b.d_cnt.as<int32_t>();
+    a.leaves_per_task = tu.leaves_per_task;
+    a.solo_max = tu.solo_max;
+    a.count = b.count;
+    a.spin_ticks = b.spin_ticks;
+    return a;
+}
+
+static bkd_tuning normalise(const bkd_tuning *t)
+{
+    bkd_tuning u{8, 4, 2048};
+    if (t) {
+        if (t->leaves_per_task) u.leaves_per_task = t->leaves_per_task;
+        if (t->groups_per_cu) u.groups_per_cu = t->groups_per_cu;
+        if (t->solo_max) u.solo_max = t->solo_max;
+    }
+    if (u.leaves_per_task < 1 || u.leaves_per_task > 256) fail(BKD_EINVAL, "leaves_per_task must be in [1, 256]");
+    if (u.groups_per_cu < 1 || u.groups_per_cu > 16) fail(BKD_EINVAL, "groups_per_cu must be in [1, 16]");
+    if (u.solo_max < 0) fail(BKD_EINVAL, "solo_max must be >= 0");
+    return u;
+}
+
+void batch_run(Batch &b, const bkd_tuning *tune, hipStream_t s)
+{
+    BKD_HIP(hipSetDevice(b.device));
+    const bkd_tuning tu = normalise(tune ? tune : (b.have_tuned ? &b.tuned : nullptr));
+    const auto key = std::make_tuple(tu.leaves_per_task, tu.groups_per_cu, tu.solo_max);
+    auto it = b.graphs.find(key);
+    if (it == b.graphs.end()) {
+        auto G = std::make_unique<Batch::Graph>();
+        // first tasks: whole-instance solo rounds for small instances, FIND slices otherwise
+        std::vector<int4> seed;
+        for (int i : b.live) {
+            const int64_t m = b.inst[(size_t)i].m;
+            if (m <= tu.solo_max) {
+                seed.push_back(make_int4(TASK_SOLO, i, 0, 0));
+            } else {
+                for (int64_t j0 = 0; j0 < m; j0 += FIND_CHUNK)
+                    seed.push_back(make_int4(TASK_FIND, i, (int)j0, (int)std::min<int64_t>(m, j0 + FIND_CHUNK)));
+            }
+        }
+        if ((unsigned long long)seed.size() >= QCAP) fail(BKD_EINVAL, "too many queries for one batched launch");
+        upload(G->seed, seed);
+        // capture: reset state, persistent kernel, key -> (index, distance)
+        const BatchArgs a = batch_args(b, tu);
+        hipStream_t c = b.cap_stream;
+        BKD_HIP(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
+        k_batch_reset_u64<<<1024, 256, 0, c>>>(b.d_keys.as<unsigned long long>(), EMPTY_KEY, b.keys_total);
+        k_batch_reset_i32<<<1024, 256, 0, c>>>(b.d_node.as<int32_t>(), NODE_FRESH,
+                                                (int64_t)(b.d_node.bytes / sizeof(int32_t)));
+        k_batch_reset_i32<<<256, 256, 0, c>>>(b.d_cnt.as<int32_t>(), 0, (int64_t)(b.d_cnt.bytes / sizeof(int32_t)));
+        k_batch_reset_u64<<<1024, 256, 0, c>>>(b.d_seq.as<unsigned long long>(), 0ull, (int64_t)QCAP);
+        const int nseed = (int)seed.size(), nlive = (int)b.live.size();
+        k_batch_seed<<<(std::max(b.count, nseed) + 255) / 256 + 1, 256, 0, c>>>(a, G->seed.as<int4>(), nseed, nlive);
+        k_batch<<<b.cus * tu.groups_per_cu, BT, 0, c>>>(a);
+        k_batch_finalize<<<1024, 256, 0, c>>>(b.d_keys.as<uint64_t>(), b.keys_total, b.d_oidx.as<int64_t>(),
+                                              b.d_odist.as<float>(), (b.flags & BKD_FLAG_SQUARED) ? 1 : 0);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c, &g);
+        if (e != hipSuccess) fail(BKD_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) fail(BKD_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        it = b.graphs.emplace(key, std::move(G)).first;
+    }
+    BKD_HIP(hipEventRecord(b.ev0, s));
+    BKD_HIP(hipGraphLaunch(it->second->exec, s));
+    BKD_HIP(hipEventRecord(b.ev1, s));
+    b.last_stream = s;
+    b.ran = true;
+}
+
+static BQueue read_queue(Batch &b)
+{
+    BKD_HIP(hipStreamSynchronize(b.last_stream));
+    BQueue q;
+    BKD_HIP(hipMemcpy(&q, b.d_q.p, sizeof(BQueue), hipMemcpyDeviceToHost));
+    return q;
+}
+
+void batch_results(Batch &b)
+{
+    if (!b.ran) fail(BKD_EINVAL, "bkd_batch_run has not been called");
+    BQueue q = read_queue(b);
+    if (q.error) fail(BKD_EDEVICE, "batched launch stopped early (error flag " + std::to_string(q.error) + ")");
+    std::vector<int64_t> idx((size_t)b.keys_total);
+    std::vector<float> dist((size_t)b.keys_total);
+    if (b.keys_total) {
+        BKD_HIP(hipMemcpy(idx.data(), b.d_oidx.p, sizeof(int64_t) * idx.size(), hipMemcpyDeviceToHost));
+        BKD_HIP(hipMemcpy(dist.data(), b.d_odist.p, sizeof(float) * dist.size(), hipMemcpyDeviceToHost));
+    }
+    for (int i = 0; i < b.count; i++) {
+        const bkd_instance &x = b.inst[(size_t)i];
+        const int64_t o = b.desc[(size_t)i].key_off, c = x.m * x.k;
+        if (c) {
+            std::memcpy(x.out_idx, idx.data() + o, sizeof(int64_t) * c);
+            std::memcpy(x.out_dist, dist.data() + o, sizeof(float) * c);
+        }
+    }
+}
+
+void batch_stats(Batch &b, bkd_batch_stats *out)
+{
+    *out = bkd_batch_stats{};
+    out->instances = b.count;
+    for (auto &x : b.inst) out->queries += x.m;
+    if (!b.ran) return;
+    BQueue q = read_queue(b);
+    out->tasks = (int64_t)q.tasks;
+    out->rounds = (int64_t)q.rounds;
+    out->pairs = (int64_t)q.pairs;
+    out->flops = (int64_t)q.flops;
+    out->error = q.error;
+    float ms = 0;
+    BKD_HIP(hipEventElapsedTime(&ms, b.ev0, b.ev1));
+    out->run_ms = ms;
+}
+
+void batch_autotune(Batch &b, bkd_tuning *best, double *best_ms)
+{
+    const int lpts[] = {4, 16, 64};
+    const int gpcs[] = {2, 4};
+    const int solos[] = {512, 2048, 8192};
+    hipStream_t s = b.cap_stream;
+    double bm = 1e300;
+    bkd_tuning bt{8, 4, 2048};
+    for (int g : gpcs)
+        for (int l : lpts)
+            for (int so : solos) {
+            bkd_tuning t{l, g, so};
+            batch_run(b, &t, s);  // warm-up (first run also captures the graph)
+            batch_run(b, &t, s);
+            BQueue q = read_queue(b);
+            if (q.error) fail(BKD_EDEVICE, "batched launch stopped early during tuning");
+            float ms = 0;
+            BKD_HIP(hipEventElapsedTime(&ms, b.ev0, b.ev1));
+            if (ms < bm) {
+                bm = ms;
+                bt = t;
+            }
+        }
+    b.tuned = bt;
+    b.have_tuned = true;
+    if (best) *best = bt;
+    if (best_ms) *best_ms = bm;
+}
+
+}  // namespace bkd
+
+struct bkd_batch {
+    bkd::Batch *b;
+};
+
+namespace bkd {
+int guarded_call(const std::function<void()> &f);
+}
+
+extern "C" {
+
+int bkd_batch_create(const bkd_instance *inst, int32_t count, int32_t device, int32_t flags, bkd_batch **out)
+{
+    return bkd::guarded_call([&] {
+        if (!out) bkd::fail(BKD_EINVAL, "out is NULL");
+        *out = nullptr;
+        std::unique_ptr<bkd::Batch> b(bkd::batch_create(inst, count, device, flags));
+        *out = new bkd_batch{b.release()};
+    });
+}
+
+int bkd_batch_run(bkd_batch *batch, const bkd_tuning *tune, void *stream)
+{
+    return bkd::guarded_call([&] {
+        if (!batch) bkd::fail(BKD_EINVAL, "batch is NULL");
+        bkd::batch_run(*batch->b, tune, static_cast<hipStream_t>(stream));
+    });
+}
+
+int bkd_batch_results(bkd_batch *batch)
+{
+    return bkd::guarded_call([&] {
+        if (!batch) bkd::fail(BKD_EINVAL, "batch is NULL");
+        bkd::batch_results(*batch->b);
+    });
+}
+
+int bkd_batch_autotune(bkd_batch *batch, bkd_tuning *best, double *best_ms)
+{
+    return bkd::guarded_call([&] {
+        if (!batch) bkd::fail(BKD_EINVAL, "batch is NULL");
+        bkd::batch_autotune(*batch->b, best, best_ms);
+    });
+}
+
+int bkd_batch_stats_get(const bkd_batch *batch, bkd_batch_stats *out)
+{
+    return bkd::guarded_call([&] {
+        if (!batch || !out) bkd::fail(BKD_EINVAL, "NULL pointer");
+        bkd::batch_stats(*batch->b, out);
+    });
+}
+
+int bkd_batch_free(bkd_batch *batch)
+{
+    return bkd::guarded_call([&] {
+        if (!batch) return;
+        (void)hipSetDevice(batch->b->device);
+        (void)hipDeviceSynchronize();
+        delete batch->b;
+        delete batch;
+    });
+}
+
+}  // extern "C"

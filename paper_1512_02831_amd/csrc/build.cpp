@@ -22,7 +22,7 @@ struct VI {
 inline bool vi_less(const VI &a, const VI &b) { return a.v < b.v || (!(b.v < a.v) && a.i < b.i); }
 }  // namespace
 
-void build_canonical(const float *P, int64_t n, int d, int h, HostTree &t)
+void build_canonical(const float *P, int64_t n, int d, int h, HostTree &t, bool parallel)
 {
     const int64_t nleaf = int64_t(1) << h;
     const int64_t nnodes = 2 * nleaf - 1;
@@ -56,7 +56,7 @@ void build_canonical(const float *P, int64_t n, int d, int h, HostTree &t)
             lo[2 * v + 2] = a + c / 2;
             hi[2 * v + 2] = a + c;
         };
-        if (count >= 4) {
+        if (parallel && count >= 4) {
             parallel_for(count, [&](int64_t b, int64_t e) {
                 for (int64_t x = b; x < e; x++) split_node(first + x);
             });
@@ -64,12 +64,14 @@ void build_canonical(const float *P, int64_t n, int d, int h, HostTree &t)
             for (int64_t x = 0; x < count; x++) split_node(first + x);
         }
     }
-    parallel_for(nleaf, [&](int64_t b, int64_t e) {
+    auto sort_leaves = [&](int64_t b, int64_t e) {
         for (int64_t x = b; x < e; x++) {
             int64_t v = nleaf - 1 + x;
             std::sort(perm + lo[v], perm + hi[v]);
         }
-    });
+    };
+    if (parallel) parallel_for(nleaf, sort_leaves);
+    else sort_leaves(0, nleaf);
     for (int64_t x = 0; x < nleaf; x++) t.leaf_off[(size_t)x] = lo[nleaf - 1 + x];
     t.leaf_off[(size_t)nleaf] = n;
 }

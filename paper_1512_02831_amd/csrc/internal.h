@@ -71,8 +71,8 @@ struct HostTree {
     std::vector<int32_t> perm;     // n
 };
 
-// Build the canonical tree of P (row-major n x d).
-void build_canonical(const float *P, int64_t n, int d, int h, HostTree &t);
+// Build the canonical tree of P (row-major n x d); parallel = use the host thread pool.
+void build_canonical(const float *P, int64_t n, int d, int h, HostTree &t, bool parallel = true);
 
 // Leaf-block layout of the leaf structure: leaf l occupies 4-byte words
 // [blk[l], blk[l+1]): d rows of len_l float32 coordinates (row j holds
@@ -149,6 +149,12 @@ struct FetchSpec {
     const int32_t *ring;  // reinsert ring
     int64_t ring_head, ring_count, ring_cap;
     int64_t in_start, in_count;  // input queue part: queries in_start .. in_start + in_count - 1
+    const int32_t *in_list = nullptr;  // if set, the input part holds in_list[in_start ..] instead
+    // served form: per-query k, owning request, outstanding-query counters and the completion list
+    const int32_t *kq = nullptr;
+    const int32_t *req_of = nullptr;
+    int32_t *req_left = nullptr;
+    int32_t *done_list = nullptr;  // done_list[0] = count, then request table indices
 };
 
 void launch_init_state(int32_t *node, uint64_t *keys, int64_t m, int K, hipStream_t s);
@@ -197,6 +203,13 @@ int key_capacity(int k);
 // Host driver (query.cpp).
 
 void tree_build(Tree &t, const float *P, int64_t n, int d, int h, const bkd_options &opt);
+int guarded_call(const std::function<void()> &f);
 void tree_query_device(Tree &t, const float *dQ, int64_t m, int k, int64_t *d_idx, float *d_dist, hipStream_t s);
 
 }  // namespace bkd
+
+// The ABI's tree handle.
+struct bkd_tree {
+    bkd::Tree t;
+    hipStream_t stream = nullptr;  // stream of the host-pointer entry point
+};

@@ -11,14 +11,12 @@
 #include <climits>
 
 #include "internal.h"
+#include "traverse.h"
 
 namespace bkd {
 
 namespace {
 
-constexpr int32_t NODE_FRESH = -2;
-constexpr int32_t NODE_DONE = -1;
-constexpr uint64_t EMPTY_KEY = 0x7F800000FFFFFFFFull;
 
 inline unsigned grid_for(int64_t count, int threads) { return (unsigned)((count + threads - 1) / threads); }
 
@@ -48,23 +46,6 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t count)
     if (i < count) p[i] = v;
 }
 
-// Descend from heap node v at the given level to a leaf: left iff q[dim] < split.
-__device__ inline int32_t descend(const float *q, const float *split, int32_t v, int level, int h, int d)
-{
-    int dim = level % d;
-    while (level < h) {
-        v = (q[dim] < split[v]) ? 2 * v + 1 : 2 * v + 2;
-        level++;
-        dim = (dim + 1 == d) ? 0 : dim + 1;
-    }
-    return v;
-}
-
-// FindLeafBatch over one fetch.  State per query: FRESH, DONE or the heap
-// index of the last leaf visited.  After a visit the walk goes back up; at
-// a parent reached from its near child the far child is entered when the
-// float32 plane term (q[dim]-s)^2 does not exceed the current k-th squared
-// distance; reaching the root from above ends the traversal.
 __global__ __launch_bounds__(256) void k_find_leaf(FetchSpec f, const float *__restrict__ Q, int d,
                                                    int32_t *__restrict__ node, const uint64_t *__restrict__ keys,
                                                    int K, int k, const float *__restrict__ split, int h,
@@ -80,37 +61,20 @@ __global__ __launch_bounds__(256) void k_find_leaf(FetchSpec f, const float *__r
     bool valid = false;
     uint32_t leaf = nleaf;
     if (j < total) {
-        int32_t q = (j < f.ring_count) ? f.ring[(f.ring_head + j) % f.ring_cap]
-                                       : (int32_t)(f.in_start + (j - f.ring_count));
+        int32_t q;
+        if (j < f.ring_count) q = f.ring[(f.ring_head + j) % f.ring_cap];
+        else if (f.in_list) q = f.in_list[f.in_start + (j - f.ring_count)];
+        else q = (int32_t)(f.in_start + (j - f.ring_count));
         const float *qp = Q + (int64_t)q * d;
-        int32_t st = node[q];
-        int32_t v = NODE_DONE;
-        if (st == NODE_FRESH) {
-            v = descend(qp, split, 0, 0, h, d);
-        } else if (st != NODE_DONE) {
-            const float kth = __uint_as_float((uint32_t)(keys[(int64_t)q * K + (k - 1)] >> 32));
-            int32_t u = st;
-            int level = h;
-            while (u != 0) {
-                int32_t p = (u - 1) >> 1;
-                level--;
-                int dim = level % d;
-                float s = split[p];
-                float qd = qp[dim];
-                int32_t nearc = (qd < s) ? 2 * p + 1 : 2 * p + 2;
-                if (u == nearc) {
-                    float t = qd - s;
-                    float h2 = t * t;
-                    if (h2 <= kth) {
-                        int32_t sib = (nearc == 2 * p + 1) ? 2 * p + 2 : 2 * p + 1;
-                        v = descend(qp, split, sib, level + 1, h, d);
-                        break;
-                    }
-                }
-                u = p;
-            }
-        }
+        const int kk = f.kq ? f.kq[q] : k;
+        const int32_t st = node[q];
+        const int32_t v = next_leaf(st, qp, keys + (int64_t)q * K + (kk - 1), split, h, d);
         node[q] = v;
+        if (f.req_left && v == NODE_DONE && st != NODE_DONE) {
+            // last query of its request: record the request as complete
+            const int32_t r = f.req_of[q];
+            if (atomicSub(&f.req_left[r], 1) == 1) f.done_list[1 + atomicAdd(&f.done_list[0], 1)] = r;
+        }
         leaf = (v >= 0) ? (uint32_t)(v - first) : nleaf;
         pend_leaf[pend_base + j] = leaf;
         pend_q[pend_base + j] = q;

@@ -1,0 +1,100 @@
+"""Served form: continuous batching over resident trees.  Every request's result equals
+the same query answered alone, whatever else is in flight; admission respects the slot
+budget; waiting requests can be cancelled."""
+from __future__ import annotations
+
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import datagen
+import paper_1512_02831_amd as bkd
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def trees():
+    PA, _ = datagen.mixture_pq(seed=31, n=40_000, m=1, d=10, comps=16)
+    PB, _ = datagen.mixture_pq(seed=32, n=12_000, m=1, d=15, comps=16)
+    return (PA, 7), (PB, 5)
+
+
+def test_requests_same_alone_and_in_the_mix():
+    say("case: 80 requests, two trees, mixed k, two submitting threads")
+    (PA, hA), (PB, hB) = trees()
+    ta = bkd.build(PA, hA, flags=bkd.FLAG_SQUARED)
+    tb = bkd.build(PB, hB, flags=bkd.FLAG_SQUARED)
+    rng = np.random.default_rng(5)
+    reqs = []
+    for i in range(80):
+        tree = int(rng.integers(0, 2))
+        m = int(np.floor(2 ** rng.uniform(0, 11.5)))
+        k = int(rng.choice([1, 10, 32]))
+        P = PA if tree == 0 else PB
+        comps = 16
+        _, Q = datagen.mixture_pq(seed=31 + tree, n=1, m=m, d=P.shape[1], comps=comps)
+        Q = Q + np.float32(rng.normal(0, 0.01))  # distinct queries per request
+        reqs.append((tree, Q.astype(np.float32), k))
+    with bkd.server_create(flags=bkd.FLAG_SQUARED) as srv:
+        ida = bkd.server_add_tree(srv, ta)
+        idb = bkd.server_add_tree(srv, tb)
+        handles = [None] * len(reqs)
+
+        def feed(part):
+            for i in part:
+                tree, Q, k = reqs[i]
+                handles[i] = bkd.submit(srv, ida if tree == 0 else idb, Q, k)
+                time.sleep(0.001 * ((i * 7919) % 3))
+
+        th = [threading.Thread(target=feed, args=(range(j, len(reqs), 2),)) for j in range(2)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        for h in handles:
+            bkd.wait(srv, h, 60_000_000)
+            assert bkd.poll(srv, h) == bkd.REQ_DONE
+        for (tree, Q, k), h in zip(reqs, handles):
+            t = ta if tree == 0 else tb
+            idx, d2 = bkd.query(t, Q, k)
+            assert np.array_equal(idx, h.idx) and np.array_equal(d2, h.dist)
+            s, a, d = bkd.request_times(srv, h)
+            assert s <= a <= d
+    ta.free()
+    tb.free()
+
+
+def test_admission_by_slots_and_cancel():
+    say("case: slot budget and cancel")
+    (PA, hA), _ = trees()
+    ta = bkd.build(PA, hA)
+    _, Q = datagen.mixture_pq(seed=40, n=1, m=450, d=10, comps=16)
+    with bkd.server_create(slots_per_session=500) as srv:
+        tid = bkd.server_add_tree(srv, ta)
+        with pytest.raises(bkd.BkdError) as e:
+            bkd.submit(srv, tid, np.zeros((501, 10), np.float32), 10)
+        assert e.value.code == bkd.EBUSY
+        hs = [bkd.submit(srv, tid, Q, 10) for _ in range(6)]  # only one fits at a time
+        bkd.cancel(srv, hs[-1])
+        for h in hs[:-1]:
+            bkd.wait(srv, h, 60_000_000)
+        bkd.wait(srv, hs[-1], 60_000_000)
+        assert bkd.poll(srv, hs[-1]) == bkd.REQ_CANCELLED
+        ref, _ = bkd.query(ta, Q, 10)
+        for h in hs[:-1]:
+            assert np.array_equal(h.idx, ref)
+        times = [bkd.request_times(srv, h) for h in hs[:-1]]
+        for (s0, a0, d0), (s1, a1, d1) in zip(times, times[1:]):
+            assert a1 >= d0 - 1e-3  # admitted after the previous one released its slots
+        with pytest.raises(bkd.BkdError) as e:
+            bkd.submit(srv, 7, Q, 10)
+        assert e.value.code == bkd.ENOTFOUND
+    ta.free()
