@@ -277,6 +277,8 @@ def main():
     ap.add_argument("--seed", type=int, default=datagen.DEFAULT_SEED)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU baseline sample size in seconds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 256 MiB device-to-device copy (counter calibration for profiles)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -288,6 +290,12 @@ def main():
     import torch
     import paper_1512_02831_amd as bkd
 
+    if args.calibrate_copy:
+        src = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "batched":
         print(json.dumps(run_batched(args, torch, bkd)), flush=True)
         return

@@ -119,6 +119,7 @@ struct Tree {
     // leaf structure
     std::vector<int64_t> leaf_blk; // [nleaf+1] word offsets of the leaf blocks
     DevBuf d_leaf_blk;
+    DevBuf d_centers;              // [nleaf][d] float32: bounding-box midpoint of each leaf
     bool resident = true;
     bool sweep = false;            // streaming with the chunk-sweep schedule
     std::vector<Chunk> chunks;
@@ -134,6 +135,8 @@ struct Tree {
     DevBuf d_Q, d_outi, d_outd;
     DevBuf d_keys, d_node, d_ring, d_pleaf, d_pq, d_tleaf, d_tq, d_hist;
     DevBuf d_cnt, d_off, d_tiles, d_ctl;
+    DevBuf d_chunk_of, d_rleaf, d_rq, d_rcnt;  // chunk sweep: leaf -> chunk, per-chunk pending regions
+    PinnedBuf h_rcnt;
     PinnedBuf h_ctl, h_tiles;  // h_tiles: dense tiles, sparse items, buffer offsets (3 x (nleaf+1))
 
     // results of the last query
@@ -168,7 +171,12 @@ int launch_sort_pairs(uint32_t *key_a, int32_t *val_a, uint32_t *key_b, int32_t 
 size_t sort_hist_words(int64_t count);
 // tiles: [2][nleaf+1] -- dense work-item offsets, then sparse (per buffered query) offsets.
 void launch_leaf_offsets(const int32_t *cnt, const int32_t *leaf_off, int nleaf, int qt, int dense_min, int32_t *off,
-                         int32_t *tiles, int32_t *ctl, hipStream_t s);
+                         int32_t *tiles, int32_t *sparse, int32_t *ctl, hipStream_t s);
+void launch_distribute(const uint32_t *leaf, const int32_t *q, int64_t n, int nleaf, const int32_t *chunk_of, int c,
+                       uint32_t *rleaf, int32_t *rq, int64_t rcap, int32_t *rcnt, uint32_t *sleaf, int32_t *sq,
+                       int nchunks, hipStream_t s);
+void launch_restore(const uint32_t *sleaf, const int32_t *sq, int64_t n, uint32_t *rleaf, int32_t *rq, int32_t *rcnt,
+                    int c, int nchunks, hipStream_t s);
 void launch_count_work(const int32_t *off, const int32_t *leaf_off, int lf, int ll, int dense_min, int32_t *ctl,
                        hipStream_t s);
 void launch_ring_append(int32_t *ring, int64_t cap, int64_t tail, const int32_t *src, int64_t count, hipStream_t s);
@@ -192,7 +200,12 @@ struct ScanArgs {
     const float *Q;           // [m][d]
     int d;
     uint64_t *keys;           // [m][K]
+    const float *centers;     // [nleaf][d] leaf centres of the inner-product filter
+    float filter_coef;        // 1 - c(d), c(d) the relative error band of the filter
 };
+
+// Relative error band c(d) of the dense scan's inner-product filter (see leaf_scan.h).
+float filter_band(int d);
 
 // Dispatch on padded dimension and key capacity; sparse = 0: dense items, 1: sparse items.
 void launch_leaf_scan(const ScanArgs &a, int K, int sparse, hipStream_t s);

@@ -245,10 +245,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const uint32_t *
 __global__ __launch_bounds__(1024) void k_leaf_offsets(const int32_t *__restrict__ cnt,
                                                        const int32_t *__restrict__ leaf_off, int nleaf, int qt,
                                                        int dense_min, int32_t *__restrict__ off,
-                                                       int32_t *__restrict__ tiles, int32_t *__restrict__ ctl)
+                                                       int32_t *__restrict__ tiles, int32_t *__restrict__ sparse,
+                                                       int32_t *__restrict__ ctl)
 {
     __shared__ long long lds[1024];
-    int32_t *sparse = tiles + nleaf + 1;
     const int tid = threadIdx.x;
     const int seg = (nleaf + 1023) / 1024;
     const int lo = min(nleaf, tid * seg), hi = min(nleaf, lo + seg);
@@ -305,6 +305,42 @@ __global__ __launch_bounds__(256) void k_count_work(const int32_t *__restrict__ 
         if (pd) atomicAdd((unsigned long long *)(ctl + CTL_DPAIRS_LO), (unsigned long long)pd);
         if (ps) atomicAdd((unsigned long long *)(ctl + CTL_SPAIRS_LO), (unsigned long long)ps);
     }
+}
+
+// Chunk sweep: route entries of the drained chunk c to the pending regions of
+// their next chunk; entries staying in c go to a side buffer, finished ones are dropped.
+__global__ void k_distribute(const uint32_t *__restrict__ leaf, const int32_t *__restrict__ q, int64_t n,
+                             uint32_t nleaf, const int32_t *__restrict__ chunk_of, int c, uint32_t *__restrict__ rleaf,
+                             int32_t *__restrict__ rq, int64_t rcap, int32_t *__restrict__ rcnt,
+                             uint32_t *__restrict__ sleaf, int32_t *__restrict__ sq, int nchunks)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t l = leaf[i];
+    if (l >= nleaf) return;
+    const int t = chunk_of[l];
+    if (t == c) {
+        const int32_t pos = atomicAdd(&rcnt[nchunks], 1);
+        sleaf[pos] = l;
+        sq[pos] = q[i];
+    } else {
+        const int32_t pos = atomicAdd(&rcnt[t], 1);
+        rleaf[(int64_t)t * rcap + pos] = l;
+        rq[(int64_t)t * rcap + pos] = q[i];
+    }
+}
+
+__global__ void k_restore(const uint32_t *__restrict__ sleaf, const int32_t *__restrict__ sq, int64_t n,
+                          uint32_t *__restrict__ rleaf, int32_t *__restrict__ rq, int32_t *__restrict__ rcnt, int c,
+                          int nchunks)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t stay = rcnt[nchunks];
+    if (i < stay) {
+        rleaf[i] = sleaf[i];
+        rq[i] = sq[i];
+    }
+    if (i == 0) rcnt[c] = stay;
 }
 
 __global__ void k_ring_append(int32_t *ring, int64_t cap, int64_t tail, const int32_t *src, int64_t count)
@@ -398,9 +434,9 @@ int launch_sort_pairs(uint32_t *key_a, int32_t *val_a, uint32_t *key_b, int32_t 
 }
 
 void launch_leaf_offsets(const int32_t *cnt, const int32_t *leaf_off, int nleaf, int qt, int dense_min, int32_t *off,
-                         int32_t *tiles, int32_t *ctl, hipStream_t s)
+                         int32_t *tiles, int32_t *sparse, int32_t *ctl, hipStream_t s)
 {
-    k_leaf_offsets<<<1, 1024, 0, s>>>(cnt, leaf_off, nleaf, qt, dense_min, off, tiles, ctl);
+    k_leaf_offsets<<<1, 1024, 0, s>>>(cnt, leaf_off, nleaf, qt, dense_min, off, tiles, sparse, ctl);
     check_launch();
 }
 
@@ -408,6 +444,23 @@ void launch_count_work(const int32_t *off, const int32_t *leaf_off, int lf, int 
                        hipStream_t s)
 {
     k_count_work<<<1, 256, 0, s>>>(off, leaf_off, lf, ll, dense_min, ctl);
+    check_launch();
+}
+
+void launch_distribute(const uint32_t *leaf, const int32_t *q, int64_t n, int nleaf, const int32_t *chunk_of, int c,
+                       uint32_t *rleaf, int32_t *rq, int64_t rcap, int32_t *rcnt, uint32_t *sleaf, int32_t *sq,
+                       int nchunks, hipStream_t s)
+{
+    if (n <= 0) return;
+    k_distribute<<<grid_for(n, 256), 256, 0, s>>>(leaf, q, n, (uint32_t)nleaf, chunk_of, c, rleaf, rq, rcap, rcnt, sleaf,
+                                                  sq, nchunks);
+    check_launch();
+}
+
+void launch_restore(const uint32_t *sleaf, const int32_t *sq, int64_t n, uint32_t *rleaf, int32_t *rq, int32_t *rcnt,
+                    int c, int nchunks, hipStream_t s)
+{
+    k_restore<<<grid_for(std::max<int64_t>(n, 1), 256), 256, 0, s>>>(sleaf, sq, n, rleaf, rq, rcnt, c, nchunks);
     check_launch();
 }
 

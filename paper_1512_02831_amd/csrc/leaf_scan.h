@@ -1,13 +1,26 @@
 // leaf_scan.h -- ProcessAllBuffers leaf scan (Section 2.4, Section 3.2), gfx950.
 //
 // Dense leaves (many buffered queries): one workgroup of 256 lanes takes one
-// work item, up to 256 buffered queries of one leaf, one query per lane.  The leaf's points (the part held by the
-// current chunk) stream through LDS in tiles of 256 points, stored point-major
-// with the coordinates padded to a multiple of four, so that every lane reads
-// the same point with a broadcast ds_read_b128.  Each lane keeps its query in
-// registers and its K best keys as a sorted register list; a point enters
-// through a compare-exchange cascade only when its key beats the K-th best
-// (a wave-uniform branch, skipped when no lane qualifies).
+// work item, up to 256 buffered queries of one leaf, one query per lane.  The
+// leaf's points (the part held by the current chunk) stream through LDS in
+// tiles, point-major with the coordinates padded to a multiple of four, so
+// that every lane reads the same point with a broadcast ds_read_b128.  Each
+// lane keeps its query in registers and its K best keys as a sorted register
+// list; a point enters through a compare-exchange cascade only when its key
+// beats the K-th best (a wave-uniform branch, skipped when no lane qualifies).
+//
+// Inner-product filter.  Once every query of a tile has K candidates, a point
+// is first tested with the expansion |q-x|^2 = |q'|^2 + |x'|^2 - 2<q',x'> on
+// coordinates relative to the leaf centre c (q' = q-c, x' = x-c, both rounded
+// to float32): d fused multiply-adds per pair instead of d subtractions and d
+// FMAs.  The test accepts every point whose exact float32 distance could reach
+// the K-th best thr: with S = |q'|^2 + |x'|^2, the computed expansion differs
+// from the float32 distance by at most (4d + 14) 2^-24 S (centring, the dot
+// product, the norms, the final combination and the float32 distance itself;
+// a borderline case has thr <= 2S, so the comparison's own rounding is of the
+// same order), and the test  (1 - c(d)) S - 2<q',x'> <= thr  uses c(d) = 4
+// times that bound.  Accepted points are re-checked with the exact float32
+// distance, so keys and results are bit-identical to the exact path.
 //
 // Squared distances follow the float32 reading: t = q_j - x_j rounded, then
 // acc = fma(t, t, acc) for j = 0..d-1 from +0.  Padding dimensions hold zero in
@@ -55,8 +68,11 @@ __device__ inline int xcd_item(int b, int grid)
 template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
 {
     constexpr int DS = (D + 3) & ~3;
-    __shared__ float4 xs[SCAN_PT * DS / 4];
-    __shared__ int32_t os[SCAN_PT];
+    constexpr int PT = D > 16 ? SCAN_PT / 2 : SCAN_PT;  // points per LDS tile
+    __shared__ float4 xs[PT * DS / 4];  // original coordinates, point-major
+    __shared__ float4 xc[PT * DS / 4];  // coordinates minus the leaf centre
+    __shared__ float bs[PT];            // (1 - c) |x - centre|^2 / 2
+    __shared__ int32_t os[PT];
 
     int item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= a.item_count) return;
@@ -78,48 +94,108 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
     const int64_t p1 = min(l0 + len, a.chunk_hi);
     const float *X = a.base + (a.blk[L] + a.blk_shift);
     const int32_t *orig = reinterpret_cast<const int32_t *>(X) + (int64_t)a.d * len;
+    const float *cen = a.centers + (int64_t)L * a.d;
+    const float coef = a.filter_coef;
 
     const int tid = threadIdx.x;
     const bool act = tid < qcnt;
     const bool wave_busy = (tid & ~63) < qcnt;
     const int32_t q = act ? a.bufq[qbase + tid] : 0;
-    float qv[D];
+    float qv[D], qc[D];
+    float Qn = 0.0f;
 #pragma unroll
-    for (int j = 0; j < D; j++) qv[j] = (act && j < a.d) ? a.Q[(int64_t)q * a.d + j] : 0.0f;
+    for (int j = 0; j < D; j++) {
+        qv[j] = (act && j < a.d) ? a.Q[(int64_t)q * a.d + j] : 0.0f;
+        qc[j] = (j < a.d) ? qv[j] - cen[j] : 0.0f;
+        Qn = fmaf(qc[j], qc[j], Qn);
+    }
     uint64_t lst[K];
 #pragma unroll
     for (int s = 0; s < K; s++) lst[s] = act ? a.keys[(int64_t)q * K + s] : 0ull;  // 0: nothing enters
+    float thr = __uint_as_float((uint32_t)(lst[K - 1] >> 32));
+    // A query whose list is not full yet (K-th key EMPTY) accepts every point; such
+    // tiles take the exact path, all others the inner-product filter.
+    const bool exact_path = __syncthreads_or(act && isinf(thr)) != 0;
+    float Aq = act ? 0.5f * (coef * Qn - thr) : INFINITY;
 
-    for (int64_t pt = p0; pt < p1; pt += SCAN_PT) {
-        const int np = (int)min((int64_t)SCAN_PT, p1 - pt);
+    for (int64_t pt = p0; pt < p1; pt += PT) {
+        const int np = (int)min((int64_t)PT, p1 - pt);
         __syncthreads();
-        if (tid < np) {
-            const int i = (int)(pt - l0) + tid;
-            float *row = reinterpret_cast<float *>(xs) + tid * DS;
+        for (int t = tid; t < np; t += SCAN_THREADS) {
+            const int i = (int)(pt - l0) + t;
+            float *ro = reinterpret_cast<float *>(xs) + t * DS;
+            float *rc = reinterpret_cast<float *>(xc) + t * DS;
+            float Xn = 0.0f;
 #pragma unroll
-            for (int j = 0; j < DS; j++) row[j] = (j < a.d) ? X[j * len + i] : 0.0f;
-            os[tid] = orig[i];
+            for (int j = 0; j < DS; j++) {
+                const float x = (j < a.d) ? X[j * len + i] : 0.0f;
+                const float c = (j < a.d) ? x - cen[j] : 0.0f;
+                ro[j] = x;
+                rc[j] = c;
+                Xn = fmaf(c, c, Xn);
+            }
+            bs[t] = 0.5f * (coef * Xn);
+            os[t] = orig[i];
         }
         __syncthreads();
         if (!wave_busy) continue;  // whole wave without queries: only helps staging
+        if (exact_path) {
 #pragma unroll 2
-        for (int i = 0; i < np; i++) {
-            const float4 *xp = xs + i * (DS / 4);
-            float acc = 0.0f;
+            for (int i = 0; i < np; i++) {
+                const float4 *xp = xs + i * (DS / 4);
+                float acc = 0.0f;
 #pragma unroll
-            for (int c = 0; c < DS / 4; c++) {
-                float4 x4 = xp[c];
-                float xe[4] = {x4.x, x4.y, x4.z, x4.w};
+                for (int c = 0; c < DS / 4; c++) {
+                    float4 x4 = xp[c];
+                    float xe[4] = {x4.x, x4.y, x4.z, x4.w};
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    if (4 * c + e < D) {
-                        float t = qv[4 * c + e] - xe[e];
-                        acc = fmaf(t, t, acc);
+                    for (int e = 0; e < 4; e++) {
+                        if (4 * c + e < D) {
+                            float t = qv[4 * c + e] - xe[e];
+                            acc = fmaf(t, t, acc);
+                        }
+                    }
+                }
+                uint64_t key = ((uint64_t)__float_as_uint(acc) << 32) | (uint32_t)os[i];
+                if (key < lst[K - 1]) key_insert<K>(lst, key);
+            }
+        } else {
+#pragma unroll 4
+            for (int i = 0; i < np; i++) {
+                const float4 *cp = xc + i * (DS / 4);
+                float dot = 0.0f;
+#pragma unroll
+                for (int c = 0; c < DS / 4; c++) {
+                    float4 x4 = cp[c];
+                    float xe[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+                    for (int e = 0; e < 4; e++)
+                        if (4 * c + e < D) dot = fmaf(qc[4 * c + e], xe[e], dot);
+                }
+                if (Aq + bs[i] <= dot) {
+                    // inside the error band of the filter: decide with the exact float32 distance
+                    const float4 *xp = xs + i * (DS / 4);
+                    float acc = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < DS / 4; c++) {
+                        float4 x4 = xp[c];
+                        float xe[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+                        for (int e = 0; e < 4; e++) {
+                            if (4 * c + e < D) {
+                                float t = qv[4 * c + e] - xe[e];
+                                acc = fmaf(t, t, acc);
+                            }
+                        }
+                    }
+                    uint64_t key = ((uint64_t)__float_as_uint(acc) << 32) | (uint32_t)os[i];
+                    if (key < lst[K - 1]) {
+                        key_insert<K>(lst, key);
+                        thr = __uint_as_float((uint32_t)(lst[K - 1] >> 32));
+                        Aq = 0.5f * (coef * Qn - thr);
                     }
                 }
             }
-            uint64_t key = ((uint64_t)__float_as_uint(acc) << 32) | (uint32_t)os[i];
-            if (key < lst[K - 1]) key_insert<K>(lst, key);
         }
     }
     if (act) {

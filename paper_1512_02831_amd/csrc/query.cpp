@@ -172,6 +172,25 @@ void tree_build(Tree &t, const float *P, int64_t n, int d, int h, const bkd_opti
     BKD_HIP(hipMemcpy(t.d_leaf_off.p, lo32.data(), sizeof(int32_t) * lo32.size(), hipMemcpyHostToDevice));
     t.d_leaf_blk.ensure(sizeof(int64_t) * t.leaf_blk.size());
     BKD_HIP(hipMemcpy(t.d_leaf_blk.p, t.leaf_blk.data(), sizeof(int64_t) * t.leaf_blk.size(), hipMemcpyHostToDevice));
+    {
+        // leaf centres (bounding-box midpoints) for the inner-product filter of the dense scan
+        std::vector<float> cen((size_t)t.nleaf * d);
+        parallel_for(t.nleaf, [&](int64_t b, int64_t e) {
+            for (int64_t l = b; l < e; l++) {
+                for (int j = 0; j < d; j++) {
+                    float lo = INFINITY, hi = -INFINITY;
+                    for (int64_t p = H.leaf_off[(size_t)l]; p < H.leaf_off[(size_t)l + 1]; p++) {
+                        const float v = P[(int64_t)H.perm[(size_t)p] * d + j];
+                        lo = std::min(lo, v);
+                        hi = std::max(hi, v);
+                    }
+                    cen[(size_t)l * d + j] = 0.5f * lo + 0.5f * hi;
+                }
+            }
+        });
+        t.d_centers.ensure(sizeof(float) * cen.size());
+        BKD_HIP(hipMemcpy(t.d_centers.p, cen.data(), sizeof(float) * cen.size(), hipMemcpyHostToDevice));
+    }
 
     const size_t total_bytes = (size_t)t.leaf_blk.back() * 4;
     if (t.resident) {
@@ -193,6 +212,11 @@ void tree_build(Tree &t, const float *P, int64_t n, int d, int h, const bkd_opti
             BKD_HIP(hipEventRecord(t.ev_used[b], t.copy_stream));
         }
         t.chunk_in[0] = t.chunk_in[1] = -1;
+        std::vector<int32_t> chunk_of((size_t)t.nleaf, 0);
+        for (int j = 0; j < (int)t.chunks.size(); j++)
+            for (int l = t.chunks[(size_t)j].leaf_first; l <= t.chunks[(size_t)j].leaf_last; l++) chunk_of[(size_t)l] = j;
+        t.d_chunk_of.ensure(sizeof(int32_t) * chunk_of.size());
+        BKD_HIP(hipMemcpy(t.d_chunk_of.p, chunk_of.data(), sizeof(int32_t) * chunk_of.size(), hipMemcpyHostToDevice));
     }
     t.d_ctl.ensure(sizeof(int32_t) * CTL_WORDS);
     t.h_ctl.ensure(sizeof(int32_t) * CTL_WORDS);
@@ -250,6 +274,7 @@ struct Run {
     uint32_t *leafbuf[2];
     int32_t *qbuf[2];
     int cur = 0;  // pair holding the pending list
+    const int32_t *bufq_override = nullptr;  // scan input other than the pending pair (chunk sweep)
     Timer tdense, tsparse;
     std::vector<int32_t> tr_q, tr_l;
 
@@ -290,17 +315,19 @@ struct Run {
         if (hctl[CTL_BAD]) fail(BKD_EINVAL, "query coordinates must be finite");
     }
 
-    void find_leaf(const FetchSpec &f, int64_t base)
+    void find_leaf(const FetchSpec &f, int64_t base) { find_leaf_into(f, leafbuf[cur], qbuf[cur], base); }
+
+    void find_leaf_into(const FetchSpec &f, uint32_t *out_leaf, int32_t *out_q, int64_t base)
     {
         launch_find_leaf(f, dQ, d, t.d_node.as<int32_t>(), t.d_keys.as<uint64_t>(), K, k, t.d_split.as<float>(), h,
-                         leafbuf[cur], qbuf[cur], base, cnt, ctl, s);
+                         out_leaf, out_q, base, cnt, ctl, s);
         t.stats.fetches++;
         const int64_t F = f.ring_count + f.in_count;
         if (tracing && F > 0) {
             tr_q.resize((size_t)F);
             tr_l.resize((size_t)F);
-            BKD_HIP(hipMemcpyAsync(tr_q.data(), qbuf[cur] + base, sizeof(int32_t) * F, hipMemcpyDeviceToHost, s));
-            BKD_HIP(hipMemcpyAsync(tr_l.data(), leafbuf[cur] + base, sizeof(int32_t) * F, hipMemcpyDeviceToHost, s));
+            BKD_HIP(hipMemcpyAsync(tr_q.data(), out_q + base, sizeof(int32_t) * F, hipMemcpyDeviceToHost, s));
+            BKD_HIP(hipMemcpyAsync(tr_l.data(), out_leaf + base, sizeof(int32_t) * F, hipMemcpyDeviceToHost, s));
             BKD_HIP(hipStreamSynchronize(s));
             for (int64_t j = 0; j < F; j++) {
                 t.trace_q.push_back(tr_q[(size_t)j]);
@@ -316,7 +343,7 @@ struct Run {
                                       t.d_hist.as<uint32_t>(), s);
         if (which) cur = 1 - cur;
         launch_leaf_offsets(cnt, t.d_leaf_off.as<int32_t>(), nleaf, SCAN_QT, SCAN_DENSE_MIN, t.d_off.as<int32_t>(),
-                            t.d_tiles.as<int32_t>(), ctl, s);
+                            t.d_tiles.as<int32_t>(), t.d_tiles.as<int32_t>() + nleaf + 1, ctl, s);
         if (!t.resident) {
             BKD_HIP(hipMemcpyAsync(t.h_tiles.p, t.d_tiles.p, sizeof(int32_t) * 2 * (size_t)(nleaf + 1),
                                    hipMemcpyDeviceToHost, s));
@@ -332,7 +359,7 @@ struct Run {
         a.tiles = t.d_tiles.as<int32_t>();
         a.sparse = a.tiles + nleaf + 1;
         a.off = t.d_off.as<int32_t>();
-        a.bufq = qbuf[cur];
+        a.bufq = bufq_override ? bufq_override : qbuf[cur];
         a.leaf_off = t.d_leaf_off.as<int32_t>();
         a.base = base;
         a.blk = t.d_leaf_blk.as<int64_t>();
@@ -340,6 +367,8 @@ struct Run {
         a.Q = dQ;
         a.d = d;
         a.keys = t.d_keys.as<uint64_t>();
+        a.centers = t.d_centers.as<float>();
+        a.filter_coef = 1.0f - filter_band(d);
         return a;
     }
 
@@ -478,15 +507,17 @@ struct Run {
         }
     }
 
-    // ---------------------------------------------------------------- lock-step rounds / chunk sweep
+    // ---------------------------------------------------------------- lock-step rounds
     void lockstep()
     {
         // first round: every query descends from the root
         FetchSpec f0{nullptr, 0, 0, 1, 0, m};
         find_leaf(f0, 0);
+        if (t.sweep) {
+            sweep();
+            return;
+        }
         int64_t P = m;  // pending entries (leaf order after each sort; finished ones sort last)
-        int cur_chunk = -1;
-        const int nchunks = (int)t.chunks.size();
         for (;;) {
             sort_and_offsets(P);
             P = hctl[CTL_V];
@@ -494,40 +525,97 @@ struct Run {
                 end_call();
                 break;
             }
-            int lf = 0, ll = nleaf - 1;
-            if (t.resident) {
-                scan_resident();
-            } else if (!t.sweep) {
-                scan_all_chunks();
-            } else {
-                // drain the current chunk, else move to the next chunk holding pending queries
-                auto has = [&](int j) { return j >= 0 && chunk_items(j) > 0; };
-                int c = has(cur_chunk) ? cur_chunk : -1;
-                for (int x = 1; c < 0 && x <= nchunks; x++) {
-                    int j = (cur_chunk + x + nchunks) % nchunks;
-                    if (has(j)) c = j;
-                }
-                int nc = -1;
-                for (int x = 1; nc < 0 && x < nchunks; x++) {
-                    int j = (c + x) % nchunks;
-                    if (has(j)) nc = j;
-                }
-                count_work(t.chunks[(size_t)c].leaf_first, t.chunks[(size_t)c].leaf_last);
-                scan_chunk(c, nc);
-                cur_chunk = c;
-                lf = t.chunks[(size_t)c].leaf_first;
-                ll = t.chunks[(size_t)c].leaf_last;
-            }
+            if (t.resident) scan_resident();
+            else scan_all_chunks();
             end_call();
-            // route the scanned queries again; entries of other chunks keep their leaf
-            int64_t a = 0, e = P;
-            if (t.sweep) {
-                a = hoff()[lf];
-                e = hoff()[ll + 1];
+            launch_fill_i32(cnt, 0, nleaf, s);
+            FetchSpec f{qbuf[cur], 0, P, std::max<int64_t>(P, 1), 0, 0};
+            find_leaf(f, 0);
+        }
+    }
+
+    // Chunk sweep over a streamed, leaf-aligned structure.  Pending entries live in one
+    // region per chunk; a step sorts only the region of the resident chunk c, scans it,
+    // routes its queries again and moves each entry to the region of its next chunk.
+    // The sweep stays on c while c holds at least a quarter of the average pending
+    // share, then moves on (cyclically) to the next chunk above that mark, whose copy
+    // was prefetched meanwhile.
+    void sweep()
+    {
+        const int N = (int)t.chunks.size();
+        t.d_rleaf.ensure(sizeof(uint32_t) * (size_t)N * m);
+        t.d_rq.ensure(sizeof(int32_t) * (size_t)N * m);
+        t.d_rcnt.ensure(sizeof(int32_t) * (N + 1));
+        t.h_rcnt.ensure(sizeof(int32_t) * (N + 1));
+        uint32_t *rleaf = t.d_rleaf.as<uint32_t>();
+        int32_t *rq = t.d_rq.as<int32_t>();
+        int32_t *rcnt = t.d_rcnt.as<int32_t>();
+        int32_t *hr = t.h_rcnt.as<int32_t>();
+        const int32_t *chunk_of = t.d_chunk_of.as<int32_t>();
+        uint32_t *sleaf = leafbuf[1 - cur];
+        int32_t *sq = qbuf[1 - cur];
+        auto read_counts = [&]() {
+            BKD_HIP(hipMemcpyAsync(hr, rcnt, sizeof(int32_t) * (N + 1), hipMemcpyDeviceToHost, s));
+            BKD_HIP(hipStreamSynchronize(s));
+        };
+        launch_fill_i32(rcnt, 0, N + 1, s);
+        launch_distribute(leafbuf[cur], qbuf[cur], m, nleaf, chunk_of, -1, rleaf, rq, m, rcnt, sleaf, sq, N, s);
+        read_counts();
+        int c = -1;
+        for (;;) {
+            int64_t total = 0, best = -1;
+            for (int j = 0; j < N; j++) {
+                total += hr[j];
+                if (best < 0 || hr[j] > hr[best]) best = j;
             }
-            launch_fill_i32(cnt + lf, 0, ll - lf + 1, s);
-            FetchSpec f{qbuf[cur] + a, 0, e - a, std::max<int64_t>(e - a, 1), 0, 0};
-            find_leaf(f, a);
+            if (total == 0) {
+                end_call();
+                break;
+            }
+            const int64_t mark = std::max<int64_t>(1, total / N / 4);
+            auto next_from = [&](int from, int skip) {
+                for (int x = 1; x <= N; x++) {
+                    const int j = ((from < 0 ? -1 : from) + x + N) % N;
+                    if (j != skip && hr[j] >= mark) return j;
+                }
+                int b = -1;
+                for (int j = 0; j < N; j++)
+                    if (j != skip && hr[j] > 0 && (b < 0 || hr[j] > hr[b])) b = j;
+                return b;
+            };
+            if (c < 0 || hr[c] < mark) c = next_from(c, -1);
+            const int nc = next_from(c, c);
+            const Chunk &C = t.chunks[(size_t)c];
+            const int lf = C.leaf_first, ll = C.leaf_last, nl = ll - lf + 1;
+            const int64_t n = hr[c];
+            uint32_t *Rl = rleaf + (int64_t)c * m;
+            int32_t *Rq = rq + (int64_t)c * m;
+            // sort the region by leaf, then offsets and work items of chunk c's leaves
+            if (launch_sort_pairs(Rl, Rq, sleaf, sq, n, kbits, t.d_hist.as<uint32_t>(), s)) {
+                BKD_HIP(hipMemcpyAsync(Rl, sleaf, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+                BKD_HIP(hipMemcpyAsync(Rq, sq, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+            }
+            int32_t *dtiles = t.d_tiles.as<int32_t>();
+            launch_leaf_offsets(cnt + lf, t.d_leaf_off.as<int32_t>() + lf, nl, SCAN_QT, SCAN_DENSE_MIN,
+                                t.d_off.as<int32_t>() + lf, dtiles + lf, dtiles + nleaf + 1 + lf, ctl, s);
+            BKD_HIP(hipMemcpyAsync(t.h_tiles.as<int32_t>() + lf, dtiles + lf, sizeof(int32_t) * (nl + 1),
+                                   hipMemcpyDeviceToHost, s));
+            BKD_HIP(hipMemcpyAsync(t.h_tiles.as<int32_t>() + nleaf + 1 + lf, dtiles + nleaf + 1 + lf,
+                                   sizeof(int32_t) * (nl + 1), hipMemcpyDeviceToHost, s));
+            readback();
+            count_work(lf, ll);
+            bufq_override = Rq;
+            scan_chunk(c, nc);
+            bufq_override = nullptr;
+            end_call();
+            // route again in place, then move every entry to the region of its next chunk
+            launch_fill_i32(cnt + lf, 0, nl, s);
+            FetchSpec f{Rq, 0, n, std::max<int64_t>(n, 1), 0, 0};
+            find_leaf_into(f, Rl, Rq, 0);
+            launch_distribute(Rl, Rq, n, nleaf, chunk_of, c, rleaf, rq, m, rcnt, sleaf, sq, N, s);
+            launch_restore(sleaf, sq, n, Rl, Rq, rcnt, c, N, s);
+            launch_fill_i32(rcnt + N, 0, 1, s);
+            read_counts();
         }
     }
 };

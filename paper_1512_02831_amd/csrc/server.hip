@@ -229,7 +229,7 @@ static void session_round(Session &S, int64_t nnew)
                                   S.hist.as<uint32_t>(), S.s);
     if (which) S.cur = 1 - S.cur;
     launch_leaf_offsets(S.cnt.as<int32_t>(), T.d_leaf_off.as<int32_t>(), nleaf, SCAN_QT, SCAN_DENSE_MIN,
-                        S.off.as<int32_t>(), S.tiles.as<int32_t>(), ctl, S.s);
+                        S.off.as<int32_t>(), S.tiles.as<int32_t>(), S.tiles.as<int32_t>() + nleaf + 1, ctl, S.s);
     BKD_HIP(hipMemcpyAsync(hctl, ctl, sizeof(int32_t) * CTL_WORDS, hipMemcpyDeviceToHost, S.s));
     BKD_HIP(hipStreamSynchronize(S.s));
     S.P = hctl[CTL_V];
@@ -254,6 +254,8 @@ static void session_round(Session &S, int64_t nnew)
         a.Q = S.Qpool.as<float>();
         a.d = H.d;
         a.keys = S.keys.as<uint64_t>();
+        a.centers = T.d_centers.as<float>();
+        a.filter_coef = 1.0f - filter_band(H.d);
         launch_leaf_scan(a, S.K, 0, S.s);
         launch_leaf_scan(a, S.K, 1, S.s);
         S.scans++;

@@ -1,0 +1,85 @@
+"""Pin of the dense leaf scan's inner-product filter bound.
+
+The filter compares (1 - c(d)) S - 2<q',x'> with the current K-th squared
+distance, where q' = q - centre and x' = x - centre are rounded to float32,
+S = |q'|^2 + |x'|^2 and every quantity is accumulated with float32 fused
+multiply-adds.  It is exact (never drops a point that the float32 distance
+would keep) provided |(S - 2<q',x'>)_float32 - d2_float32| <= (4d + 14) 2^-24 S,
+with c(d) four times that.  Here the float32 arithmetic is emulated exactly
+with rationals (round to nearest even after every operation) and the bound is
+checked on random and adversarial inputs.  This pins the constant; the GPU
+parity tests check that results stay bit-identical.
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+
+import numpy as np
+
+from tests.exact_ref import round_f32
+
+U = Fraction(1, 1 << 24)
+
+
+def f(x):
+    return Fraction(float(x))
+
+
+def fmaf(a, b, c):
+    return Fraction(round_f32(a * b + c))
+
+
+def sub(a, b):
+    return Fraction(round_f32(a - b))
+
+
+def filter_terms(q, x, cen):
+    d = len(q)
+    qc = [sub(f(q[j]), f(cen[j])) for j in range(d)]
+    xc = [sub(f(x[j]), f(cen[j])) for j in range(d)]
+    Qn = Xn = dot = Fraction(0)
+    for j in range(d):
+        Qn = fmaf(qc[j], qc[j], Qn)
+        Xn = fmaf(xc[j], xc[j], Xn)
+        dot = fmaf(qc[j], xc[j], dot)
+    d2 = Fraction(0)
+    for j in range(d):
+        t = sub(f(q[j]), f(x[j]))
+        d2 = fmaf(t, t, d2)
+    S = Qn + Xn
+    approx = S - 2 * dot  # exact combination; the kernel's own rounding of it is covered by the factor 4
+    return approx, d2, S
+
+
+def check(q, x, cen):
+    d = len(q)
+    approx, d2, S = filter_terms(q, x, cen)
+    bound = (4 * d + 14) * U * S
+    assert abs(approx - d2) <= bound + Fraction(1, 10 ** 40), (float(approx), float(d2), float(S))
+
+
+def test_band_random_mixture_scale():
+    rng = np.random.default_rng(1)
+    for d in (3, 10, 15):
+        for _ in range(150):
+            cen = (rng.uniform(0, 20, d)).astype(np.float32)
+            spread = rng.choice([1e-3, 0.1, 2.0, 30.0])
+            q = (cen + rng.normal(0, spread, d)).astype(np.float32)
+            x = (cen + rng.normal(0, spread, d)).astype(np.float32)
+            check(q, x, cen)
+
+
+def test_band_adversarial():
+    rng = np.random.default_rng(2)
+    d = 10
+    for _ in range(100):
+        # far from the origin, tiny separation (cancellation), centre off to one side
+        base = rng.uniform(1e3, 1e4, d).astype(np.float32)
+        q = base
+        x = np.nextafter(base, np.float32(np.inf)) if rng.random() < 0.5 else (base + np.float32(1e-3))
+        cen = (base + rng.normal(0, 50, d)).astype(np.float32)
+        check(q, x.astype(np.float32), cen)
+        check(q, q.copy(), cen)  # identical points: distance 0
+        # subnormal-sized differences
+        tiny = (rng.normal(0, 1e-39, d)).astype(np.float32)
+        check(tiny, np.zeros(d, np.float32), np.zeros(d, np.float32))
