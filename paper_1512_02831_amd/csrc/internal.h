@@ -101,10 +101,14 @@ enum Ctl : int {
     CTL_WORDS = 16
 };
 
-// Query-tile width of the dense leaf scan (queries per work item), and the
-// buffer fill below which a leaf is scanned with one wave per buffered query.
-constexpr int SCAN_QT = 256;
+// Buffer fill below which a leaf is scanned with one wave per buffered query.
 constexpr int SCAN_DENSE_MIN = 32;
+
+// Queries per lane of the dense leaf scan for padded dimension D and key
+// capacity K (two when the register budget allows), and its work-item width.
+__host__ __device__ constexpr int dense_queries_per_lane(int D, int K) { return (K <= 10 && D <= 16) ? 2 : 1; }
+constexpr int SCAN_LANES = 256;
+int dense_tile_queries(int d, int k);  // 256 * dense_queries_per_lane(padded_dim(d), key_capacity(k))
 
 struct Tree {
     HostTree host;

@@ -39,6 +39,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace bkd {
@@ -67,6 +69,8 @@ __device__ inline int xcd_item(int b, int grid)
 
 template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
 {
+    constexpr int NQ = dense_queries_per_lane(D, K);  // queries per lane: each staged point feeds NQ queries
+    constexpr int QT = SCAN_THREADS * NQ;
     constexpr int DS = (D + 3) & ~3;
     constexpr int PT = D > 16 ? SCAN_PT / 2 : SCAN_PT;  // points per LDS tile
     __shared__ float4 xs[PT * DS / 4];  // original coordinates, point-major
@@ -86,8 +90,8 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
         else hi = mid - 1;
     }
     const int L = lo;
-    const int qbase = a.off[L] + (item - a.tiles[L]) * SCAN_QT;
-    const int qcnt = min(SCAN_QT, a.off[L + 1] - qbase);
+    const int qbase = a.off[L] + (item - a.tiles[L]) * QT;
+    const int qcnt = min(QT, a.off[L + 1] - qbase);
     const int64_t l0 = a.leaf_off[L];
     const int len = a.leaf_off[L + 1] - a.leaf_off[L];
     const int64_t p0 = max(l0, a.chunk_lo);
@@ -98,25 +102,121 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
     const float coef = a.filter_coef;
 
     const int tid = threadIdx.x;
-    const bool act = tid < qcnt;
-    const bool wave_busy = (tid & ~63) < qcnt;
-    const int32_t q = act ? a.bufq[qbase + tid] : 0;
-    float qv[D], qc[D];
-    float Qn = 0.0f;
+    // lane tid holds queries tid and tid + 256 of the tile
+    bool act[NQ];
+    int32_t q[NQ];
+    float qv[NQ][D], qc[NQ][D], Qn[NQ], thr[NQ], Aq[NQ];
+    uint64_t lst[NQ][K];
+    bool fresh = false;
 #pragma unroll
-    for (int j = 0; j < D; j++) {
-        qv[j] = (act && j < a.d) ? a.Q[(int64_t)q * a.d + j] : 0.0f;
-        qc[j] = (j < a.d) ? qv[j] - cen[j] : 0.0f;
-        Qn = fmaf(qc[j], qc[j], Qn);
+    for (int u = 0; u < NQ; u++) {
+        act[u] = tid + SCAN_THREADS * u < qcnt;
+        q[u] = act[u] ? a.bufq[qbase + tid + SCAN_THREADS * u] : 0;
+        Qn[u] = 0.0f;
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            qv[u][j] = (act[u] && j < a.d) ? a.Q[(int64_t)q[u] * a.d + j] : 0.0f;
+            qc[u][j] = (j < a.d) ? qv[u][j] - cen[j] : 0.0f;
+            Qn[u] = fmaf(qc[u][j], qc[u][j], Qn[u]);
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < K; s2++) lst[u][s2] = act[u] ? a.keys[(int64_t)q[u] * K + s2] : 0ull;  // 0: nothing enters
+        thr[u] = __uint_as_float((uint32_t)(lst[u][K - 1] >> 32));
+        fresh |= act[u] && isinf(thr[u]);
+        Aq[u] = act[u] ? 0.5f * (coef * Qn[u] - thr[u]) : INFINITY;
     }
-    uint64_t lst[K];
-#pragma unroll
-    for (int s = 0; s < K; s++) lst[s] = act ? a.keys[(int64_t)q * K + s] : 0ull;  // 0: nothing enters
-    float thr = __uint_as_float((uint32_t)(lst[K - 1] >> 32));
+    const bool wave_busy = (tid & ~63) < qcnt;
+    const bool wave_dual = NQ > 1 && (tid & ~63) + SCAN_THREADS < qcnt;
     // A query whose list is not full yet (K-th key EMPTY) accepts every point; such
     // tiles take the exact path, all others the inner-product filter.
-    const bool exact_path = __syncthreads_or(act && isinf(thr)) != 0;
-    float Aq = act ? 0.5f * (coef * Qn - thr) : INFINITY;
+    const bool exact_path = __syncthreads_or(fresh) != 0;
+
+    auto exact_points = [&](auto nq_tag, int np) {
+        constexpr int N = decltype(nq_tag)::value;
+#pragma unroll 2
+        for (int i = 0; i < np; i++) {
+            const float4 *xp = xs + i * (DS / 4);
+            float acc[N];
+#pragma unroll
+            for (int u = 0; u < N; u++) acc[u] = 0.0f;
+#pragma unroll
+            for (int c = 0; c < DS / 4; c++) {
+                float4 x4 = xp[c];
+                float xe[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    if (4 * c + e < D) {
+#pragma unroll
+                        for (int u = 0; u < N; u++) {
+                            float t = qv[u][4 * c + e] - xe[e];
+                            acc[u] = fmaf(t, t, acc[u]);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < N; u++) {
+                uint64_t key = ((uint64_t)__float_as_uint(acc[u]) << 32) | (uint32_t)os[i];
+                if (key < lst[u][K - 1]) key_insert<K>(lst[u], key);
+            }
+        }
+    };
+    auto filter_points = [&](auto nq_tag, int np) {
+        constexpr int N = decltype(nq_tag)::value;
+#pragma unroll 4
+        for (int i = 0; i < np; i++) {
+            const float4 *cp = xc + i * (DS / 4);
+            float dot[N];
+#pragma unroll
+            for (int u = 0; u < N; u++) dot[u] = 0.0f;
+#pragma unroll
+            for (int c = 0; c < DS / 4; c++) {
+                float4 x4 = cp[c];
+                float xe[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+                for (int e = 0; e < 4; e++)
+                    if (4 * c + e < D) {
+#pragma unroll
+                        for (int u = 0; u < N; u++) dot[u] = fmaf(qc[u][4 * c + e], xe[e], dot[u]);
+                    }
+            }
+            const float b = bs[i];
+            bool pass[N], any = false;
+#pragma unroll
+            for (int u = 0; u < N; u++) {
+                pass[u] = Aq[u] + b <= dot[u];
+                any |= pass[u];
+            }
+            if (any) {
+                // inside the error band of the filter: decide with the exact float32 distance
+                const float4 *xp = xs + i * (DS / 4);
+#pragma unroll
+                for (int u = 0; u < N; u++) {
+                    if (pass[u]) {
+                        float acc = 0.0f;
+#pragma unroll
+                        for (int c = 0; c < DS / 4; c++) {
+                            float4 x4 = xp[c];
+                            float xe[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+                            for (int e = 0; e < 4; e++) {
+                                if (4 * c + e < D) {
+                                    float t = qv[u][4 * c + e] - xe[e];
+                                    acc = fmaf(t, t, acc);
+                                }
+                            }
+                        }
+                        uint64_t key = ((uint64_t)__float_as_uint(acc) << 32) | (uint32_t)os[i];
+                        if (key < lst[u][K - 1]) {
+                            key_insert<K>(lst[u], key);
+                            thr[u] = __uint_as_float((uint32_t)(lst[u][K - 1] >> 32));
+                            Aq[u] = 0.5f * (coef * Qn[u] - thr[u]);
+                        }
+                    }
+                }
+            }
+        }
+    };
 
     for (int64_t pt = p0; pt < p1; pt += PT) {
         const int np = (int)min((int64_t)PT, p1 - pt);
@@ -139,68 +239,22 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
         }
         __syncthreads();
         if (!wave_busy) continue;  // whole wave without queries: only helps staging
-        if (exact_path) {
-#pragma unroll 2
-            for (int i = 0; i < np; i++) {
-                const float4 *xp = xs + i * (DS / 4);
-                float acc = 0.0f;
-#pragma unroll
-                for (int c = 0; c < DS / 4; c++) {
-                    float4 x4 = xp[c];
-                    float xe[4] = {x4.x, x4.y, x4.z, x4.w};
-#pragma unroll
-                    for (int e = 0; e < 4; e++) {
-                        if (4 * c + e < D) {
-                            float t = qv[4 * c + e] - xe[e];
-                            acc = fmaf(t, t, acc);
-                        }
-                    }
-                }
-                uint64_t key = ((uint64_t)__float_as_uint(acc) << 32) | (uint32_t)os[i];
-                if (key < lst[K - 1]) key_insert<K>(lst, key);
-            }
-        } else {
-#pragma unroll 4
-            for (int i = 0; i < np; i++) {
-                const float4 *cp = xc + i * (DS / 4);
-                float dot = 0.0f;
-#pragma unroll
-                for (int c = 0; c < DS / 4; c++) {
-                    float4 x4 = cp[c];
-                    float xe[4] = {x4.x, x4.y, x4.z, x4.w};
-#pragma unroll
-                    for (int e = 0; e < 4; e++)
-                        if (4 * c + e < D) dot = fmaf(qc[4 * c + e], xe[e], dot);
-                }
-                if (Aq + bs[i] <= dot) {
-                    // inside the error band of the filter: decide with the exact float32 distance
-                    const float4 *xp = xs + i * (DS / 4);
-                    float acc = 0.0f;
-#pragma unroll
-                    for (int c = 0; c < DS / 4; c++) {
-                        float4 x4 = xp[c];
-                        float xe[4] = {x4.x, x4.y, x4.z, x4.w};
-#pragma unroll
-                        for (int e = 0; e < 4; e++) {
-                            if (4 * c + e < D) {
-                                float t = qv[4 * c + e] - xe[e];
-                                acc = fmaf(t, t, acc);
-                            }
-                        }
-                    }
-                    uint64_t key = ((uint64_t)__float_as_uint(acc) << 32) | (uint32_t)os[i];
-                    if (key < lst[K - 1]) {
-                        key_insert<K>(lst, key);
-                        thr = __uint_as_float((uint32_t)(lst[K - 1] >> 32));
-                        Aq = 0.5f * (coef * Qn - thr);
-                    }
-                }
+        if constexpr (NQ > 1) {
+            if (wave_dual) {
+                if (exact_path) exact_points(std::integral_constant<int, 2>{}, np);
+                else filter_points(std::integral_constant<int, 2>{}, np);
+                continue;
             }
         }
+        if (exact_path) exact_points(std::integral_constant<int, 1>{}, np);
+        else filter_points(std::integral_constant<int, 1>{}, np);
     }
-    if (act) {
 #pragma unroll
-        for (int s = 0; s < K; s++) a.keys[(int64_t)q * K + s] = lst[s];
+    for (int u = 0; u < NQ; u++) {
+        if (act[u]) {
+#pragma unroll
+            for (int s2 = 0; s2 < K; s2++) a.keys[(int64_t)q[u] * K + s2] = lst[u][s2];
+        }
     }
 }
 
