@@ -21,8 +21,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I", os.path.join(ROOT, "include")]
+# Packed FP32 stays off; matrix-core accumulators live in ordinary VGPRs, so
+# the filter reads them without accvgpr moves.
 DEVICE = [f"--offload-arch={ARCH}", "-mcode-object-version=5", "-fno-gpu-flush-denormals-to-zero",
-          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def sources():

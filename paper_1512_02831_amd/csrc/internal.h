@@ -101,14 +101,10 @@ enum Ctl : int {
     CTL_WORDS = 16
 };
 
-// Buffer fill below which a leaf is scanned with one wave per buffered query.
+// Query-tile width of the dense leaf scan (queries per work item), and the
+// buffer fill below which a leaf is scanned with one wave per buffered query.
+constexpr int SCAN_QT = 256;
 constexpr int SCAN_DENSE_MIN = 32;
-
-// Queries per lane of the dense leaf scan for padded dimension D and key
-// capacity K (two when the register budget allows), and its work-item width.
-__host__ __device__ constexpr int dense_queries_per_lane(int D, int K) { return (K <= 10 && D <= 16) ? 2 : 1; }
-constexpr int SCAN_LANES = 256;
-int dense_tile_queries(int d, int k);  // 256 * dense_queries_per_lane(padded_dim(d), key_capacity(k))
 
 struct Tree {
     HostTree host;
@@ -162,6 +158,9 @@ struct FetchSpec {
     const int32_t *req_of = nullptr;
     int32_t *req_left = nullptr;
     int32_t *done_list = nullptr;  // done_list[0] = count, then request table indices
+    // Algorithm 1 schedule: record the largest buffer fill (the half-full trigger);
+    // other schedules only need the per-leaf counts.
+    bool track_fill = false;
 };
 
 void launch_init_state(int32_t *node, uint64_t *keys, int64_t m, int K, hipStream_t s);

@@ -82,26 +82,36 @@ __global__ __launch_bounds__(256) void k_find_leaf(FetchSpec f, const float *__r
     }
     // Buffer fills: lanes bound for the same leaf are counted with one atomic
     // (fetched queries arrive grouped by their previous leaf, so a wave holds
-    // few distinct leaves); each lane learns its fill for the trigger test.
+    // few distinct leaves).  Under the Algorithm 1 schedule each lane also
+    // learns its fill for the half-full trigger, which needs the atomic's
+    // return value; otherwise the atomics are fire-and-forget.
     uint64_t todo = __ballot(valid);
-    const uint64_t below = lanemask_lt();
-    while (todo) {
-        const int leader = __ffsll((unsigned long long)todo) - 1;
-        const uint32_t ll = (uint32_t)__builtin_amdgcn_readlane((int)leaf, leader);
-        const uint64_t grp = __ballot(valid && leaf == ll);
-        int32_t old = 0;
-        if (__lane_id() == leader) old = atomicAdd(&cnt[ll], (int32_t)__popcll(grp));
-        old = __builtin_amdgcn_readlane(old, leader);
-        if ((grp >> __lane_id()) & 1ull) fill = old + (int32_t)__popcll(grp & below) + 1;
-        todo &= ~grp;
+    const uint64_t vb = todo;
+    if (f.track_fill) {
+        const uint64_t below = lanemask_lt();
+        while (todo) {
+            const int leader = __ffsll((unsigned long long)todo) - 1;
+            const uint32_t ll = (uint32_t)__builtin_amdgcn_readlane((int)leaf, leader);
+            const uint64_t grp = __ballot(valid && leaf == ll);
+            int32_t old = 0;
+            if (__lane_id() == leader) old = atomicAdd(&cnt[ll], (int32_t)__popcll(grp));
+            old = __builtin_amdgcn_readlane(old, leader);
+            if ((grp >> __lane_id()) & 1ull) fill = old + (int32_t)__popcll(grp & below) + 1;
+            todo &= ~grp;
+        }
+        int32_t mx = fill;
+        for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
+        if (__lane_id() == 0 && mx > 0) atomicMax(&ctl[CTL_MAXCNT], mx);
+    } else {
+        while (todo) {
+            const int leader = __ffsll((unsigned long long)todo) - 1;
+            const uint32_t ll = (uint32_t)__builtin_amdgcn_readlane((int)leaf, leader);
+            const uint64_t grp = __ballot(valid && leaf == ll);
+            if (__lane_id() == leader) atomicAdd(&cnt[ll], (int32_t)__popcll(grp));
+            todo &= ~grp;
+        }
     }
-    int32_t mx = fill;
-    for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
-    uint64_t vb = __ballot(valid);
-    if (__lane_id() == 0) {
-        if (mx > 0) atomicMax(&ctl[CTL_MAXCNT], mx);
-        if (vb) atomicAdd(&ctl[CTL_NVALID], (int32_t)__popcll(vb));
-    }
+    if (__lane_id() == 0 && vb) atomicAdd(&ctl[CTL_NVALID], (int32_t)__popcll(vb));
 }
 
 // ---------------------------------------------------------------------------

@@ -1,26 +1,29 @@
 // leaf_scan.h -- ProcessAllBuffers leaf scan (Section 2.4, Section 3.2), gfx950.
 //
 // Dense leaves (many buffered queries): one workgroup of 256 lanes takes one
-// work item, up to 256 buffered queries of one leaf, one query per lane.  The
-// leaf's points (the part held by the current chunk) stream through LDS in
-// tiles, point-major with the coordinates padded to a multiple of four, so
-// that every lane reads the same point with a broadcast ds_read_b128.  Each
-// lane keeps its query in registers and its K best keys as a sorted register
-// list; a point enters through a compare-exchange cascade only when its key
-// beats the K-th best (a wave-uniform branch, skipped when no lane qualifies).
+// work item, up to 256 buffered queries of one leaf; lane i owns query i (its
+// coordinates and its K best keys as a sorted register list).  The leaf's
+// points (the part held by the current chunk) stream through LDS in tiles.
 //
-// Inner-product filter.  Once every query of a tile has K candidates, a point
-// is first tested with the expansion |q-x|^2 = |q'|^2 + |x'|^2 - 2<q',x'> on
+// Matrix-core filter.  Once every query of a wave has K candidates, a pair is
+// first tested with the expansion |q-x|^2 = |q'|^2 + |x'|^2 - 2<q',x'> on
 // coordinates relative to the leaf centre c (q' = q-c, x' = x-c, both rounded
-// to float32): d fused multiply-adds per pair instead of d subtractions and d
-// FMAs.  The test accepts every point whose exact float32 distance could reach
-// the K-th best thr: with S = |q'|^2 + |x'|^2, the computed expansion differs
-// from the float32 distance by at most (4d + 14) 2^-24 S (centring, the dot
-// product, the norms, the final combination and the float32 distance itself;
-// a borderline case has thr <= 2S, so the comparison's own rounding is of the
-// same order), and the test  (1 - c(d)) S - 2<q',x'> <= thr  uses c(d) = 4
-// times that bound.  Accepted points are re-checked with the exact float32
-// distance, so keys and results are bit-identical to the exact path.
+// to float32).  The inner products of 32 points against the wave's 64 queries
+// are two 32x32 float32 MFMA tiles (v_mfma_f32_32x32x2f32, two coordinates
+// per step), so the vector unit only does one subtraction and half a max per
+// pair.  A pair passes when  <q',x'> - (1-c(d)) |x'|^2/2 >= ((1-c(d)) |q'|^2
+// - thr)/2 - eta, thr the query's current K-th squared distance.  With
+// S = |q'|^2 + |x'|^2 the computed expansion is within (4d + 14) 2^-24 S of
+// the float32 distance when every float32 operation rounds to nearest, and
+// within twice that when the matrix unit's inner product errs by up to 2^-23
+// per operation in any order (truncating arithmetic); c(d) = 4 (4d + 14)
+// 2^-24 covers both and the final combination's own rounding (a borderline
+// pair has thr <= 2S).  eta = 2^-120 covers products flushed to zero below the
+// normal range.  Passing pairs go to the lane owning the query, which re-checks
+// them with the exact float32 distance, so keys and results are bit-identical
+// to the exact path.  A wave holding a query whose list is not full yet (a
+// first visit) takes the exact path, every point through the float32
+// distance, 32 points at a time until all its lists are full.
 //
 // Squared distances follow the float32 reading: t = q_j - x_j rounded, then
 // acc = fma(t, t, acc) for j = 0..d-1 from +0.  Padding dimensions hold zero in
@@ -38,8 +41,6 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
-
-#include <type_traits>
 
 #include "internal.h"
 
@@ -67,15 +68,21 @@ __device__ inline int xcd_item(int b, int grid)
     return (b & 7) * per + (b >> 3);
 }
 
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Absolute slack of the matrix-core filter: covers products that the matrix
+// unit may flush to zero when they fall below the float32 normal range.
+constexpr float FILTER_ABS_SLACK = 0x1p-120f;
+
 template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
 {
-    constexpr int NQ = dense_queries_per_lane(D, K);  // queries per lane: each staged point feeds NQ queries
-    constexpr int QT = SCAN_THREADS * NQ;
-    constexpr int DS = (D + 3) & ~3;
+    constexpr int DS = (D + 3) & ~3;   // row of the exact copy, padded for float4 reads
+    constexpr int SM = (D + 1) / 2;    // matrix-core steps of two coordinates
     constexpr int PT = D > 16 ? SCAN_PT / 2 : SCAN_PT;  // points per LDS tile
-    __shared__ float4 xs[PT * DS / 4];  // original coordinates, point-major
-    __shared__ float4 xc[PT * DS / 4];  // coordinates minus the leaf centre
-    __shared__ float bs[PT];            // (1 - c) |x - centre|^2 / 2
+    constexpr int NB = PT / 32;        // 32-point blocks per tile
+    __shared__ float4 xs[PT * DS / 4];  // original coordinates, point-major (exact distances)
+    __shared__ float xa[NB * SM * 64];  // centred coordinates in matrix-core operand order
+    __shared__ float bs[PT];            // (1 - c) |x - centre|^2 / 2, +inf on padding rows
     __shared__ int32_t os[PT];
 
     int item = xcd_item(blockIdx.x, gridDim.x);
@@ -90,8 +97,8 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
         else hi = mid - 1;
     }
     const int L = lo;
-    const int qbase = a.off[L] + (item - a.tiles[L]) * QT;
-    const int qcnt = min(QT, a.off[L + 1] - qbase);
+    const int qbase = a.off[L] + (item - a.tiles[L]) * SCAN_QT;
+    const int qcnt = min(SCAN_QT, a.off[L + 1] - qbase);
     const int64_t l0 = a.leaf_off[L];
     const int len = a.leaf_off[L + 1] - a.leaf_off[L];
     const int64_t p0 = max(l0, a.chunk_lo);
@@ -102,43 +109,50 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
     const float coef = a.filter_coef;
 
     const int tid = threadIdx.x;
-    // lane tid holds queries tid and tid + 256 of the tile
-    bool act[NQ];
-    int32_t q[NQ];
-    float qv[NQ][D], qc[NQ][D], Qn[NQ], thr[NQ], Aq[NQ];
-    uint64_t lst[NQ][K];
-    bool fresh = false;
+    const int lane = tid & 63, half = lane >> 5, col = lane & 31;
+    const bool act = tid < qcnt;
+    const int32_t q = act ? a.bufq[qbase + tid] : 0;
+    float qv[D], qc[D], Qn = 0.0f;
 #pragma unroll
-    for (int u = 0; u < NQ; u++) {
-        act[u] = tid + SCAN_THREADS * u < qcnt;
-        q[u] = act[u] ? a.bufq[qbase + tid + SCAN_THREADS * u] : 0;
-        Qn[u] = 0.0f;
-#pragma unroll
-        for (int j = 0; j < D; j++) {
-            qv[u][j] = (act[u] && j < a.d) ? a.Q[(int64_t)q[u] * a.d + j] : 0.0f;
-            qc[u][j] = (j < a.d) ? qv[u][j] - cen[j] : 0.0f;
-            Qn[u] = fmaf(qc[u][j], qc[u][j], Qn[u]);
-        }
-#pragma unroll
-        for (int s2 = 0; s2 < K; s2++) lst[u][s2] = act[u] ? a.keys[(int64_t)q[u] * K + s2] : 0ull;  // 0: nothing enters
-        thr[u] = __uint_as_float((uint32_t)(lst[u][K - 1] >> 32));
-        fresh |= act[u] && isinf(thr[u]);
-        Aq[u] = act[u] ? 0.5f * (coef * Qn[u] - thr[u]) : INFINITY;
+    for (int j = 0; j < D; j++) {
+        qv[j] = (act && j < a.d) ? a.Q[(int64_t)q * a.d + j] : 0.0f;
+        qc[j] = (act && j < a.d) ? qv[j] - cen[j] : 0.0f;
+        Qn = fmaf(qc[j], qc[j], Qn);
     }
-    const bool wave_busy = (tid & ~63) < qcnt;
-    const bool wave_dual = NQ > 1 && (tid & ~63) + SCAN_THREADS < qcnt;
-    // A query whose list is not full yet (K-th key EMPTY) accepts every point; such
-    // tiles take the exact path, all others the inner-product filter.
-    const bool exact_path = __syncthreads_or(fresh) != 0;
-
-    auto exact_points = [&](auto nq_tag, int np) {
-        constexpr int N = decltype(nq_tag)::value;
-#pragma unroll 2
-        for (int i = 0; i < np; i++) {
-            const float4 *xp = xs + i * (DS / 4);
-            float acc[N];
+    uint64_t lst[K];
 #pragma unroll
-            for (int u = 0; u < N; u++) acc[u] = 0.0f;
+    for (int s2 = 0; s2 < K; s2++) lst[s2] = act ? a.keys[(int64_t)q * K + s2] : 0ull;  // 0: nothing enters
+    float thr = __uint_as_float((uint32_t)(lst[K - 1] >> 32));
+    // filter threshold of this lane's query: a pair passes when <q',x'> - bs >= aq
+    auto own_aq = [&]() { return act ? 0.5f * (coef * Qn - thr) - FILTER_ABS_SLACK : INFINITY; };
+
+    const bool wave_busy = (tid & ~63) < qcnt;
+    // A wave with a query whose list is not full yet (K-th key EMPTY, first
+    // visit) accepts every point: it takes the exact path, 32 points at a time,
+    // until every list is full, then the filter.
+    bool exact_wave = __any(act && isinf(thr));
+
+    // Matrix-core operands of the filter.  The wave's 64 queries form two
+    // column tiles of 32; lane l supplies query (32 t + l % 32), coordinates
+    // 2 s + l / 32 for step s, and holds that query's threshold.
+    float qb[2][SM], aq[2];
+#pragma unroll
+    for (int t = 0; t < 2; t++) {
+        const int src = 32 * t + col;
+#pragma unroll
+        for (int s2 = 0; s2 < SM; s2++) {
+            const float v0 = __shfl(qc[2 * s2], src);
+            const float v1 = (2 * s2 + 1 < D) ? __shfl(qc[2 * s2 + 1 < D ? 2 * s2 + 1 : 0], src) : 0.0f;
+            qb[t][s2] = half ? v1 : v0;
+        }
+        aq[t] = __shfl(own_aq(), src);
+    }
+
+    auto exact_points = [&](int i0, int i1) {
+#pragma unroll 2
+        for (int i = i0; i < i1; i++) {
+            const float4 *xp = xs + i * (DS / 4);
+            float acc = 0.0f;
 #pragma unroll
             for (int c = 0; c < DS / 4; c++) {
                 float4 x4 = xp[c];
@@ -146,115 +160,155 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
                     if (4 * c + e < D) {
-#pragma unroll
-                        for (int u = 0; u < N; u++) {
-                            float t = qv[u][4 * c + e] - xe[e];
-                            acc[u] = fmaf(t, t, acc[u]);
-                        }
+                        float t = qv[4 * c + e] - xe[e];
+                        acc = fmaf(t, t, acc);
                     }
                 }
             }
-#pragma unroll
-            for (int u = 0; u < N; u++) {
-                uint64_t key = ((uint64_t)__float_as_uint(acc[u]) << 32) | (uint32_t)os[i];
-                if (key < lst[u][K - 1]) key_insert<K>(lst[u], key);
-            }
-        }
-    };
-    auto filter_points = [&](auto nq_tag, int np) {
-        constexpr int N = decltype(nq_tag)::value;
-#pragma unroll 4
-        for (int i = 0; i < np; i++) {
-            const float4 *cp = xc + i * (DS / 4);
-            float dot[N];
-#pragma unroll
-            for (int u = 0; u < N; u++) dot[u] = 0.0f;
-#pragma unroll
-            for (int c = 0; c < DS / 4; c++) {
-                float4 x4 = cp[c];
-                float xe[4] = {x4.x, x4.y, x4.z, x4.w};
-#pragma unroll
-                for (int e = 0; e < 4; e++)
-                    if (4 * c + e < D) {
-#pragma unroll
-                        for (int u = 0; u < N; u++) dot[u] = fmaf(qc[u][4 * c + e], xe[e], dot[u]);
-                    }
-            }
-            const float b = bs[i];
-            bool pass[N], any = false;
-#pragma unroll
-            for (int u = 0; u < N; u++) {
-                pass[u] = Aq[u] + b <= dot[u];
-                any |= pass[u];
-            }
-            if (any) {
-                // inside the error band of the filter: decide with the exact float32 distance
-                const float4 *xp = xs + i * (DS / 4);
-#pragma unroll
-                for (int u = 0; u < N; u++) {
-                    if (pass[u]) {
-                        float acc = 0.0f;
-#pragma unroll
-                        for (int c = 0; c < DS / 4; c++) {
-                            float4 x4 = xp[c];
-                            float xe[4] = {x4.x, x4.y, x4.z, x4.w};
-#pragma unroll
-                            for (int e = 0; e < 4; e++) {
-                                if (4 * c + e < D) {
-                                    float t = qv[u][4 * c + e] - xe[e];
-                                    acc = fmaf(t, t, acc);
-                                }
-                            }
-                        }
-                        uint64_t key = ((uint64_t)__float_as_uint(acc) << 32) | (uint32_t)os[i];
-                        if (key < lst[u][K - 1]) {
-                            key_insert<K>(lst[u], key);
-                            thr[u] = __uint_as_float((uint32_t)(lst[u][K - 1] >> 32));
-                            Aq[u] = 0.5f * (coef * Qn[u] - thr[u]);
-                        }
-                    }
-                }
-            }
+            uint64_t key = ((uint64_t)__float_as_uint(acc) << 32) | (uint32_t)os[i];
+            if (key < lst[K - 1]) key_insert<K>(lst, key);
         }
     };
 
+    // One 32-point block against the wave's 64 queries.  The accumulator
+    // register r of lane l holds point 32 b + (r % 4) + 8 (r / 4) + 4 (l / 32)
+    // against query (32 t + l % 32).
+    auto filter_block = [&](int b, int np) {
+        f32x16 c0 = {}, c1 = {};
+#pragma unroll
+        for (int s2 = 0; s2 < SM; s2++) {
+            const float av = xa[(b * SM + s2) * 64 + lane];
+            c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, qb[0][s2], c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, qb[1][s2], c1, 0, 0, 0);
+        }
+        float bv[16];
+#pragma unroll
+        for (int g = 0; g < 4; g++) {
+            const float4 b4 = *reinterpret_cast<const float4 *>(bs + 32 * b + 8 * g + 4 * half);
+            bv[4 * g] = b4.x;
+            bv[4 * g + 1] = b4.y;
+            bv[4 * g + 2] = b4.z;
+            bv[4 * g + 3] = b4.w;
+        }
+        float m0 = -INFINITY, m1 = -INFINITY;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            m0 = fmaxf(m0, c0[r] - bv[r]);
+            m1 = fmaxf(m1, c1[r] - bv[r]);
+        }
+        if (!__any(m0 >= aq[0] || m1 >= aq[1])) return;
+        // Some pair passed: hand each passing (point, query) to the lane that
+        // owns the query (lane 32 t + j for column j of tile t), which
+        // re-checks it with the exact float32 distance.
+        uint32_t f0 = 0, f1 = 0;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            f0 |= (c0[r] - bv[r] >= aq[0]) ? (1u << r) : 0u;
+            f1 |= (c1[r] - bv[r] >= aq[1]) ? (1u << r) : 0u;
+        }
+        const uint32_t lo0 = __shfl(f0, col), hi0 = __shfl(f0, col + 32);
+        const uint32_t lo1 = __shfl(f1, col), hi1 = __shfl(f1, col + 32);
+        uint32_t mlo = half ? lo1 : lo0, mhi = half ? hi1 : hi0;
+        bool changed = false;
+        while (mlo | mhi) {
+            int r, h;
+            if (mlo) {
+                r = __builtin_ctz(mlo);
+                mlo &= mlo - 1;
+                h = 0;
+            } else {
+                r = __builtin_ctz(mhi);
+                mhi &= mhi - 1;
+                h = 1;
+            }
+            const int p = 32 * b + (r & 3) + 8 * (r >> 2) + 4 * h;
+            if (p >= np) continue;
+            const float4 *xp = xs + p * (DS / 4);
+            float acc = 0.0f;
+#pragma unroll
+            for (int c = 0; c < DS / 4; c++) {
+                float4 x4 = xp[c];
+                float xe[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    if (4 * c + e < D) {
+                        float t = qv[4 * c + e] - xe[e];
+                        acc = fmaf(t, t, acc);
+                    }
+                }
+            }
+            const uint64_t key = ((uint64_t)__float_as_uint(acc) << 32) | (uint32_t)os[p];
+            if (key < lst[K - 1]) {
+                key_insert<K>(lst, key);
+                changed = true;
+            }
+        }
+        if (__any(changed)) {
+            thr = __uint_as_float((uint32_t)(lst[K - 1] >> 32));
+            aq[0] = __shfl(own_aq(), col);
+            aq[1] = __shfl(own_aq(), 32 + col);
+        }
+    };
+
+    // Staging: thread t brings point t of a tile; the next tile's coordinates
+    // are loaded into registers while the current tile is scanned.
+    const int first_pt = (int)(p0 - l0);  // a valid point of this item (clamped loads stay in the chunk)
+    float pre[DS], cr[DS];
+    int32_t pre_o = 0;
+#pragma unroll
+    for (int j = 0; j < DS; j++) cr[j] = (j < a.d) ? cen[j] : 0.0f;
+    auto load_tile = [&](int64_t pt) {
+        if (PT < SCAN_THREADS && tid >= PT) return;
+        const int np = (int)min((int64_t)PT, p1 - pt);
+        const bool live = tid < np;
+        const int i = live ? (int)(pt - l0) + tid : first_pt;
+#pragma unroll
+        for (int j = 0; j < DS; j++) {
+            const float x = X[(j < a.d ? j : 0) * len + i];
+            pre[j] = (live && j < a.d) ? x : 0.0f;
+        }
+        pre_o = orig[i];
+    };
+    load_tile(p0);
     for (int64_t pt = p0; pt < p1; pt += PT) {
         const int np = (int)min((int64_t)PT, p1 - pt);
+        const int npad = (np + 31) & ~31;
         __syncthreads();
-        for (int t = tid; t < np; t += SCAN_THREADS) {
-            const int i = (int)(pt - l0) + t;
-            float *ro = reinterpret_cast<float *>(xs) + t * DS;
-            float *rc = reinterpret_cast<float *>(xc) + t * DS;
+        if (tid < npad) {
+            const bool live = tid < np;
+            float *ro = reinterpret_cast<float *>(xs) + tid * DS;
+            float *ra = xa + (tid >> 5) * SM * 64 + (tid & 31);
             float Xn = 0.0f;
 #pragma unroll
             for (int j = 0; j < DS; j++) {
-                const float x = (j < a.d) ? X[j * len + i] : 0.0f;
-                const float c = (j < a.d) ? x - cen[j] : 0.0f;
-                ro[j] = x;
-                rc[j] = c;
+                const float c = (live && j < a.d) ? pre[j] - cr[j] : 0.0f;
+                ro[j] = pre[j];
+                if (j < 2 * SM) ra[(j >> 1) * 64 + 32 * (j & 1)] = c;
                 Xn = fmaf(c, c, Xn);
             }
-            bs[t] = 0.5f * (coef * Xn);
-            os[t] = orig[i];
+            bs[tid] = live ? 0.5f * (coef * Xn) : INFINITY;
+            os[tid] = pre_o;
         }
         __syncthreads();
+        if (pt + PT < p1) load_tile(pt + PT);
         if (!wave_busy) continue;  // whole wave without queries: only helps staging
-        if constexpr (NQ > 1) {
-            if (wave_dual) {
-                if (exact_path) exact_points(std::integral_constant<int, 2>{}, np);
-                else filter_points(std::integral_constant<int, 2>{}, np);
+        for (int b = 0; b < npad / 32; b++) {
+            if (!exact_wave) {
+                filter_block(b, np);
                 continue;
             }
+            exact_points(32 * b, min(32 * b + 32, np));
+            thr = __uint_as_float((uint32_t)(lst[K - 1] >> 32));
+            exact_wave = __any(act && isinf(thr));
+            if (!exact_wave) {
+                aq[0] = __shfl(own_aq(), col);
+                aq[1] = __shfl(own_aq(), 32 + col);
+            }
         }
-        if (exact_path) exact_points(std::integral_constant<int, 1>{}, np);
-        else filter_points(std::integral_constant<int, 1>{}, np);
     }
+    if (act) {
 #pragma unroll
-    for (int u = 0; u < NQ; u++) {
-        if (act[u]) {
-#pragma unroll
-            for (int s2 = 0; s2 < K; s2++) a.keys[(int64_t)q[u] * K + s2] = lst[u][s2];
-        }
+        for (int s2 = 0; s2 < K; s2++) a.keys[(int64_t)q * K + s2] = lst[s2];
     }
 }
 

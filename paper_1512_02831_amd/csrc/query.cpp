@@ -342,7 +342,7 @@ struct Run {
         int which = launch_sort_pairs(leafbuf[cur], qbuf[cur], leafbuf[1 - cur], qbuf[1 - cur], count, kbits,
                                       t.d_hist.as<uint32_t>(), s);
         if (which) cur = 1 - cur;
-        launch_leaf_offsets(cnt, t.d_leaf_off.as<int32_t>(), nleaf, dense_tile_queries(d, k), SCAN_DENSE_MIN, t.d_off.as<int32_t>(),
+        launch_leaf_offsets(cnt, t.d_leaf_off.as<int32_t>(), nleaf, SCAN_QT, SCAN_DENSE_MIN, t.d_off.as<int32_t>(),
                             t.d_tiles.as<int32_t>(), t.d_tiles.as<int32_t>() + nleaf + 1, ctl, s);
         if (!t.resident) {
             BKD_HIP(hipMemcpyAsync(t.h_tiles.p, t.d_tiles.p, sizeof(int32_t) * 2 * (size_t)(nleaf + 1),
@@ -479,6 +479,7 @@ struct Run {
             const int64_t take_re = std::min(M, re_len);
             const int64_t take_in = std::min(M - take_re, m - in_head);
             FetchSpec f{t.d_ring.as<int32_t>(), re_head, take_re, m, in_head, take_in};
+            f.track_fill = true;
             find_leaf(f, pend);
             pend += take_re + take_in;
             re_head = (re_head + take_re) % m;
@@ -596,7 +597,7 @@ struct Run {
                 BKD_HIP(hipMemcpyAsync(Rq, sq, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
             }
             int32_t *dtiles = t.d_tiles.as<int32_t>();
-            launch_leaf_offsets(cnt + lf, t.d_leaf_off.as<int32_t>() + lf, nl, dense_tile_queries(d, k), SCAN_DENSE_MIN,
+            launch_leaf_offsets(cnt + lf, t.d_leaf_off.as<int32_t>() + lf, nl, SCAN_QT, SCAN_DENSE_MIN,
                                 t.d_off.as<int32_t>() + lf, dtiles + lf, dtiles + nleaf + 1 + lf, ctl, s);
             BKD_HIP(hipMemcpyAsync(t.h_tiles.as<int32_t>() + lf, dtiles + lf, sizeof(int32_t) * (nl + 1),
                                    hipMemcpyDeviceToHost, s));

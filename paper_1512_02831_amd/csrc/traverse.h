@@ -37,10 +37,11 @@ __device__ inline int32_t next_leaf(int32_t st, const float *qp, const uint64_t 
     const float kth = __uint_as_float((uint32_t)(*kth_key >> 32));
     int32_t u = st;
     int level = h;
+    int dim = h % d;  // split dimension of the level, tracked on the way up
     while (u != 0) {
         const int32_t p = (u - 1) >> 1;
         level--;
-        const int dim = level % d;
+        dim = (dim == 0) ? d - 1 : dim - 1;
         const float s = split[p];
         const float qd = qp[dim];
         const int32_t nearc = (qd < s) ? 2 * p + 1 : 2 * p + 2;

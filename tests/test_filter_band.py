@@ -9,6 +9,12 @@ with c(d) four times that.  Here the float32 arithmetic is emulated exactly
 with rationals (round to nearest even after every operation) and the bound is
 checked on random and adversarial inputs.  This pins the constant; the GPU
 parity tests check that results stay bit-identical.
+
+The inner product may also come from a matrix unit that adds two products
+per step in an unspecified order and may truncate instead of rounding to
+nearest (error up to 2^-23 per operation).  The second set of tests emulates
+that arithmetic in every add order, with both rounding modes, and checks the
+expansion against twice the bound, which c(d) still covers with a factor 2.
 """
 from __future__ import annotations
 
@@ -33,7 +39,30 @@ def sub(a, b):
     return Fraction(round_f32(a - b))
 
 
-def filter_terms(q, x, cen):
+def round_rz(x: Fraction) -> Fraction:
+    """Round an exact rational to float32 toward zero."""
+    r = Fraction(round_f32(x))
+    if abs(r) > abs(x):
+        r = Fraction(float(np.nextafter(np.float32(float(r)), np.float32(0.0))))
+    return r
+
+
+def mx_dot(qc, xc, rnd, order):
+    """Inner product in steps of two coordinates, every product and sum rounded by rnd."""
+    acc = Fraction(0)
+    for j in range(0, len(qc), 2):
+        p0 = rnd(qc[j] * xc[j])
+        p1 = rnd(qc[j + 1] * xc[j + 1]) if j + 1 < len(qc) else Fraction(0)
+        if order == 0:
+            acc = rnd(rnd(acc + p0) + p1)
+        elif order == 1:
+            acc = rnd(rnd(acc + p1) + p0)
+        else:
+            acc = rnd(acc + rnd(p0 + p1))
+    return acc
+
+
+def filter_terms(q, x, cen, dot_fn=None):
     d = len(q)
     qc = [sub(f(q[j]), f(cen[j])) for j in range(d)]
     xc = [sub(f(x[j]), f(cen[j])) for j in range(d)]
@@ -42,6 +71,8 @@ def filter_terms(q, x, cen):
         Qn = fmaf(qc[j], qc[j], Qn)
         Xn = fmaf(xc[j], xc[j], Xn)
         dot = fmaf(qc[j], xc[j], dot)
+    if dot_fn is not None:
+        dot = dot_fn(qc, xc)
     d2 = Fraction(0)
     for j in range(d):
         t = sub(f(q[j]), f(x[j]))
@@ -56,6 +87,19 @@ def check(q, x, cen):
     approx, d2, S = filter_terms(q, x, cen)
     bound = (4 * d + 14) * U * S
     assert abs(approx - d2) <= bound + Fraction(1, 10 ** 40), (float(approx), float(d2), float(S))
+
+
+def check_mx(q, x, cen):
+    d = len(q)
+    bound = 2 * (4 * d + 14) * U
+    worst = Fraction(0)
+    for rnd in (lambda v: Fraction(round_f32(v)), round_rz):
+        for order in range(3):
+            approx, d2, S = filter_terms(q, x, cen, lambda a, b: mx_dot(a, b, rnd, order))
+            assert abs(approx - d2) <= bound * S + Fraction(1, 10 ** 40), (float(approx), float(d2), float(S))
+            if S > 0:
+                worst = max(worst, abs(approx - d2) / (bound * S))
+    return worst
 
 
 def test_band_random_mixture_scale():
@@ -83,3 +127,31 @@ def test_band_adversarial():
         # subnormal-sized differences
         tiny = (rng.normal(0, 1e-39, d)).astype(np.float32)
         check(tiny, np.zeros(d, np.float32), np.zeros(d, np.float32))
+
+
+def test_band_matrix_unit_model_random():
+    rng = np.random.default_rng(3)
+    worst = Fraction(0)
+    for d in (3, 10, 15):
+        for _ in range(40):
+            cen = (rng.uniform(0, 20, d)).astype(np.float32)
+            spread = rng.choice([1e-3, 0.1, 2.0, 30.0])
+            q = (cen + rng.normal(0, spread, d)).astype(np.float32)
+            x = (cen + rng.normal(0, spread, d)).astype(np.float32)
+            worst = max(worst, check_mx(q, x, cen))
+    assert worst < 1
+
+
+def test_band_matrix_unit_model_adversarial():
+    rng = np.random.default_rng(4)
+    d = 10
+    for _ in range(30):
+        base = rng.uniform(1e3, 1e4, d).astype(np.float32)
+        x = np.nextafter(base, np.float32(np.inf)) if rng.random() < 0.5 else (base + np.float32(1e-3))
+        cen = (base + rng.normal(0, 50, d)).astype(np.float32)
+        check_mx(base, x.astype(np.float32), cen)
+        check_mx(base, base.copy(), cen)
+    # the wrong model fails: an inner product that loses one step's rounding twice over breaks the bound
+    q = np.float32([3.0, -1.0, 2.5]); x = np.float32([2.9, -1.2, 2.4]); cen = np.float32([0.0, 0.0, 0.0])
+    approx, d2, S = filter_terms(q, x, cen, lambda a, b: sum(a[j] * b[j] for j in range(3)) * (1 + 200 * U))
+    assert abs(approx - d2) > 2 * (4 * 3 + 14) * U * S
