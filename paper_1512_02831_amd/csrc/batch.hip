@@ -194,7 +194,7 @@ __device__ __forceinline__ void find_task(const BatchArgs &a, int i, int j0, int
         if (j < j1) {
             const int32_t q = round == 0 ? j : inb[j];
             const int32_t v =
-                next_leaf(node[q], Q + (int64_t)q * I.d, keys + (int64_t)q * I.k + (I.k - 1), split, I.h, I.d);
+                next_leaf(node[q], Q + (int64_t)q * I.d, keys + (int64_t)q * I.k + (I.k - 1), split, nullptr, 0, I.h, I.d);
             node[q] = v;
             lf = v >= 0 ? v - first : -1;
             tmp[j] = lf;
@@ -323,7 +323,7 @@ __device__ __forceinline__ void solo_task(const BatchArgs &a, int i, RouteLds &L
         for (int j = tid; j < A; j += BT) {
             const int32_t q = round == 0 ? j : inb[j];
             const int32_t v =
-                next_leaf(node[q], Q + (int64_t)q * I.d, keys + (int64_t)q * I.k + (I.k - 1), split, I.h, I.d);
+                next_leaf(node[q], Q + (int64_t)q * I.d, keys + (int64_t)q * I.k + (I.k - 1), split, nullptr, 0, I.h, I.d);
             node[q] = v;
             const int32_t lf = v >= 0 ? v - first : -1;
             tmp[j] = lf;

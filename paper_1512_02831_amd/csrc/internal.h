@@ -90,7 +90,7 @@ struct Chunk {
 // Device control words (one small array per tree, read back by the host).
 enum Ctl : int {
     CTL_MAXCNT = 0,   // largest buffer fill since the last call
-    CTL_NVALID = 1,   // fetched entries that got a leaf since the last call
+    // word 1 is unused
     CTL_V = 2,        // buffered entries of the current call
     CTL_T = 3,        // work items of the current call
     CTL_BAD = 4,      // non-finite query coordinate seen
@@ -133,8 +133,9 @@ struct Tree {
 
     // query workspace
     DevBuf d_Q, d_outi, d_outd;
+    DevBuf d_Qp, d_perm;  // lock-step rounds: queries renumbered in first-leaf order
     DevBuf d_keys, d_node, d_ring, d_pleaf, d_pq, d_tleaf, d_tq, d_hist;
-    DevBuf d_cnt, d_off, d_tiles, d_ctl;
+    DevBuf d_cnt, d_cnt0, d_off, d_tiles, d_ctl;  // d_cnt0: run starts of the sorted pending list
     DevBuf d_chunk_of, d_rleaf, d_rq, d_rcnt;  // chunk sweep: leaf -> chunk, per-chunk pending regions
     PinnedBuf h_rcnt;
     PinnedBuf h_ctl, h_tiles;  // h_tiles: dense tiles, sparse items, buffer offsets (3 x (nleaf+1))
@@ -159,8 +160,10 @@ struct FetchSpec {
     int32_t *req_left = nullptr;
     int32_t *done_list = nullptr;  // done_list[0] = count, then request table indices
     // Algorithm 1 schedule: record the largest buffer fill (the half-full trigger);
-    // other schedules only need the per-leaf counts.
+    // other schedules only need the per-leaf counts, and the lock-step rounds take
+    // those from the sorted list instead (count_leaves false: no atomics).
     bool track_fill = false;
+    bool count_leaves = true;
 };
 
 void launch_init_state(int32_t *node, uint64_t *keys, int64_t m, int K, hipStream_t s);
@@ -173,8 +176,9 @@ int launch_sort_pairs(uint32_t *key_a, int32_t *val_a, uint32_t *key_b, int32_t 
                       uint32_t *hist, hipStream_t s);
 size_t sort_hist_words(int64_t count);
 // tiles: [2][nleaf+1] -- dense work-item offsets, then sparse (per buffered query) offsets.
-void launch_leaf_offsets(const int32_t *cnt, const int32_t *leaf_off, int nleaf, int qt, int dense_min, int32_t *off,
-                         int32_t *tiles, int32_t *sparse, int32_t *ctl, hipStream_t s);
+void launch_leaf_offsets(const int32_t *cnt, const int32_t *start, const int32_t *leaf_off, int nleaf, int qt,
+                         int dense_min, int32_t *off, int32_t *tiles, int32_t *sparse, int32_t *ctl, hipStream_t s);
+void launch_run_bounds(const uint32_t *leaf, int64_t count, int nleaf, int32_t *start, int32_t *end, hipStream_t s);
 void launch_distribute(const uint32_t *leaf, const int32_t *q, int64_t n, int nleaf, const int32_t *chunk_of, int c,
                        uint32_t *rleaf, int32_t *rq, int64_t rcap, int32_t *rcnt, uint32_t *sleaf, int32_t *sq,
                        int nchunks, hipStream_t s);
@@ -183,8 +187,10 @@ void launch_restore(const uint32_t *sleaf, const int32_t *sq, int64_t n, uint32_
 void launch_count_work(const int32_t *off, const int32_t *leaf_off, int lf, int ll, int dense_min, int32_t *ctl,
                        hipStream_t s);
 void launch_ring_append(int32_t *ring, int64_t cap, int64_t tail, const int32_t *src, int64_t count, hipStream_t s);
-void launch_finalize(const uint64_t *keys, int K, int k, int64_t m, int64_t *idx, float *dist, bool squared,
-                     hipStream_t s);
+void launch_finalize(const uint64_t *keys, int K, int k, int64_t m, const int32_t *perm, int64_t *idx, float *dist,
+                     bool squared, hipStream_t s);
+void launch_localize(int32_t *ids, const uint32_t *leaf, int64_t m, int d, const float *Q, float *Qp, int32_t *perm,
+                     int32_t *node, int h, hipStream_t s);
 void launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s);
 
 struct ScanArgs {

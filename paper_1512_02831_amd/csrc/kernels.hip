@@ -22,6 +22,8 @@ inline unsigned grid_for(int64_t count, int threads) { return (unsigned)((count 
 
 __device__ inline uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
+constexpr int FIND_LDS_SPLITS = 2047;  // heap nodes of the top 11 levels
+
 // ---------------------------------------------------------------------------
 
 __global__ void k_init_state(int32_t *node, uint64_t *keys, int64_t m, int K)
@@ -53,6 +55,11 @@ __global__ __launch_bounds__(256) void k_find_leaf(FetchSpec f, const float *__r
                                                    int64_t pend_base, int32_t *__restrict__ cnt,
                                                    int32_t *__restrict__ ctl)
 {
+    // the upper levels of the split array, shared by every walk of the block
+    __shared__ float split_lds[FIND_LDS_SPLITS];
+    const int lds_nodes = min((1 << h) - 1, FIND_LDS_SPLITS);
+    for (int i = threadIdx.x; i < lds_nodes; i += blockDim.x) split_lds[i] = split[i];
+    __syncthreads();
     const int64_t total = f.ring_count + f.in_count;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t first = (1 << h) - 1;
@@ -62,13 +69,17 @@ __global__ __launch_bounds__(256) void k_find_leaf(FetchSpec f, const float *__r
     uint32_t leaf = nleaf;
     if (j < total) {
         int32_t q;
-        if (j < f.ring_count) q = f.ring[(f.ring_head + j) % f.ring_cap];
+        if (j < f.ring_count) {
+            int64_t r = f.ring_head + j;  // ring_head < ring_cap and ring_count <= ring_cap
+            if (r >= f.ring_cap) r -= f.ring_cap;
+            q = f.ring[r];
+        }
         else if (f.in_list) q = f.in_list[f.in_start + (j - f.ring_count)];
         else q = (int32_t)(f.in_start + (j - f.ring_count));
         const float *qp = Q + (int64_t)q * d;
         const int kk = f.kq ? f.kq[q] : k;
         const int32_t st = node[q];
-        const int32_t v = next_leaf(st, qp, keys + (int64_t)q * K + (kk - 1), split, h, d);
+        const int32_t v = next_leaf(st, qp, keys + (int64_t)q * K + (kk - 1), split, split_lds, lds_nodes, h, d);
         node[q] = v;
         if (f.req_left && v == NODE_DONE && st != NODE_DONE) {
             // last query of its request: record the request as complete
@@ -86,7 +97,7 @@ __global__ __launch_bounds__(256) void k_find_leaf(FetchSpec f, const float *__r
     // learns its fill for the half-full trigger, which needs the atomic's
     // return value; otherwise the atomics are fire-and-forget.
     uint64_t todo = __ballot(valid);
-    const uint64_t vb = todo;
+    if (!f.count_leaves) return;
     if (f.track_fill) {
         const uint64_t below = lanemask_lt();
         while (todo) {
@@ -111,7 +122,19 @@ __global__ __launch_bounds__(256) void k_find_leaf(FetchSpec f, const float *__r
             todo &= ~grp;
         }
     }
-    if (__lane_id() == 0 && vb) atomicAdd(&ctl[CTL_NVALID], (int32_t)__popcll(vb));
+}
+
+// Per-leaf counts of a pending list sorted by leaf, without atomics: the run
+// of leaf l occupies [start[l], end[l]); both arrays are zero for absent leaves.
+__global__ void k_run_bounds(const uint32_t *__restrict__ leaf, int64_t count, uint32_t nleaf,
+                             int32_t *__restrict__ start, int32_t *__restrict__ end)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const uint32_t l = leaf[i];
+    if (l >= nleaf) return;
+    if (i == 0 || leaf[i - 1] != l) start[l] = (int32_t)i;
+    if (i + 1 == count || leaf[i + 1] != l) end[l] = (int32_t)(i + 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -253,6 +276,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const uint32_t *
 // queries is scanned in tiles of `qt` queries (one lane per query); a leaf
 // holding fewer gets one wave per buffered query (lanes over points).
 __global__ __launch_bounds__(1024) void k_leaf_offsets(const int32_t *__restrict__ cnt,
+                                                       const int32_t *__restrict__ start,
                                                        const int32_t *__restrict__ leaf_off, int nleaf, int qt,
                                                        int dense_min, int32_t *__restrict__ off,
                                                        int32_t *__restrict__ tiles, int32_t *__restrict__ sparse,
@@ -263,8 +287,9 @@ __global__ __launch_bounds__(1024) void k_leaf_offsets(const int32_t *__restrict
     const int seg = (nleaf + 1023) / 1024;
     const int lo = min(nleaf, tid * seg), hi = min(nleaf, lo + seg);
     long long sc = 0, st = 0, ss = 0;
+    // count of leaf l: cnt[l], or end - start of its run when start is given
     for (int l = lo; l < hi; l++) {
-        int c = cnt[l];
+        int c = cnt[l] - (start ? start[l] : 0);
         sc += c;
         if (c >= dense_min) st += (c + qt - 1) / qt;
         else ss += c;
@@ -274,7 +299,7 @@ __global__ __launch_bounds__(1024) void k_leaf_offsets(const int32_t *__restrict
     long long rt = block_exclusive_scan_1024<long long>(st, lds, &tt);
     long long rs = block_exclusive_scan_1024<long long>(ss, lds, &ts);
     for (int l = lo; l < hi; l++) {
-        int c = cnt[l];
+        int c = cnt[l] - (start ? start[l] : 0);
         off[l] = (int32_t)rc;
         tiles[l] = (int32_t)rt;
         sparse[l] = (int32_t)rs;
@@ -359,17 +384,35 @@ __global__ void k_ring_append(int32_t *ring, int64_t cap, int64_t tail, const in
     if (i < count) ring[(tail + i) % cap] = src[i];
 }
 
-__global__ void k_finalize(const uint64_t *__restrict__ keys, int K, int k, int64_t m, int64_t *__restrict__ idx,
-                           float *__restrict__ dist, int squared)
+__global__ void k_finalize(const uint64_t *__restrict__ keys, int K, int k, int64_t m, const int32_t *__restrict__ perm,
+                           int64_t *__restrict__ idx, float *__restrict__ dist, int squared)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m * k) return;
     int64_t q = i / k;
     int s = (int)(i - q * k);
     uint64_t key = keys[q * K + s];
-    idx[i] = (int64_t)(uint32_t)key;
+    const int64_t o = (perm ? (int64_t)perm[q] : q) * k + s;  // row of the caller's query
+    idx[o] = (int64_t)(uint32_t)key;
     float d2 = __uint_as_float((uint32_t)(key >> 32));
-    dist[i] = squared ? d2 : sqrtf(d2);
+    dist[o] = squared ? d2 : sqrtf(d2);
+}
+
+// Renumber the queries in the order of a pending list sorted by leaf: slot i
+// takes query q = ids[i] (perm[i] = q, coordinates copied, node = its leaf) and
+// ids[i] becomes i.  Queries sharing a buffer then have neighbouring numbers,
+// so per-query state is read and written in contiguous runs.
+__global__ void k_localize(int32_t *__restrict__ ids, const uint32_t *__restrict__ leaf, int64_t m, int d,
+                           const float *__restrict__ Q, float *__restrict__ Qp, int32_t *__restrict__ perm,
+                           int32_t *__restrict__ node, int32_t first, uint32_t nleaf)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int32_t q = ids[i];
+    perm[i] = q;
+    for (int j = 0; j < d; j++) Qp[i * d + j] = Q[(int64_t)q * d + j];
+    node[i] = leaf[i] < nleaf ? first + (int32_t)leaf[i] : NODE_DONE;
+    ids[i] = (int32_t)i;
 }
 
 }  // namespace
@@ -443,10 +486,17 @@ int launch_sort_pairs(uint32_t *key_a, int32_t *val_a, uint32_t *key_b, int32_t 
     return (passes & 1) ? 1 : 0;
 }
 
-void launch_leaf_offsets(const int32_t *cnt, const int32_t *leaf_off, int nleaf, int qt, int dense_min, int32_t *off,
-                         int32_t *tiles, int32_t *sparse, int32_t *ctl, hipStream_t s)
+void launch_leaf_offsets(const int32_t *cnt, const int32_t *start, const int32_t *leaf_off, int nleaf, int qt,
+                         int dense_min, int32_t *off, int32_t *tiles, int32_t *sparse, int32_t *ctl, hipStream_t s)
 {
-    k_leaf_offsets<<<1, 1024, 0, s>>>(cnt, leaf_off, nleaf, qt, dense_min, off, tiles, sparse, ctl);
+    k_leaf_offsets<<<1, 1024, 0, s>>>(cnt, start, leaf_off, nleaf, qt, dense_min, off, tiles, sparse, ctl);
+    check_launch();
+}
+
+void launch_run_bounds(const uint32_t *leaf, int64_t count, int nleaf, int32_t *start, int32_t *end, hipStream_t s)
+{
+    if (count <= 0) return;
+    k_run_bounds<<<grid_for(count, 256), 256, 0, s>>>(leaf, count, (uint32_t)nleaf, start, end);
     check_launch();
 }
 
@@ -481,11 +531,19 @@ void launch_ring_append(int32_t *ring, int64_t cap, int64_t tail, const int32_t 
     check_launch();
 }
 
-void launch_finalize(const uint64_t *keys, int K, int k, int64_t m, int64_t *idx, float *dist, bool squared,
-                     hipStream_t s)
+void launch_finalize(const uint64_t *keys, int K, int k, int64_t m, const int32_t *perm, int64_t *idx, float *dist,
+                     bool squared, hipStream_t s)
 {
     if (m <= 0) return;
-    k_finalize<<<grid_for(m * k, 256), 256, 0, s>>>(keys, K, k, m, idx, dist, squared ? 1 : 0);
+    k_finalize<<<grid_for(m * k, 256), 256, 0, s>>>(keys, K, k, m, perm, idx, dist, squared ? 1 : 0);
+    check_launch();
+}
+
+void launch_localize(int32_t *ids, const uint32_t *leaf, int64_t m, int d, const float *Q, float *Qp, int32_t *perm,
+                     int32_t *node, int h, hipStream_t s)
+{
+    if (m <= 0) return;
+    k_localize<<<grid_for(m, 256), 256, 0, s>>>(ids, leaf, m, d, Q, Qp, perm, node, (1 << h) - 1, 1u << h);
     check_launch();
 }
 

@@ -74,7 +74,8 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // unit may flush to zero when they fall below the float32 normal range.
 constexpr float FILTER_ABS_SLACK = 0x1p-120f;
 
-template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
+template <int D, int K>
+__global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
 {
     constexpr int DS = (D + 3) & ~3;   // row of the exact copy, padded for float4 reads
     constexpr int SM = (D + 1) / 2;    // matrix-core steps of two coordinates
@@ -200,11 +201,13 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
         // Some pair passed: hand each passing (point, query) to the lane that
         // owns the query (lane 32 t + j for column j of tile t), which
         // re-checks it with the exact float32 distance.
+        // (the per-pair test is taken as <q',x'> >= aq + bs here, so that the
+        // differences above need not stay live; both forms are within the band)
         uint32_t f0 = 0, f1 = 0;
 #pragma unroll
         for (int r = 0; r < 16; r++) {
-            f0 |= (c0[r] - bv[r] >= aq[0]) ? (1u << r) : 0u;
-            f1 |= (c1[r] - bv[r] >= aq[1]) ? (1u << r) : 0u;
+            f0 |= (c0[r] >= aq[0] + bv[r]) ? (1u << r) : 0u;
+            f1 |= (c1[r] >= aq[1] + bv[r]) ? (1u << r) : 0u;
         }
         const uint32_t lo0 = __shfl(f0, col), hi0 = __shfl(f0, col + 32);
         const uint32_t lo1 = __shfl(f1, col), hi1 = __shfl(f1, col + 32);
@@ -348,30 +351,50 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
     const int64_t p1 = min(l0 + len, a.chunk_hi);
     const float *X = a.base + (a.blk[L] + a.blk_shift);
     const int32_t *orig = reinterpret_cast<const int32_t *>(X) + (int64_t)a.d * len;
-    for (int64_t pb = p0; pb < p1; pb += 64) {
-        const int64_t p = pb + lane;
-        const bool valid = p < p1;
-        const int i = valid ? (int)(p - l0) : 0;
-        float acc = 0.0f;
+    // Four batches of 64 points per iteration: all their loads are issued before
+    // the first distance, so a query's walk over the leaf waits on memory a
+    // quarter as often.  Lanes past the end load a valid point and discard it.
+    constexpr int U = 4;
+    const int i_first = (int)(p0 - l0);
+    for (int64_t pb = p0; pb < p1; pb += 64 * U) {
+        float x[U][D];
+        int32_t o[U];
+        bool valid[U];
 #pragma unroll
-        for (int j = 0; j < D; j++) {
-            float x = (valid && j < a.d) ? X[j * len + i] : 0.0f;
-            float t = qv[j] - x;
-            acc = fmaf(t, t, acc);
+        for (int u = 0; u < U; u++) {
+            const int64_t p = pb + 64 * u + lane;
+            valid[u] = p < p1;
+            const int i = valid[u] ? (int)(p - l0) : i_first;
+#pragma unroll
+            for (int j = 0; j < D; j++) x[u][j] = X[(j < a.d ? j : 0) * len + i];
+            o[u] = orig[i];
         }
-        const uint64_t key = valid ? (((uint64_t)__float_as_uint(acc) << 32) | (uint32_t)orig[i]) : ~0ull;
-        uint64_t cand = __ballot(key < kth);
-        while (cand) {
-            const int c = __ffsll((unsigned long long)cand) - 1;
-            cand &= cand - 1;
-            const uint64_t ck = readlane_u64(key, c);
-            if (ck < kth) {
-                const uint64_t moved = __ballot(li > ck);  // entries at and after the insertion rank
-                const int pos = __ffsll((unsigned long long)moved) - 1;
-                const uint64_t up = __shfl_up(li, 1);
-                li = (lane < pos) ? li : (lane == pos ? ck : up);
-                if (lane >= K) li = ~0ull;
-                kth = readlane_u64(li, K - 1);
+        uint64_t key[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int j = 0; j < D; j++) {
+                const float t = qv[j] - ((j < a.d) ? x[u][j] : 0.0f);
+                acc = fmaf(t, t, acc);
+            }
+            key[u] = valid[u] ? (((uint64_t)__float_as_uint(acc) << 32) | (uint32_t)o[u]) : ~0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            uint64_t cand = __ballot(key[u] < kth);
+            while (cand) {
+                const int c = __ffsll((unsigned long long)cand) - 1;
+                cand &= cand - 1;
+                const uint64_t ck = readlane_u64(key[u], c);
+                if (ck < kth) {
+                    const uint64_t moved = __ballot(li > ck);  // entries at and after the insertion rank
+                    const int pos = __ffsll((unsigned long long)moved) - 1;
+                    const uint64_t up = __shfl_up(li, 1);
+                    li = (lane < pos) ? li : (lane == pos ? ck : up);
+                    if (lane >= K) li = ~0ull;
+                    kth = readlane_u64(li, K - 1);
+                }
             }
         }
     }

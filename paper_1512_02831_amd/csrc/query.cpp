@@ -266,7 +266,8 @@ struct Timer {
 struct Run {
     Tree &t;
     hipStream_t s;
-    const float *dQ;
+    const float *dQ;               // query coordinates as numbered inside the call
+    const int32_t *perm = nullptr;  // internal number -> caller's query (null: identity)
     int64_t m;
     int k, K, d, h, nleaf, kbits;
     bool tracing;
@@ -291,6 +292,7 @@ struct Run {
         t.d_tq.ensure(sizeof(int32_t) * (size_t)m);
         t.d_hist.ensure(sizeof(uint32_t) * sort_hist_words(m));
         t.d_cnt.ensure(sizeof(int32_t) * (size_t)nleaf);
+        t.d_cnt0.ensure(sizeof(int32_t) * (size_t)nleaf);
         t.d_off.ensure(sizeof(int32_t) * (size_t)(nleaf + 1));
         t.d_tiles.ensure(sizeof(int32_t) * 2 * (size_t)(nleaf + 1));
         if (!t.resident) t.h_tiles.ensure(sizeof(int32_t) * 3 * (size_t)(nleaf + 1));
@@ -337,13 +339,23 @@ struct Run {
     }
 
     // Sort the pending list, compute buffer offsets and work items, read the counters back.
-    void sort_and_offsets(int64_t count)
+    // With runs, the per-leaf counts come from the runs of the sorted list (the fetch
+    // did not count); otherwise from the fetch's counters.
+    void sort_and_offsets(int64_t count, bool runs = false)
     {
         int which = launch_sort_pairs(leafbuf[cur], qbuf[cur], leafbuf[1 - cur], qbuf[1 - cur], count, kbits,
                                       t.d_hist.as<uint32_t>(), s);
         if (which) cur = 1 - cur;
-        launch_leaf_offsets(cnt, t.d_leaf_off.as<int32_t>(), nleaf, SCAN_QT, SCAN_DENSE_MIN, t.d_off.as<int32_t>(),
-                            t.d_tiles.as<int32_t>(), t.d_tiles.as<int32_t>() + nleaf + 1, ctl, s);
+        int32_t *start = nullptr;
+        if (runs) {
+            start = t.d_cnt0.as<int32_t>();
+            launch_fill_i32(cnt, 0, nleaf, s);
+            launch_fill_i32(start, 0, nleaf, s);
+            launch_run_bounds(leafbuf[cur], count, nleaf, start, cnt, s);
+        }
+        launch_leaf_offsets(cnt, start, t.d_leaf_off.as<int32_t>(), nleaf, SCAN_QT, SCAN_DENSE_MIN,
+                            t.d_off.as<int32_t>(), t.d_tiles.as<int32_t>(), t.d_tiles.as<int32_t>() + nleaf + 1, ctl,
+                            s);
         if (!t.resident) {
             BKD_HIP(hipMemcpyAsync(t.h_tiles.p, t.d_tiles.p, sizeof(int32_t) * 2 * (size_t)(nleaf + 1),
                                    hipMemcpyDeviceToHost, s));
@@ -513,26 +525,43 @@ struct Run {
     {
         // first round: every query descends from the root
         FetchSpec f0{nullptr, 0, 0, 1, 0, m};
+        f0.count_leaves = t.sweep;
         find_leaf(f0, 0);
         if (t.sweep) {
             sweep();
             return;
         }
         int64_t P = m;  // pending entries (leaf order after each sort; finished ones sort last)
+        bool first = true;
         for (;;) {
-            sort_and_offsets(P);
+            sort_and_offsets(P, true);
             P = hctl[CTL_V];
             if (P == 0) {
                 end_call();
                 break;
             }
+            if (first && !tracing) localize();
+            first = false;
             if (t.resident) scan_resident();
             else scan_all_chunks();
             end_call();
-            launch_fill_i32(cnt, 0, nleaf, s);
             FetchSpec f{qbuf[cur], 0, P, std::max<int64_t>(P, 1), 0, 0};
+            f.count_leaves = false;
             find_leaf(f, 0);
         }
+    }
+
+    // Renumber the queries in first-leaf order (the pending list right after the
+    // first sort), so that the queries of one buffer have neighbouring numbers.
+    // Results are independent of numbering; traces keep the caller's numbers.
+    void localize()
+    {
+        t.d_Qp.ensure(sizeof(float) * (size_t)m * d);
+        t.d_perm.ensure(sizeof(int32_t) * (size_t)m);
+        launch_localize(qbuf[cur], leafbuf[cur], m, d, dQ, t.d_Qp.as<float>(), t.d_perm.as<int32_t>(),
+                        t.d_node.as<int32_t>(), h, s);
+        dQ = t.d_Qp.as<float>();
+        perm = t.d_perm.as<int32_t>();
     }
 
     // Chunk sweep over a streamed, leaf-aligned structure.  Pending entries live in one
@@ -597,7 +626,7 @@ struct Run {
                 BKD_HIP(hipMemcpyAsync(Rq, sq, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
             }
             int32_t *dtiles = t.d_tiles.as<int32_t>();
-            launch_leaf_offsets(cnt + lf, t.d_leaf_off.as<int32_t>() + lf, nl, SCAN_QT, SCAN_DENSE_MIN,
+            launch_leaf_offsets(cnt + lf, nullptr, t.d_leaf_off.as<int32_t>() + lf, nl, SCAN_QT, SCAN_DENSE_MIN,
                                 t.d_off.as<int32_t>() + lf, dtiles + lf, dtiles + nleaf + 1 + lf, ctl, s);
             BKD_HIP(hipMemcpyAsync(t.h_tiles.as<int32_t>() + lf, dtiles + lf, sizeof(int32_t) * (nl + 1),
                                    hipMemcpyDeviceToHost, s));
@@ -641,7 +670,8 @@ void tree_query_device(Tree &t, const float *dQ, int64_t m, int k, int64_t *d_id
     launch_init_state(t.d_node.as<int32_t>(), t.d_keys.as<uint64_t>(), m, r.K, s);
     if (t.M < 0) r.lockstep();
     else r.algorithm1();
-    launch_finalize(t.d_keys.as<uint64_t>(), r.K, k, m, d_idx, d_dist, (t.opt.flags & BKD_FLAG_SQUARED) != 0, s);
+    launch_finalize(t.d_keys.as<uint64_t>(), r.K, k, m, r.perm, d_idx, d_dist, (t.opt.flags & BKD_FLAG_SQUARED) != 0,
+                    s);
     r.readback();
     std::memcpy(&t.stats.visits, r.hctl + CTL_VISITS_LO, 8);
     std::memcpy(&t.stats.dense_pairs, r.hctl + CTL_DPAIRS_LO, 8);

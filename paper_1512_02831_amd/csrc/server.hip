@@ -228,7 +228,7 @@ static void session_round(Session &S, int64_t nnew)
                                   [&] { int b = 1; while ((1ll << b) <= nleaf) b++; return b; }(),
                                   S.hist.as<uint32_t>(), S.s);
     if (which) S.cur = 1 - S.cur;
-    launch_leaf_offsets(S.cnt.as<int32_t>(), T.d_leaf_off.as<int32_t>(), nleaf, SCAN_QT, SCAN_DENSE_MIN,
+    launch_leaf_offsets(S.cnt.as<int32_t>(), nullptr, T.d_leaf_off.as<int32_t>(), nleaf, SCAN_QT, SCAN_DENSE_MIN,
                         S.off.as<int32_t>(), S.tiles.as<int32_t>(), S.tiles.as<int32_t>() + nleaf + 1, ctl, S.s);
     BKD_HIP(hipMemcpyAsync(hctl, ctl, sizeof(int32_t) * CTL_WORDS, hipMemcpyDeviceToHost, S.s));
     BKD_HIP(hipStreamSynchronize(S.s));
