@@ -213,7 +213,8 @@ struct ScanArgs {
     float filter_coef;        // 1 - c(d), c(d) the relative error band of the filter
 };
 
-// Relative error band c(d) of the dense scan's inner-product filter (see leaf_scan.h).
+// Relative error band c of the dense scan's inner-product filter: 2^-12 for the
+// bfloat16-split matrix-core inner product (derivation beside the kernel).
 float filter_band(int d);
 
 // Dispatch on padded dimension and key capacity; sparse = 0: dense items, 1: sparse items.

@@ -7,23 +7,26 @@
 //
 // Matrix-core filter.  Once every query of a wave has K candidates, a pair is
 // first tested with the expansion |q-x|^2 = |q'|^2 + |x'|^2 - 2<q',x'> on
-// coordinates relative to the leaf centre c (q' = q-c, x' = x-c, both rounded
-// to float32).  The inner products of 32 points against the wave's 64 queries
-// are two 32x32 float32 MFMA tiles (v_mfma_f32_32x32x2f32, two coordinates
-// per step), so the vector unit only does one subtraction and half a max per
-// pair.  A pair passes when  <q',x'> - (1-c(d)) |x'|^2/2 >= ((1-c(d)) |q'|^2
-// - thr)/2 - eta, thr the query's current K-th squared distance.  With
-// S = |q'|^2 + |x'|^2 the computed expansion is within (4d + 14) 2^-24 S of
-// the float32 distance when every float32 operation rounds to nearest, and
-// within twice that when the matrix unit's inner product errs by up to 2^-23
-// per operation in any order (truncating arithmetic); c(d) = 4 (4d + 14)
-// 2^-24 covers both and the final combination's own rounding (a borderline
-// pair has thr <= 2S).  eta = 2^-120 covers products flushed to zero below the
-// normal range.  Passing pairs go to the lane owning the query, which re-checks
-// them with the exact float32 distance, so keys and results are bit-identical
-// to the exact path.  A wave holding a query whose list is not full yet (a
-// first visit) takes the exact path, every point through the float32
-// distance, 32 points at a time until all its lists are full.
+// coordinates relative to the leaf centre c (q' = q-c, x' = x-c, rounded to
+// float32).  The inner products of 32 points against the wave's 64 queries
+// are two 32x32 tiles on the matrix cores: every centred coordinate is split
+// into bfloat16 parts hi + lo, and <q',x'> ~ xl.qh + xh.ql + xh.qh takes three
+// v_mfma_f32_32x32x16_bf16 per tile and 16 coordinates, a third of the
+// matrix-core time of float32 MFMA.  The vector unit then does one
+// subtraction and half a max per pair.  A pair passes when
+// <q',x'> - (1-c) |x'|^2/2 >= ((1-c) |q'|^2 - thr)/2 - eta, thr the query's
+// current K-th squared distance.  With S = |q'|^2 + |x'|^2, the dropped split
+// terms are at most 3 2^-16 sum |q'_j x'_j| <= 1.5 2^-16 S per inner product,
+// the float32 accumulation in the matrix unit (any order, rounding either
+// way) and every other float32 step add well under 2^-16 S, so the expansion
+// is within 2^-14 S of the float32 distance; c = 2^-12 is four times that and
+// also covers the final comparison's rounding (a borderline pair has
+// thr <= 2S).  eta = 2^-100 covers parts and products flushed to zero below
+// the normal range.  Passing pairs go to the lane owning the query, which
+// re-checks them with the exact float32 distance, so keys and results are
+// bit-identical to the exact path.  A wave holding a query whose list is not
+// full yet (a first visit) takes the exact path, every point through the
+// float32 distance, 32 points at a time until all its lists are full.
 //
 // Squared distances follow the float32 reading: t = q_j - x_j rounded, then
 // acc = fma(t, t, acc) for j = 0..d-1 from +0.  Padding dimensions hold zero in
@@ -69,20 +72,30 @@ __device__ inline int xcd_item(int b, int grid)
 }
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// Absolute slack of the matrix-core filter: covers products that the matrix
-// unit may flush to zero when they fall below the float32 normal range.
-constexpr float FILTER_ABS_SLACK = 0x1p-120f;
+// Absolute slack of the matrix-core filter: covers split parts and products
+// that may be flushed to zero below the normal range (for any finite S).
+constexpr float FILTER_ABS_SLACK = 0x1p-100f;
+
+// A float32 value as the sum of two bfloat16 values (round to nearest even
+// twice); hi + lo differs from x by at most 2^-16 |x|.
+__device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo)
+{
+    hi = static_cast<__bf16>(x);
+    lo = static_cast<__bf16>(x - static_cast<float>(hi));
+}
 
 template <int D, int K>
 __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
 {
     constexpr int DS = (D + 3) & ~3;   // row of the exact copy, padded for float4 reads
-    constexpr int SM = (D + 1) / 2;    // matrix-core steps of two coordinates
+    constexpr int KB = (D + 15) / 16;  // matrix-core steps of sixteen coordinates
     constexpr int PT = D > 16 ? SCAN_PT / 2 : SCAN_PT;  // points per LDS tile
     constexpr int NB = PT / 32;        // 32-point blocks per tile
     __shared__ float4 xs[PT * DS / 4];  // original coordinates, point-major (exact distances)
-    __shared__ float xa[NB * SM * 64];  // centred coordinates in matrix-core operand order
+    // centred coordinates in matrix-core operand order: [block][step][lane] -> (hi x8, lo x8)
+    __shared__ bf16x8 xa[NB * KB * 64 * 2];
     __shared__ float bs[PT];            // (1 - c) |x - centre|^2 / 2, +inf on padding rows
     __shared__ int32_t os[PT];
 
@@ -135,16 +148,25 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
 
     // Matrix-core operands of the filter.  The wave's 64 queries form two
     // column tiles of 32; lane l supplies query (32 t + l % 32), coordinates
-    // 2 s + l / 32 for step s, and holds that query's threshold.
-    float qb[2][SM], aq[2];
+    // 16 s + 8 (l / 32) .. + 7 of step s as bfloat16 hi and lo parts, and holds
+    // that query's threshold.
+    bf16x8 qh[2][KB], ql[2][KB];
+    float aq[2];
 #pragma unroll
     for (int t = 0; t < 2; t++) {
         const int src = 32 * t + col;
 #pragma unroll
-        for (int s2 = 0; s2 < SM; s2++) {
-            const float v0 = __shfl(qc[2 * s2], src);
-            const float v1 = (2 * s2 + 1 < D) ? __shfl(qc[2 * s2 + 1 < D ? 2 * s2 + 1 : 0], src) : 0.0f;
-            qb[t][s2] = half ? v1 : v0;
+        for (int s2 = 0; s2 < KB; s2++) {
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int j0 = 16 * s2 + e, j1 = 16 * s2 + 8 + e;
+                const float v0 = (j0 < D) ? __shfl(qc[j0 < D ? j0 : 0], src) : 0.0f;
+                const float v1 = (j1 < D) ? __shfl(qc[j1 < D ? j1 : 0], src) : 0.0f;
+                __bf16 h, l;
+                split_bf16(half ? v1 : v0, h, l);
+                qh[t][s2][e] = h;
+                ql[t][s2][e] = l;
+            }
         }
         aq[t] = __shfl(own_aq(), src);
     }
@@ -175,12 +197,19 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
     // register r of lane l holds point 32 b + (r % 4) + 8 (r / 4) + 4 (l / 32)
     // against query (32 t + l % 32).
     auto filter_block = [&](int b, int np) {
+        // <q',x'> ~ xl.qh + xh.ql + xh.qh (the lo.lo term and the split
+        // remainders stay within 3 2^-16 sum |q'_j x'_j|)
         f32x16 c0 = {}, c1 = {};
 #pragma unroll
-        for (int s2 = 0; s2 < SM; s2++) {
-            const float av = xa[(b * SM + s2) * 64 + lane];
-            c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, qb[0][s2], c0, 0, 0, 0);
-            c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, qb[1][s2], c1, 0, 0, 0);
+        for (int s2 = 0; s2 < KB; s2++) {
+            const bf16x8 ah = xa[((b * KB + s2) * 64 + lane) * 2];
+            const bf16x8 al = xa[((b * KB + s2) * 64 + lane) * 2 + 1];
+            c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, qh[0][s2], c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, qh[1][s2], c1, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, ql[0][s2], c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, ql[1][s2], c1, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, qh[0][s2], c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, qh[1][s2], c1, 0, 0, 0);
         }
         float bv[16];
 #pragma unroll
@@ -280,14 +309,27 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
         if (tid < npad) {
             const bool live = tid < np;
             float *ro = reinterpret_cast<float *>(xs) + tid * DS;
-            float *ra = xa + (tid >> 5) * SM * 64 + (tid & 31);
+            bf16x8 *ra = xa + ((tid >> 5) * KB * 64 + (tid & 31)) * 2;
             float Xn = 0.0f;
+            bf16x8 vh[2 * KB], vl[2 * KB];
 #pragma unroll
-            for (int j = 0; j < DS; j++) {
-                const float c = (live && j < a.d) ? pre[j] - cr[j] : 0.0f;
-                ro[j] = pre[j];
-                if (j < 2 * SM) ra[(j >> 1) * 64 + 32 * (j & 1)] = c;
+            for (int j = 0; j < 16 * KB; j++) {
+                const float c = (live && j < a.d && j < D) ? pre[j < DS ? j : 0] - cr[j < DS ? j : 0] : 0.0f;
+                if (j < DS) ro[j] = pre[j];
+                __bf16 h, l;
+                split_bf16(c, h, l);
+                vh[j >> 3][j & 7] = h;
+                vl[j >> 3][j & 7] = l;
                 Xn = fmaf(c, c, Xn);
+            }
+            // step s, half h of the point's coordinates go to lane slot (tid % 32) + 32 h
+#pragma unroll
+            for (int s2 = 0; s2 < KB; s2++) {
+#pragma unroll
+                for (int h2 = 0; h2 < 2; h2++) {
+                    ra[(s2 * 64 + 32 * h2) * 2] = vh[2 * s2 + h2];
+                    ra[(s2 * 64 + 32 * h2) * 2 + 1] = vl[2 * s2 + h2];
+                }
             }
             bs[tid] = live ? 0.5f * (coef * Xn) : INFINITY;
             os[tid] = pre_o;

@@ -14,7 +14,16 @@ The inner product may also come from a matrix unit that adds two products
 per step in an unspecified order and may truncate instead of rounding to
 nearest (error up to 2^-23 per operation).  The second set of tests emulates
 that arithmetic in every add order, with both rounding modes, and checks the
-expansion against twice the bound, which c(d) still covers with a factor 2.
+expansion against twice the bound.
+
+The dense scan itself forms the inner product from bfloat16 parts: each
+centred float32 coordinate v is split as hi = bf16(v), lo = bf16(v - hi), and
+<q',x'> is taken as sum(xl qh + xh ql + xh qh) over three matrix-unit calls
+whose float32 accumulation may round either way in any order.  The dropped
+terms are at most 3 2^-16 sum |q'_j x'_j|, so the expansion stays within
+2^-14 S of the float32 distance; the kernel's band is c = 2^-12, four times
+that.  The third set of tests emulates this exactly and checks 2^-14 S, and
+checks that dropping one of the three products breaks it.
 """
 from __future__ import annotations
 
@@ -155,3 +164,95 @@ def test_band_matrix_unit_model_adversarial():
     q = np.float32([3.0, -1.0, 2.5]); x = np.float32([2.9, -1.2, 2.4]); cen = np.float32([0.0, 0.0, 0.0])
     approx, d2, S = filter_terms(q, x, cen, lambda a, b: sum(a[j] * b[j] for j in range(3)) * (1 + 200 * U))
     assert abs(approx - d2) > 2 * (4 * 3 + 14) * U * S
+
+
+def round_bf16(x: Fraction) -> Fraction:
+    """Round an exact rational to the nearest bfloat16 (8 significant bits, ties to even)."""
+    if x == 0:
+        return Fraction(0)
+    neg = x < 0
+    a = -x if neg else x
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    while Fraction(2) ** e > a:
+        e -= 1
+    while Fraction(2) ** (e + 1) <= a:
+        e += 1
+    q = max(e - 7, -133)
+    scaled = a / (Fraction(2) ** q)
+    n = scaled.numerator // scaled.denominator
+    rem = scaled - n
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and n % 2 == 1):
+        n += 1
+    v = Fraction(n) * Fraction(2) ** q
+    return -v if neg else v
+
+
+def split_dot(qc, xc, rnd, rng, terms=(0, 1, 2)):
+    """sum(xl qh + xh ql + xh qh): three accumulations of 16 products each, in random order."""
+    qh = [round_bf16(v) for v in qc]
+    ql = [round_bf16(v - h) for v, h in zip(qc, qh)]
+    xh = [round_bf16(v) for v in xc]
+    xl = [round_bf16(v - h) for v, h in zip(xc, xh)]
+    calls = [[xl[j] * qh[j] for j in range(len(qc))], [xh[j] * ql[j] for j in range(len(qc))],
+             [xh[j] * qh[j] for j in range(len(qc))]]
+    acc = Fraction(0)
+    for t in terms:
+        prods = calls[t]
+        order = rng.permutation(len(prods))
+        sacc = Fraction(0)
+        for o in order:
+            sacc = rnd(sacc + prods[o])
+        acc = rnd(acc + sacc)
+    return acc
+
+
+def check_split(q, x, cen, rng):
+    worst = Fraction(0)
+    for rnd in (lambda v: Fraction(round_f32(v)), round_rz):
+        approx, d2, S = filter_terms(q, x, cen, lambda a, b: split_dot(a, b, rnd, rng))
+        bound = Fraction(1, 1 << 14) * S
+        assert abs(approx - d2) <= bound + Fraction(1, 10 ** 40), (float(approx), float(d2), float(S))
+        if S > 0:
+            worst = max(worst, abs(approx - d2) / bound)
+    return worst
+
+
+def test_band_bf16_split_random():
+    rng = np.random.default_rng(5)
+    worst = Fraction(0)
+    for d in (3, 10, 15, 16):
+        for _ in range(40):
+            cen = (rng.uniform(0, 20, d)).astype(np.float32)
+            spread = rng.choice([1e-3, 0.1, 2.0, 30.0])
+            q = (cen + rng.normal(0, spread, d)).astype(np.float32)
+            x = (cen + rng.normal(0, spread, d)).astype(np.float32)
+            worst = max(worst, check_split(q, x, cen, rng))
+    assert worst < 1
+
+
+def test_band_bf16_split_adversarial():
+    rng = np.random.default_rng(6)
+    d = 10
+    for _ in range(30):
+        base = rng.uniform(1e3, 1e4, d).astype(np.float32)
+        x = np.nextafter(base, np.float32(np.inf)) if rng.random() < 0.5 else (base + np.float32(1e-3))
+        cen = (base + rng.normal(0, 50, d)).astype(np.float32)
+        check_split(base, x.astype(np.float32), cen, rng)
+        check_split(base, base.copy(), cen, rng)
+        # coordinates whose bfloat16 parts round half-way
+        hw = (cen + np.float32(1.0 + 2.0 ** -8 + 2.0 ** -17)).astype(np.float32)
+        check_split(hw, cen.copy(), cen, rng)
+
+
+def test_band_bf16_split_needs_all_three_products():
+    rng = np.random.default_rng(7)
+    broke = False
+    for _ in range(20):
+        d = 10
+        cen = np.zeros(d, np.float32)
+        q = rng.normal(0, 3, d).astype(np.float32)
+        x = rng.normal(0, 3, d).astype(np.float32)
+        approx, d2, S = filter_terms(q, x, cen, lambda a, b: split_dot(a, b, lambda v: Fraction(round_f32(v)), rng,
+                                                                         terms=(1, 2)))
+        broke |= abs(approx - d2) > Fraction(1, 1 << 14) * S
+    assert broke
