@@ -91,12 +91,16 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
 {
     constexpr int DS = (D + 3) & ~3;   // row of the exact copy, padded for float4 reads
     constexpr int KB = (D + 15) / 16;  // matrix-core steps of sixteen coordinates
+    // With a free slot after the coordinates, -bs rides in the point operand
+    // (times 1 in the query operand), so the accumulator already holds
+    // <q',x'> - bs and the vector unit only takes the max.
+    constexpr bool FOLD = D + 1 <= 16 * KB;
     constexpr int PT = D > 16 ? SCAN_PT / 2 : SCAN_PT;  // points per LDS tile
     constexpr int NB = PT / 32;        // 32-point blocks per tile
     __shared__ float4 xs[PT * DS / 4];  // original coordinates, point-major (exact distances)
     // centred coordinates in matrix-core operand order: [block][step][lane] -> (hi x8, lo x8)
     __shared__ bf16x8 xa[NB * KB * 64 * 2];
-    __shared__ float bs[PT];            // (1 - c) |x - centre|^2 / 2, +inf on padding rows
+    __shared__ float bs[FOLD ? 1 : PT];  // (1 - c) |x - centre|^2 / 2, +inf on padding rows
     __shared__ int32_t os[PT];
 
     int item = xcd_item(blockIdx.x, gridDim.x);
@@ -160,8 +164,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
 #pragma unroll
             for (int e = 0; e < 8; e++) {
                 const int j0 = 16 * s2 + e, j1 = 16 * s2 + 8 + e;
-                const float v0 = (j0 < D) ? __shfl(qc[j0 < D ? j0 : 0], src) : 0.0f;
-                const float v1 = (j1 < D) ? __shfl(qc[j1 < D ? j1 : 0], src) : 0.0f;
+                const float v0 = (j0 < D) ? __shfl(qc[j0 < D ? j0 : 0], src) : (FOLD && j0 == D) ? 1.0f : 0.0f;
+                const float v1 = (j1 < D) ? __shfl(qc[j1 < D ? j1 : 0], src) : (FOLD && j1 == D) ? 1.0f : 0.0f;
                 __bf16 h, l;
                 split_bf16(half ? v1 : v0, h, l);
                 qh[t][s2][e] = h;
@@ -214,17 +218,26 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
         float bv[16];
 #pragma unroll
         for (int g = 0; g < 4; g++) {
-            const float4 b4 = *reinterpret_cast<const float4 *>(bs + 32 * b + 8 * g + 4 * half);
-            bv[4 * g] = b4.x;
-            bv[4 * g + 1] = b4.y;
-            bv[4 * g + 2] = b4.z;
-            bv[4 * g + 3] = b4.w;
+            if constexpr (FOLD) {
+                bv[4 * g] = bv[4 * g + 1] = bv[4 * g + 2] = bv[4 * g + 3] = 0.0f;
+            } else {
+                const float4 b4 = *reinterpret_cast<const float4 *>(bs + 32 * b + 8 * g + 4 * half);
+                bv[4 * g] = b4.x;
+                bv[4 * g + 1] = b4.y;
+                bv[4 * g + 2] = b4.z;
+                bv[4 * g + 3] = b4.w;
+            }
         }
         float m0 = -INFINITY, m1 = -INFINITY;
 #pragma unroll
         for (int r = 0; r < 16; r++) {
-            m0 = fmaxf(m0, c0[r] - bv[r]);
-            m1 = fmaxf(m1, c1[r] - bv[r]);
+            if constexpr (FOLD) {
+                m0 = fmaxf(m0, c0[r]);
+                m1 = fmaxf(m1, c1[r]);
+            } else {
+                m0 = fmaxf(m0, c0[r] - bv[r]);
+                m1 = fmaxf(m1, c1[r] - bv[r]);
+            }
         }
         if (!__any(m0 >= aq[0] || m1 >= aq[1])) return;
         // Some pair passed: hand each passing (point, query) to the lane that
@@ -311,16 +324,24 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
             float *ro = reinterpret_cast<float *>(xs) + tid * DS;
             bf16x8 *ra = xa + ((tid >> 5) * KB * 64 + (tid & 31)) * 2;
             float Xn = 0.0f;
+            float cv[16 * KB];
+#pragma unroll
+            for (int j = 0; j < 16 * KB; j++) {
+                cv[j] = (live && j < a.d && j < D) ? pre[j < DS ? j : 0] - cr[j < DS ? j : 0] : 0.0f;
+                if (j < DS) ro[j] = pre[j];
+                Xn = fmaf(cv[j], cv[j], Xn);
+            }
+            const float bsv = 0.5f * (coef * Xn);
+            // padding rows: a large finite negative value keeps the split free of inf - inf
+            if constexpr (FOLD) cv[D] = live ? -bsv : -0x1p127f;
+            else bs[tid] = live ? bsv : INFINITY;
             bf16x8 vh[2 * KB], vl[2 * KB];
 #pragma unroll
             for (int j = 0; j < 16 * KB; j++) {
-                const float c = (live && j < a.d && j < D) ? pre[j < DS ? j : 0] - cr[j < DS ? j : 0] : 0.0f;
-                if (j < DS) ro[j] = pre[j];
                 __bf16 h, l;
-                split_bf16(c, h, l);
+                split_bf16(cv[j], h, l);
                 vh[j >> 3][j & 7] = h;
                 vl[j >> 3][j & 7] = l;
-                Xn = fmaf(c, c, Xn);
             }
             // step s, half h of the point's coordinates go to lane slot (tid % 32) + 32 h
 #pragma unroll
@@ -331,7 +352,6 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
                     ra[(s2 * 64 + 32 * h2) * 2 + 1] = vl[2 * s2 + h2];
                 }
             }
-            bs[tid] = live ? 0.5f * (coef * Xn) : INFINITY;
             os[tid] = pre_o;
         }
         __syncthreads();

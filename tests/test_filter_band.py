@@ -256,3 +256,40 @@ def test_band_bf16_split_needs_all_three_products():
                                                                          terms=(1, 2)))
         broke |= abs(approx - d2) > Fraction(1, 1 << 14) * S
     assert broke
+
+
+def folded_terms(q, x, cen, rnd, rng):
+    """Qn - 2 G with G = <q',x'> - |x'|^2/2 formed in one split accumulation (the norm
+    rides as one more coordinate pair (-|x'|^2/2, 1)), as the kernel does when a slot is free."""
+    d = len(q)
+    qc = [sub(f(q[j]), f(cen[j])) for j in range(d)]
+    xc = [sub(f(x[j]), f(cen[j])) for j in range(d)]
+    Qn = Xn = Fraction(0)
+    for j in range(d):
+        Qn = fmaf(qc[j], qc[j], Qn)
+        Xn = fmaf(xc[j], xc[j], Xn)
+    bs = Fraction(round_f32(Xn / 2))
+    G = split_dot(qc + [Fraction(1)], xc + [-bs], rnd, rng)
+    d2 = Fraction(0)
+    for j in range(d):
+        t = sub(f(q[j]), f(x[j]))
+        d2 = fmaf(t, t, d2)
+    return Qn - 2 * G, d2, Qn + Xn
+
+
+def test_band_bf16_split_with_folded_norm():
+    rng = np.random.default_rng(8)
+    worst = Fraction(0)
+    for d in (3, 10, 15):
+        for _ in range(40):
+            cen = (rng.uniform(0, 20, d)).astype(np.float32)
+            spread = rng.choice([1e-3, 0.1, 2.0, 30.0])
+            q = (cen + rng.normal(0, spread, d)).astype(np.float32)
+            x = (cen + rng.normal(0, spread, d)).astype(np.float32)
+            for rnd in (lambda v: Fraction(round_f32(v)), round_rz):
+                approx, d2, S = folded_terms(q, x, cen, rnd, rng)
+                bound = Fraction(1, 1 << 13) * S
+                assert abs(approx - d2) <= bound + Fraction(1, 10 ** 40)
+                if S > 0:
+                    worst = max(worst, abs(approx - d2) / bound)
+    assert worst < 1
