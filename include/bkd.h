@@ -57,6 +57,8 @@ extern "C" {
 #define BKD_FLAG_TRACE 1  /* record every fetch's (query, leaf) pairs (for parity checks)     */
 #define BKD_FLAG_TIMING 2 /* time every leaf-scan launch with HIP events                       */
 #define BKD_FLAG_SQUARED 4 /* out_dist receives the float32 squared distance, not its root      */
+#define BKD_FLAG_NO_TAIL 8 /* lock-step rounds to the end: no hand-over of the last few pending  */
+                           /* queries to one-workgroup-per-query traversals (results identical)  */
 
 typedef struct bkd_tree bkd_tree;
 

@@ -211,13 +211,26 @@ struct ScanArgs {
     uint64_t *keys;           // [m][K]
     const float *centers;     // [nleaf][d] leaf centres of the inner-product filter
     float filter_coef;        // 1 - c(d), c(d) the relative error band of the filter
+    // tail of the lock-step schedule (resident structure): pending (leaf, query) entries
+    // that each finish their whole traversal in one workgroup
+    const uint32_t *tail_leaf;
+    const int32_t *tail_q;
+    int32_t tail_count;
+    int32_t *node;            // [m] traversal state, set to DONE at the end
+    const float *split;       // [2^h - 1]
+    int h, k;                 // tree height; k of the query (pruning uses the k-th key)
+    int32_t *ctl;             // visit and pair counters
 };
+
+// Pending queries at or below which the lock-step rounds hand over to the tail kernel.
+constexpr int64_t TAIL_MAX = 2048;
 
 // Relative error band c of the dense scan's inner-product filter: 2^-12 for the
 // bfloat16-split matrix-core inner product (derivation beside the kernel).
 float filter_band(int d);
 
-// Dispatch on padded dimension and key capacity; sparse = 0: dense items, 1: sparse items.
+// Dispatch on padded dimension and key capacity; sparse = 0: dense items, 1: sparse items,
+// 2: the tail (tail_count pending entries, one workgroup each).
 void launch_leaf_scan(const ScanArgs &a, int K, int sparse, hipStream_t s);
 int padded_dim(int d);
 int key_capacity(int k);

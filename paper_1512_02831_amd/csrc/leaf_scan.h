@@ -46,6 +46,7 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "traverse.h"
 
 namespace bkd {
 
@@ -461,6 +462,124 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
         }
     }
     if (lane < K) kp[lane] = li;
+}
+
+// Tail of the lock-step schedule.  When only a few queries are pending, a
+// round costs a dozen launches for little work, and the late rounds are
+// spent on a handful of queries with long traversals.  Here each pending
+// query finishes its whole traversal in one workgroup of four waves: the
+// waves split each leaf's points, keep their new candidates (keys below the
+// query's K-th) as lane-distributed lists, and merge them into the query's
+// list in LDS order; then every lane walks to the next leaf with the same
+// state (Sections 2.3, 2.4), so the walk is uniform.  Results do not depend
+// on the schedule: a query's visits and its list are its own.
+constexpr int TAIL_THREADS = 256;
+constexpr int TAIL_LDS_SPLITS = 2047;
+
+template <int K> __device__ inline void lane_list_insert(uint64_t &li, uint64_t ck, int lane)
+{
+    const uint64_t moved = __ballot(li > ck);  // entries at and after the insertion rank
+    const int pos = __ffsll((unsigned long long)moved) - 1;
+    const uint64_t up = __shfl_up(li, 1);
+    li = (lane < pos) ? li : (lane == pos ? ck : up);
+    if (lane >= K) li = ~0ull;
+}
+
+template <int D, int K> __global__ __launch_bounds__(TAIL_THREADS) void k_tail(ScanArgs a)
+{
+    constexpr int W = TAIL_THREADS / 64;
+    constexpr int U = 4;
+    __shared__ float split_lds[TAIL_LDS_SPLITS];
+    __shared__ uint64_t cand[W][K];
+    const int h = a.h;
+    const int lds_nodes = min((1 << h) - 1, TAIL_LDS_SPLITS);
+    for (int i = threadIdx.x; i < lds_nodes; i += TAIL_THREADS) split_lds[i] = a.split[i];
+    __syncthreads();
+
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int32_t q = a.tail_q[blockIdx.x];
+    int32_t leaf = (int32_t)a.tail_leaf[blockIdx.x];
+    const float *qp = a.Q + (int64_t)q * a.d;
+    float qv[D];
+#pragma unroll
+    for (int j = 0; j < D; j++) qv[j] = (j < a.d) ? qp[j] : 0.0f;
+    uint64_t *kp = a.keys + (int64_t)q * K;
+    uint64_t li = (lane < K) ? kp[lane] : ~0ull;  // the query's list, lane i holds the i-th smallest
+    const int32_t first = (1 << h) - 1;
+    long long visits = 0, pairs = 0;
+    for (;;) {
+        const int64_t l0 = a.leaf_off[leaf];
+        const int len = a.leaf_off[leaf + 1] - (int32_t)l0;
+        const float *X = a.base + a.blk[leaf];
+        const int32_t *orig = reinterpret_cast<const int32_t *>(X) + (int64_t)a.d * len;
+        const uint64_t kthK = readlane_u64(li, K - 1);
+        // this wave's part of the leaf; its new candidates all lie below kthK
+        const int part = (len + W - 1) / W;
+        const int lo = min(len, w * part), hi = min(len, lo + part);
+        uint64_t ni = ~0ull, nth = kthK;
+        for (int pb = lo; pb < hi; pb += 64 * U) {
+            float x[U][D];
+            int32_t o[U];
+            bool valid[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int p = pb + 64 * u + lane;
+                valid[u] = p < hi;
+                const int i = valid[u] ? p : lo;
+#pragma unroll
+                for (int j = 0; j < D; j++) x[u][j] = X[(j < a.d ? j : 0) * len + i];
+                o[u] = orig[i];
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int j = 0; j < D; j++) {
+                    const float t = qv[j] - ((j < a.d) ? x[u][j] : 0.0f);
+                    acc = fmaf(t, t, acc);
+                }
+                const uint64_t key = valid[u] ? (((uint64_t)__float_as_uint(acc) << 32) | (uint32_t)o[u]) : ~0ull;
+                uint64_t cb = __ballot(key < nth);
+                while (cb) {
+                    const int c = __ffsll((unsigned long long)cb) - 1;
+                    cb &= cb - 1;
+                    const uint64_t ck = readlane_u64(key, c);
+                    if (ck < nth) {
+                        lane_list_insert<K>(ni, ck, lane);
+                        const uint64_t nk = readlane_u64(ni, K - 1);
+                        nth = nk < kthK ? nk : kthK;
+                    }
+                }
+            }
+        }
+        if (lane < K) cand[w][lane] = ni;
+        __syncthreads();
+        // every wave merges the candidate lists in the same order, so all copies agree
+#pragma unroll
+        for (int w2 = 0; w2 < W; w2++) {
+            const uint64_t cl = (lane < K) ? cand[w2][lane] : ~0ull;
+            uint64_t cb = __ballot(cl < readlane_u64(li, K - 1));
+            while (cb) {
+                const int c = __ffsll((unsigned long long)cb) - 1;
+                cb &= cb - 1;
+                const uint64_t ck = readlane_u64(cl, c);
+                if (ck < readlane_u64(li, K - 1)) lane_list_insert<K>(li, ck, lane);
+            }
+        }
+        __syncthreads();  // cand is written again for the next leaf
+        visits++;
+        pairs += len;
+        const uint64_t kth_key = readlane_u64(li, a.k - 1);
+        const int32_t v = next_leaf(first + leaf, qp, &kth_key, a.split, split_lds, lds_nodes, h, a.d);
+        if (v == NODE_DONE) break;
+        leaf = v - first;
+    }
+    if (w == 0 && lane < K) kp[lane] = li;
+    if (threadIdx.x == 0) {
+        a.node[q] = NODE_DONE;
+        atomicAdd((unsigned long long *)(a.ctl + CTL_VISITS_LO), (unsigned long long)visits);
+        atomicAdd((unsigned long long *)(a.ctl + CTL_SPAIRS_LO), (unsigned long long)pairs);
+    }
 }
 
 template <int D> void launch_leaf_scan_d(const ScanArgs &a, int K, int sparse, hipStream_t s);

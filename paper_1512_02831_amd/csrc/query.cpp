@@ -542,6 +542,11 @@ struct Run {
             }
             if (first && !tracing) localize();
             first = false;
+            if (t.resident && !tracing && !(t.opt.flags & BKD_FLAG_NO_TAIL) && P <= TAIL_MAX) {
+                tail(P);
+                end_call();
+                break;
+            }
             if (t.resident) scan_resident();
             else scan_all_chunks();
             end_call();
@@ -549,6 +554,24 @@ struct Run {
             f.count_leaves = false;
             find_leaf(f, 0);
         }
+    }
+
+    // The P pending entries (sorted, all live) finish their traversals in the tail kernel.
+    void tail(int64_t P)
+    {
+        ScanArgs a = scan_args(t.d_chunk[0].as<float>(), 0);
+        a.tail_leaf = leafbuf[cur];
+        a.tail_q = qbuf[cur];
+        a.tail_count = (int32_t)P;
+        a.node = t.d_node.as<int32_t>();
+        a.split = t.d_split.as<float>();
+        a.h = h;
+        a.k = k;
+        a.ctl = ctl;
+        tsparse.begin(s);
+        launch_leaf_scan(a, K, 2, s);
+        tsparse.end(s);
+        t.stats.sparse_launches++;
     }
 
     // Renumber the queries in first-leaf order (the pending list right after the

@@ -29,7 +29,7 @@ int key_capacity(int k)
 
 void launch_leaf_scan(const ScanArgs &a, int K, int sparse, hipStream_t s)
 {
-    if ((sparse ? a.sitem_count : a.item_count) <= 0) return;
+    if ((sparse == 2 ? a.tail_count : sparse ? a.sitem_count : a.item_count) <= 0) return;
     switch (padded_dim(a.d)) {
     case 2: launch_leaf_scan_d<2>(a, K, sparse, s); break;
     case 3: launch_leaf_scan_d<3>(a, K, sparse, s); break;

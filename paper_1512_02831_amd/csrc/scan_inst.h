@@ -5,7 +5,8 @@
 #define BKD_SCAN_CASE(D, KK)                                                                        \
     case KK:                                                                                        \
         if (!sparse && a.item_count > 0) k_leaf_scan<D, KK><<<grid, SCAN_THREADS, 0, s>>>(a);      \
-        if (sparse && a.sitem_count > 0) k_leaf_scan_sparse<D, KK><<<sgrid, SCAN_THREADS, 0, s>>>(a); \
+        if (sparse == 1 && a.sitem_count > 0) k_leaf_scan_sparse<D, KK><<<sgrid, SCAN_THREADS, 0, s>>>(a); \
+        if (sparse == 2 && a.tail_count > 0) k_tail<D, KK><<<(unsigned)a.tail_count, TAIL_THREADS, 0, s>>>(a); \
         break;
 
 #define BKD_SCAN_INSTANTIATE(D)                                                                     \

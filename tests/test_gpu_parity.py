@@ -189,6 +189,23 @@ def test_edge_shapes(n, m, d, k, h):
     check_trace(tr, oracle.replay(P, t_or, Q, k, B=o.buffer_size, M=o.fetch_size))
 
 
+@pytest.mark.parametrize("n,m,d,k,h", [
+    (1 << 16, 6000, 10, 10, 6),   # rounds first, then the tail below 2048 pending queries
+    (20000, 700, 5, 32, 5),       # tail right after the first round's sort
+    (5000, 300, 15, 64, 4),       # largest k in the tail
+    (3000, 2048, 3, 1, 8),        # exactly the hand-over size
+])
+def test_lockstep_tail_matches_rounds_and_oracle(n, m, d, k, h):
+    say(f"case: tail n={n} m={m} d={d} k={k} h={h}")
+    P, Q = datagen.mixture_pq(seed=n + m, n=n, m=m, d=d, comps=5)
+    tail, _, st_tail, _ = gpu_keys(P, Q, k, h, buffer_size=-1, fetch_size=-1)
+    rounds, _, st_rounds, _ = gpu_keys(P, Q, k, h, buffer_size=-1, fetch_size=-1, flags=bkd.FLAG_NO_TAIL)
+    assert np.array_equal(tail, rounds)
+    assert np.array_equal(tail, oracle.brute_f32c(P, Q, k))
+    # the same visits and pairs, whichever schedule finished the traversals
+    assert st_tail["visits"] == st_rounds["visits"] and st_tail["pairs"] == st_rounds["pairs"]
+
+
 def test_lattice_exact_including_ties():
     say("case: lattice ties")
     P = datagen.lattice(2, 1, 6000, 5, side=5)
