@@ -525,7 +525,7 @@ struct Run {
     {
         // first round: every query descends from the root
         FetchSpec f0{nullptr, 0, 0, 1, 0, m};
-        f0.count_leaves = t.sweep;
+        f0.count_leaves = false;  // per-leaf counts come from the sorted runs
         find_leaf(f0, 0);
         if (t.sweep) {
             sweep();
@@ -649,7 +649,11 @@ struct Run {
                 BKD_HIP(hipMemcpyAsync(Rq, sq, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
             }
             int32_t *dtiles = t.d_tiles.as<int32_t>();
-            launch_leaf_offsets(cnt + lf, nullptr, t.d_leaf_off.as<int32_t>() + lf, nl, SCAN_QT, SCAN_DENSE_MIN,
+            int32_t *start = t.d_cnt0.as<int32_t>();
+            launch_fill_i32(cnt + lf, 0, nl, s);
+            launch_fill_i32(start + lf, 0, nl, s);
+            launch_run_bounds(Rl, n, nleaf, start, cnt, s);
+            launch_leaf_offsets(cnt + lf, start + lf, t.d_leaf_off.as<int32_t>() + lf, nl, SCAN_QT, SCAN_DENSE_MIN,
                                 t.d_off.as<int32_t>() + lf, dtiles + lf, dtiles + nleaf + 1 + lf, ctl, s);
             BKD_HIP(hipMemcpyAsync(t.h_tiles.as<int32_t>() + lf, dtiles + lf, sizeof(int32_t) * (nl + 1),
                                    hipMemcpyDeviceToHost, s));
@@ -662,8 +666,8 @@ struct Run {
             bufq_override = nullptr;
             end_call();
             // route again in place, then move every entry to the region of its next chunk
-            launch_fill_i32(cnt + lf, 0, nl, s);
             FetchSpec f{Rq, 0, n, std::max<int64_t>(n, 1), 0, 0};
+            f.count_leaves = false;
             find_leaf_into(f, Rl, Rq, 0);
             launch_distribute(Rl, Rq, n, nleaf, chunk_of, c, rleaf, rq, m, rcnt, sleaf, sq, N, s);
             launch_restore(sleaf, sq, n, Rl, Rq, rcnt, c, N, s);

@@ -90,7 +90,7 @@ struct Session {
     int max_req = 0;
     hipStream_t s = nullptr;
     // device state
-    DevBuf Qpool, keys, node, kq, req_of, req_left, done, pleaf, pq, tleaf, tq, hist, cnt, off, tiles, ctl, newslots,
+    DevBuf Qpool, keys, node, kq, req_of, req_left, done, pleaf, pq, tleaf, tq, hist, cnt, cnt0, off, tiles, ctl, newslots,
         stage, oidx, odist, gslots;
     PinnedBuf hctl, hdone, hstage, hout;
     // host state
@@ -138,6 +138,7 @@ static void session_init(Session &S)
     S.tq.ensure(sizeof(int32_t) * cap);
     S.hist.ensure(sizeof(uint32_t) * sort_hist_words(cap));
     S.cnt.ensure(sizeof(int32_t) * nleaf);
+    S.cnt0.ensure(sizeof(int32_t) * nleaf);
     S.off.ensure(sizeof(int32_t) * (nleaf + 1));
     S.tiles.ensure(sizeof(int32_t) * 2 * (nleaf + 1));
     S.ctl.ensure(sizeof(int32_t) * CTL_WORDS);
@@ -214,8 +215,8 @@ static void session_round(Session &S, int64_t nnew)
     int32_t *ctl = S.ctl.as<int32_t>();
     int32_t *hctl = S.hctl.as<int32_t>();
     // route in place: the previous sorted list, then the admitted slots appended
-    launch_fill_i32(S.cnt.as<int32_t>(), 0, nleaf, S.s);
     FetchSpec f{qbuf[S.cur], 0, S.P, std::max<int64_t>(S.P, 1), 0, nnew};
+    f.count_leaves = false;  // per-leaf counts come from the runs of the sorted list
     f.in_list = S.newslots.as<int32_t>();
     f.kq = S.kq.as<int32_t>();
     f.req_of = S.req_of.as<int32_t>();
@@ -228,7 +229,11 @@ static void session_round(Session &S, int64_t nnew)
                                   [&] { int b = 1; while ((1ll << b) <= nleaf) b++; return b; }(),
                                   S.hist.as<uint32_t>(), S.s);
     if (which) S.cur = 1 - S.cur;
-    launch_leaf_offsets(S.cnt.as<int32_t>(), nullptr, T.d_leaf_off.as<int32_t>(), nleaf, SCAN_QT, SCAN_DENSE_MIN,
+    launch_fill_i32(S.cnt.as<int32_t>(), 0, nleaf, S.s);
+    launch_fill_i32(S.cnt0.as<int32_t>(), 0, nleaf, S.s);
+    launch_run_bounds(leafbuf[S.cur], total, nleaf, S.cnt0.as<int32_t>(), S.cnt.as<int32_t>(), S.s);
+    launch_leaf_offsets(S.cnt.as<int32_t>(), S.cnt0.as<int32_t>(), T.d_leaf_off.as<int32_t>(), nleaf, SCAN_QT,
+                        SCAN_DENSE_MIN,
                         S.off.as<int32_t>(), S.tiles.as<int32_t>(), S.tiles.as<int32_t>() + nleaf + 1, ctl, S.s);
     BKD_HIP(hipMemcpyAsync(hctl, ctl, sizeof(int32_t) * CTL_WORDS, hipMemcpyDeviceToHost, S.s));
     BKD_HIP(hipStreamSynchronize(S.s));
