@@ -47,6 +47,23 @@ WORKLOADS = {
 }
 
 
+def dense_scan_traffic(kernel_src="paper_1512_02831_amd/csrc/leaf_scan.h",
+                       summary="profiles/k_leaf_scan_ondevice_n2p22.md"):
+    """HBM bytes per dense-scan launch from the committed FETCH_SIZE/WRITE_SIZE summary, or None
+    when the kernel source has changed since those counters were taken."""
+    import hashlib
+    try:
+        text = open(os.path.join(ROOT, summary)).read()
+        src = open(os.path.join(ROOT, kernel_src), "rb").read()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in text.splitlines()
+                  if line.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
+    if "source_sha256" not in fields or fields["source_sha256"].split()[0] != hashlib.sha256(src).hexdigest():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def h2d_rate_gbs(torch, nbytes=1 << 30):
     """Pinned host-to-device copy rate of this machine (one 1 GiB copy after a warm-up)."""
     src = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
@@ -349,7 +366,7 @@ def main():
         "peak": FP32_MATRIX_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / FP32_MATRIX_PEAK_TFLOPS, 4),
-        "traffic": None,
+        "traffic": dense_scan_traffic() if args.workload == "ondevice" else None,
         "avg_launch_ms": round(acc["dense_ms"] / max(acc["dense_launches"], 1), 4),
         "launches_per_step": acc["dense_launches"] / args.steps,
         "pairs_per_launch": acc["dense_pairs"] // max(acc["dense_launches"], 1),
