@@ -341,6 +341,20 @@ int bkd_request_times(bkd_server *srv, int64_t req_id, double *submit_s, double 
 /* Forget a finished request (its id becomes unknown). */
 int bkd_release(bkd_server *srv, int64_t req_id);
 
+/* Counters of a server since its creation, summed over its sessions. */
+typedef struct bkd_server_stats {
+    int32_t sessions;       /* (tree, key capacity) sessions created                         */
+    int64_t rounds;         /* routing rounds                                                 */
+    int64_t scan_rounds;    /* rounds that scanned buffers with the dense/sparse kernels      */
+    int64_t tail_rounds;    /* rounds handed to the one-workgroup-per-query tail kernel       */
+    int64_t queries;        /* queries admitted                                               */
+    double busy_s;          /* host wall time inside rounds, summed over sessions             */
+    double admit_s;         /* host wall time admitting requests (copies in), summed          */
+    double complete_s;      /* host wall time delivering results (copies out), summed         */
+} bkd_server_stats;
+
+int bkd_server_stats_get(bkd_server *srv, bkd_server_stats *out);
+
 /* Stop every session and free the server (trees are not freed). */
 int bkd_server_destroy(bkd_server *srv);
 

@@ -84,6 +84,7 @@ _PROTOS = {
     "bkd_wait": (ctypes.c_int, [_V, _I64, _I64]),
     "bkd_cancel": (ctypes.c_int, [_V, _I64]),
     "bkd_request_times": (ctypes.c_int, [_V, _I64, _V, _V, _V]),
+    "bkd_server_stats_get": (ctypes.c_int, [_V, _V]),
     "bkd_release": (ctypes.c_int, [_V, _I64]),
     "bkd_server_destroy": (ctypes.c_int, [_V]),
 }
@@ -433,6 +434,19 @@ def poll(srv: Server, req: Request) -> int:
 
 def cancel(srv: Server, req: Request):
     _check(lib().bkd_cancel(srv.handle, req.id))
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("sessions", ctypes.c_int32), ("rounds", ctypes.c_int64), ("scan_rounds", ctypes.c_int64),
+                ("tail_rounds", ctypes.c_int64), ("queries", ctypes.c_int64), ("busy_s", ctypes.c_double),
+                ("admit_s", ctypes.c_double), ("complete_s", ctypes.c_double)]
+
+
+def server_stats(srv: Server) -> dict:
+    """``bkd_server_stats_get``."""
+    st = ServerStats()
+    _check(lib().bkd_server_stats_get(srv.handle, ctypes.byref(st)))
+    return {f: getattr(st, f) for f, _ in ServerStats._fields_}
 
 
 def request_times(srv: Server, req: Request):

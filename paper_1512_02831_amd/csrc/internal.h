@@ -220,6 +220,11 @@ struct ScanArgs {
     const float *split;       // [2^h - 1]
     int h, k;                 // tree height; k of the query (pruning uses the k-th key)
     int32_t *ctl;             // visit and pair counters
+    // served form: per-query k, owning request, outstanding-query counters, completion list
+    const int32_t *kq;
+    const int32_t *req_of;
+    int32_t *req_left;
+    int32_t *done_list;
 };
 
 // Pending queries at or below which the lock-step rounds hand over to the tail kernel.

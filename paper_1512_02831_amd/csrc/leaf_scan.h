@@ -99,8 +99,9 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
     constexpr int PT = D > 16 ? SCAN_PT / 2 : SCAN_PT;  // points per LDS tile
     constexpr int NB = PT / 32;        // 32-point blocks per tile
     __shared__ float4 xs[PT * DS / 4];  // original coordinates, point-major (exact distances)
-    // centred coordinates in matrix-core operand order: [block][step][lane] -> (hi x8, lo x8)
-    __shared__ bf16x8 xa[NB * KB * 64 * 2];
+    // centred coordinates in matrix-core operand order, hi and lo parts in separate planes
+    // ([block][step][lane], 16 bytes per lane: every read and write is one contiguous kilobyte)
+    __shared__ bf16x8 xah[NB * KB * 64], xal[NB * KB * 64];
     __shared__ float bs[FOLD ? 1 : PT];  // (1 - c) |x - centre|^2 / 2, +inf on padding rows
     __shared__ int32_t os[PT];
 
@@ -207,8 +208,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
         f32x16 c0 = {}, c1 = {};
 #pragma unroll
         for (int s2 = 0; s2 < KB; s2++) {
-            const bf16x8 ah = xa[((b * KB + s2) * 64 + lane) * 2];
-            const bf16x8 al = xa[((b * KB + s2) * 64 + lane) * 2 + 1];
+            const bf16x8 ah = xah[(b * KB + s2) * 64 + lane];
+            const bf16x8 al = xal[(b * KB + s2) * 64 + lane];
             c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, qh[0][s2], c0, 0, 0, 0);
             c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, qh[1][s2], c1, 0, 0, 0);
             c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, ql[0][s2], c0, 0, 0, 0);
@@ -246,11 +247,15 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
         // re-checks it with the exact float32 distance.
         // (the per-pair test is taken as <q',x'> >= aq + bs here, so that the
         // differences above need not stay live; both forms are within the band)
+        // (masks are built only for a tile that has a passing pair)
         uint32_t f0 = 0, f1 = 0;
+        if (__any(m0 >= aq[0])) {
 #pragma unroll
-        for (int r = 0; r < 16; r++) {
-            f0 |= (c0[r] >= aq[0] + bv[r]) ? (1u << r) : 0u;
-            f1 |= (c1[r] >= aq[1] + bv[r]) ? (1u << r) : 0u;
+            for (int r = 0; r < 16; r++) f0 |= (c0[r] >= aq[0] + bv[r]) ? (1u << r) : 0u;
+        }
+        if (__any(m1 >= aq[1])) {
+#pragma unroll
+            for (int r = 0; r < 16; r++) f1 |= (c1[r] >= aq[1] + bv[r]) ? (1u << r) : 0u;
         }
         const uint32_t lo0 = __shfl(f0, col), hi0 = __shfl(f0, col + 32);
         const uint32_t lo1 = __shfl(f1, col), hi1 = __shfl(f1, col + 32);
@@ -323,15 +328,17 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
         if (tid < npad) {
             const bool live = tid < np;
             float *ro = reinterpret_cast<float *>(xs) + tid * DS;
-            bf16x8 *ra = xa + ((tid >> 5) * KB * 64 + (tid & 31)) * 2;
+            const int ra = (tid >> 5) * KB * 64 + (tid & 31);
             float Xn = 0.0f;
             float cv[16 * KB];
 #pragma unroll
             for (int j = 0; j < 16 * KB; j++) {
                 cv[j] = (live && j < a.d && j < D) ? pre[j < DS ? j : 0] - cr[j < DS ? j : 0] : 0.0f;
-                if (j < DS) ro[j] = pre[j];
                 Xn = fmaf(cv[j], cv[j], Xn);
             }
+#pragma unroll
+            for (int c4 = 0; c4 < DS / 4; c4++)
+                reinterpret_cast<float4 *>(ro)[c4] = make_float4(pre[4 * c4], pre[4 * c4 + 1], pre[4 * c4 + 2], pre[4 * c4 + 3]);
             const float bsv = 0.5f * (coef * Xn);
             // padding rows: a large finite negative value keeps the split free of inf - inf
             if constexpr (FOLD) cv[D] = live ? -bsv : -0x1p127f;
@@ -349,8 +356,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
             for (int s2 = 0; s2 < KB; s2++) {
 #pragma unroll
                 for (int h2 = 0; h2 < 2; h2++) {
-                    ra[(s2 * 64 + 32 * h2) * 2] = vh[2 * s2 + h2];
-                    ra[(s2 * 64 + 32 * h2) * 2 + 1] = vl[2 * s2 + h2];
+                    xah[ra + s2 * 64 + 32 * h2] = vh[2 * s2 + h2];
+                    xal[ra + s2 * 64 + 32 * h2] = vl[2 * s2 + h2];
                 }
             }
             os[tid] = pre_o;
@@ -505,6 +512,7 @@ template <int D, int K> __global__ __launch_bounds__(TAIL_THREADS) void k_tail(S
     for (int j = 0; j < D; j++) qv[j] = (j < a.d) ? qp[j] : 0.0f;
     uint64_t *kp = a.keys + (int64_t)q * K;
     uint64_t li = (lane < K) ? kp[lane] : ~0ull;  // the query's list, lane i holds the i-th smallest
+    const int kk = a.kq ? a.kq[q] : a.k;
     const int32_t first = (1 << h) - 1;
     long long visits = 0, pairs = 0;
     for (;;) {
@@ -569,7 +577,7 @@ template <int D, int K> __global__ __launch_bounds__(TAIL_THREADS) void k_tail(S
         __syncthreads();  // cand is written again for the next leaf
         visits++;
         pairs += len;
-        const uint64_t kth_key = readlane_u64(li, a.k - 1);
+        const uint64_t kth_key = readlane_u64(li, kk - 1);
         const int32_t v = next_leaf(first + leaf, qp, &kth_key, a.split, split_lds, lds_nodes, h, a.d);
         if (v == NODE_DONE) break;
         leaf = v - first;
@@ -577,6 +585,11 @@ template <int D, int K> __global__ __launch_bounds__(TAIL_THREADS) void k_tail(S
     if (w == 0 && lane < K) kp[lane] = li;
     if (threadIdx.x == 0) {
         a.node[q] = NODE_DONE;
+        if (a.req_left) {
+            // last query of its request: record the request as complete
+            const int32_t r = a.req_of[q];
+            if (atomicSub(&a.req_left[r], 1) == 1) a.done_list[1 + atomicAdd(&a.done_list[0], 1)] = r;
+        }
         atomicAdd((unsigned long long *)(a.ctl + CTL_VISITS_LO), (unsigned long long)visits);
         atomicAdd((unsigned long long *)(a.ctl + CTL_SPAIRS_LO), (unsigned long long)pairs);
     }

@@ -92,7 +92,9 @@ struct Session {
     // device state
     DevBuf Qpool, keys, node, kq, req_of, req_left, done, pleaf, pq, tleaf, tq, hist, cnt, cnt0, off, tiles, ctl, newslots,
         stage, oidx, odist, gslots;
-    PinnedBuf hctl, hdone, hstage, hout;
+    PinnedBuf hctl, hdone, hstage, hout, hgslots;
+    hipEvent_t ev_stage = nullptr;  // after the last admission's staging copies
+    bool stage_pending = false;
     // host state
     std::vector<int32_t> free_slots, free_tables;
     std::deque<Request *> waiting;
@@ -100,8 +102,8 @@ struct Session {
     int64_t P = 0;  // pending entries in flight (sorted list of the last round)
     int cur = 0;
     std::thread th;
-    int64_t rounds = 0, scans = 0;
-    double busy_s = 0;
+    int64_t rounds = 0, scans = 0, tails = 0, admitted = 0;
+    double busy_s = 0, admit_s = 0, complete_s = 0;
 };
 
 struct Server {
@@ -150,6 +152,7 @@ static void session_init(Session &S)
     S.free_tables.resize((size_t)S.max_req);
     for (int i = 0; i < S.max_req; i++) S.free_tables[(size_t)i] = S.max_req - 1 - i;
     BKD_HIP(hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking));
+    BKD_HIP(hipEventCreateWithFlags(&S.ev_stage, hipEventDisableTiming));
     launch_fill_i32(S.cnt.as<int32_t>(), 0, nleaf, S.s);
     launch_fill_i32(S.ctl.as<int32_t>(), 0, CTL_WORDS, S.s);
     launch_fill_i32(S.done.as<int32_t>(), 0, 1, S.s);
@@ -182,24 +185,35 @@ static int64_t session_admit(Session &S, std::unique_lock<std::mutex> &lk)
         adm.push_back(r);
     }
     lk.unlock();
-    for (Request *r : adm) {
-        // coordinates: host -> pinned stage -> device stage -> slots
-        const size_t qb = sizeof(float) * (size_t)r->m * d;
-        BKD_HIP(hipStreamSynchronize(S.s));  // staging buffers are reused (and may grow)
-        S.hstage.ensure(qb + sizeof(int32_t) * (size_t)r->m);
+    if (!adm.empty()) {
+        // all admitted requests in one staging pass: host -> pinned stage -> device stage -> slots
+        int64_t total = 0;
+        for (Request *r : adm) total += r->m;
+        const size_t qb = sizeof(float) * (size_t)total * d;
+        if (S.stage_pending) BKD_HIP(hipEventSynchronize(S.ev_stage));  // the stage buffers are free again
+        S.hstage.ensure(qb + sizeof(int32_t) * (size_t)total);
         S.stage.ensure(qb);
-        std::memcpy(S.hstage.p, r->Q.data(), qb);
-        std::memcpy(static_cast<char *>(S.hstage.p) + qb, r->slots.data(), sizeof(int32_t) * (size_t)r->m);
-        BKD_HIP(hipMemcpyAsync(S.stage.p, S.hstage.p, qb, hipMemcpyHostToDevice, S.s));
-        BKD_HIP(hipMemcpyAsync(S.newslots.as<int32_t>() + nnew, static_cast<char *>(S.hstage.p) + qb,
-                               sizeof(int32_t) * (size_t)r->m, hipMemcpyHostToDevice, S.s));
-        k_admit<<<(unsigned)((r->m + 255) / 256), 256, 0, S.s>>>(
-            S.stage.as<float>(), S.newslots.as<int32_t>() + nnew, r->m, d, S.K, r->k, r->table, S.Qpool.as<float>(),
-            S.keys.as<uint64_t>(), S.node.as<int32_t>(), S.kq.as<int32_t>(), S.req_of.as<int32_t>());
-        k_set_i32<<<1, 1, 0, S.s>>>(S.req_left.as<int32_t>(), r->table, (int32_t)r->m);
-        nnew += r->m;
+        char *hs = static_cast<char *>(S.hstage.p);
+        int64_t off = 0;
+        for (Request *r : adm) {
+            std::memcpy(hs + sizeof(float) * (size_t)off * d, r->Q.data(), sizeof(float) * (size_t)r->m * d);
+            std::memcpy(hs + qb + sizeof(int32_t) * (size_t)off, r->slots.data(), sizeof(int32_t) * (size_t)r->m);
+            off += r->m;
+        }
+        BKD_HIP(hipMemcpyAsync(S.stage.p, hs, qb, hipMemcpyHostToDevice, S.s));
+        BKD_HIP(hipMemcpyAsync(S.newslots.p, hs + qb, sizeof(int32_t) * (size_t)total, hipMemcpyHostToDevice, S.s));
+        for (Request *r : adm) {
+            k_admit<<<(unsigned)((r->m + 255) / 256), 256, 0, S.s>>>(
+                S.stage.as<float>() + nnew * d, S.newslots.as<int32_t>() + nnew, r->m, d, S.K, r->k, r->table,
+                S.Qpool.as<float>(), S.keys.as<uint64_t>(), S.node.as<int32_t>(), S.kq.as<int32_t>(),
+                S.req_of.as<int32_t>());
+            k_set_i32<<<1, 1, 0, S.s>>>(S.req_left.as<int32_t>(), r->table, (int32_t)r->m);
+            nnew += r->m;
+        }
+        BKD_HIP(hipEventRecord(S.ev_stage, S.s));
+        S.stage_pending = true;
     }
-    BKD_HIP(hipStreamSynchronize(S.s));
+    S.admitted += nnew;
     lk.lock();
     return nnew;
 }
@@ -238,7 +252,32 @@ static void session_round(Session &S, int64_t nnew)
     BKD_HIP(hipMemcpyAsync(hctl, ctl, sizeof(int32_t) * CTL_WORDS, hipMemcpyDeviceToHost, S.s));
     BKD_HIP(hipStreamSynchronize(S.s));
     S.P = hctl[CTL_V];
-    if (hctl[CTL_T] + hctl[CTL_S] > 0) {
+    if (S.P > 0 && S.P <= TAIL_MAX) {
+        // few queries in flight: each finishes its traversal in one workgroup, and its request
+        // completes as its last query does
+        ScanArgs a{};
+        a.leaf_off = T.d_leaf_off.as<int32_t>();
+        a.base = T.d_chunk[0].as<float>();
+        a.blk = T.d_leaf_blk.as<int64_t>();
+        a.Q = S.Qpool.as<float>();
+        a.d = H.d;
+        a.keys = S.keys.as<uint64_t>();
+        a.tail_leaf = leafbuf[S.cur];
+        a.tail_q = qbuf[S.cur];
+        a.tail_count = (int32_t)S.P;
+        a.node = S.node.as<int32_t>();
+        a.split = T.d_split.as<float>();
+        a.h = H.h;
+        a.k = S.K;
+        a.ctl = ctl;
+        a.kq = S.kq.as<int32_t>();
+        a.req_of = S.req_of.as<int32_t>();
+        a.req_left = S.req_left.as<int32_t>();
+        a.done_list = S.done.as<int32_t>();
+        launch_leaf_scan(a, S.K, 2, S.s);
+        S.P = 0;
+        S.tails++;
+    } else if (hctl[CTL_T] + hctl[CTL_S] > 0) {
         ScanArgs a{};
         a.tiles = S.tiles.as<int32_t>();
         a.sparse = a.tiles + nleaf + 1;
@@ -271,12 +310,12 @@ static void session_round(Session &S, int64_t nnew)
 // Deliver completed requests (their last query finished in this round's routing).
 static void session_complete(Session &S, std::unique_lock<std::mutex> &lk)
 {
-    BKD_HIP(hipMemcpyAsync(S.hdone.p, S.done.p, sizeof(int32_t), hipMemcpyDeviceToHost, S.s));
+    // the completion list: its count and every entry in one copy (at most max_req entries)
+    BKD_HIP(hipMemcpyAsync(S.hdone.p, S.done.p, sizeof(int32_t) * (size_t)(1 + S.max_req), hipMemcpyDeviceToHost,
+                           S.s));
     BKD_HIP(hipStreamSynchronize(S.s));
     const int nd = S.hdone.as<int32_t>()[0];
     if (nd == 0) return;
-    BKD_HIP(hipMemcpy(S.hdone.as<int32_t>() + 1, S.done.as<int32_t>() + 1, sizeof(int32_t) * nd,
-                      hipMemcpyDeviceToHost));
     launch_fill_i32(S.done.as<int32_t>(), 0, 1, S.s);
     std::vector<Request *> fin;
     for (int x = 0; x < nd; x++) {
@@ -284,20 +323,44 @@ static void session_complete(Session &S, std::unique_lock<std::mutex> &lk)
         if (it != S.running.end()) fin.push_back(it->second);
     }
     lk.unlock();
+    // every finished request in one pass: slot lists up, one gather per request, results down
+    int64_t nslots = 0, nout = 0;
     for (Request *r : fin) {
-        const size_t cnt = (size_t)r->m * r->k;
-        S.gslots.ensure(sizeof(int32_t) * (size_t)r->m);
-        S.oidx.ensure(sizeof(int64_t) * cnt);
-        S.odist.ensure(sizeof(float) * cnt);
-        BKD_HIP(hipMemcpyAsync(S.gslots.p, r->slots.data(), sizeof(int32_t) * (size_t)r->m, hipMemcpyHostToDevice,
-                               S.s));
-        k_gather<<<(unsigned)((cnt + 255) / 256), 256, 0, S.s>>>(S.keys.as<uint64_t>(), S.gslots.as<int32_t>(), r->m,
-                                                                  S.K, r->k, S.oidx.as<int64_t>(),
-                                                                  S.odist.as<float>(),
-                                                                  (S.srv->flags & BKD_FLAG_SQUARED) ? 1 : 0);
-        BKD_HIP(hipMemcpyAsync(r->out_idx, S.oidx.p, sizeof(int64_t) * cnt, hipMemcpyDeviceToHost, S.s));
-        BKD_HIP(hipMemcpyAsync(r->out_dist, S.odist.p, sizeof(float) * cnt, hipMemcpyDeviceToHost, S.s));
-        BKD_HIP(hipStreamSynchronize(S.s));
+        nslots += r->m;
+        nout += r->m * r->k;
+    }
+    S.hgslots.ensure(sizeof(int32_t) * (size_t)nslots);
+    S.gslots.ensure(sizeof(int32_t) * (size_t)nslots);
+    S.oidx.ensure(sizeof(int64_t) * (size_t)nout);
+    S.odist.ensure(sizeof(float) * (size_t)nout);
+    S.hout.ensure((sizeof(int64_t) + sizeof(float)) * (size_t)nout);
+    int64_t so = 0;
+    for (Request *r : fin) {
+        std::memcpy(S.hgslots.as<int32_t>() + so, r->slots.data(), sizeof(int32_t) * (size_t)r->m);
+        so += r->m;
+    }
+    BKD_HIP(hipMemcpyAsync(S.gslots.p, S.hgslots.p, sizeof(int32_t) * (size_t)nslots, hipMemcpyHostToDevice, S.s));
+    so = 0;
+    int64_t oo = 0;
+    for (Request *r : fin) {
+        const int64_t cnt = r->m * r->k;
+        k_gather<<<(unsigned)((cnt + 255) / 256), 256, 0, S.s>>>(
+            S.keys.as<uint64_t>(), S.gslots.as<int32_t>() + so, r->m, S.K, r->k, S.oidx.as<int64_t>() + oo,
+            S.odist.as<float>() + oo, (S.srv->flags & BKD_FLAG_SQUARED) ? 1 : 0);
+        so += r->m;
+        oo += cnt;
+    }
+    int64_t *hidx = S.hout.as<int64_t>();
+    float *hdist = reinterpret_cast<float *>(hidx + nout);
+    BKD_HIP(hipMemcpyAsync(hidx, S.oidx.p, sizeof(int64_t) * (size_t)nout, hipMemcpyDeviceToHost, S.s));
+    BKD_HIP(hipMemcpyAsync(hdist, S.odist.p, sizeof(float) * (size_t)nout, hipMemcpyDeviceToHost, S.s));
+    BKD_HIP(hipStreamSynchronize(S.s));
+    oo = 0;
+    for (Request *r : fin) {
+        const int64_t cnt = r->m * r->k;
+        std::memcpy(r->out_idx, hidx + oo, sizeof(int64_t) * (size_t)cnt);
+        std::memcpy(r->out_dist, hdist + oo, sizeof(float) * (size_t)cnt);
+        oo += cnt;
         r->t_done = now_s();
     }
     lk.lock();
@@ -321,7 +384,9 @@ static void session_loop(Session *Sp)
         std::unique_lock<std::mutex> lk(V.mu);
         for (;;) {
             if (V.stop) break;
+            const double ta = now_s();
             const int64_t nnew = session_admit(S, lk);
+            S.admit_s += now_s() - ta;
             if (S.P == 0 && nnew == 0 && S.running.empty()) {
                 V.cv.wait_for(lk, std::chrono::milliseconds(50));
                 continue;
@@ -331,7 +396,9 @@ static void session_loop(Session *Sp)
             session_round(S, nnew);
             S.busy_s += now_s() - t0;
             lk.lock();
+            const double tc = now_s();
             session_complete(S, lk);
+            S.complete_s += now_s() - tc;
         }
     } catch (const BkdError &e) {
         std::lock_guard<std::mutex> g(V.mu);
@@ -489,6 +556,25 @@ int bkd_request_times(bkd_server *srv, int64_t req_id, double *submit_s, double 
     });
 }
 
+int bkd_server_stats_get(bkd_server *srv, bkd_server_stats *out)
+{
+    return bkd::guarded_call([&] {
+        if (!srv || !out) bkd::fail(BKD_EINVAL, "NULL pointer");
+        std::lock_guard<std::mutex> g(srv->v.mu);
+        *out = bkd_server_stats{};
+        for (auto &s : srv->v.sessions) {
+            out->sessions++;
+            out->rounds += s->rounds;
+            out->scan_rounds += s->scans;
+            out->tail_rounds += s->tails;
+            out->queries += s->admitted;
+            out->busy_s += s->busy_s;
+            out->admit_s += s->admit_s;
+            out->complete_s += s->complete_s;
+        }
+    });
+}
+
 int bkd_release(bkd_server *srv, int64_t req_id)
 {
     return bkd::guarded_call([&] {
@@ -513,8 +599,11 @@ int bkd_server_destroy(bkd_server *srv)
         for (auto &s : srv->v.sessions)
             if (s->th.joinable()) s->th.join();
         (void)hipSetDevice(srv->v.device);
-        for (auto &s : srv->v.sessions)
+        (void)hipDeviceSynchronize();
+        for (auto &s : srv->v.sessions) {
+            if (s->ev_stage) (void)hipEventDestroy(s->ev_stage);
             if (s->s) (void)hipStreamDestroy(s->s);
+        }
         delete srv;
     });
 }
