@@ -193,7 +193,29 @@ def run_batched(args, torch, bkd):
                      "peak_nonpacked": round(FP32_NONPACKED_TFLOPS, 1),
                      "frac_nonpacked": round(achieved / FP32_NONPACKED_TFLOPS, 4),
                      "avg_launch_ms": round(run_ms / args.steps, 4), "flops_per_launch": flops},
+        **({} if args.no_cpu_baseline else {"cpu_baseline": cpu_baseline_batched(inst, args.cpu_seconds)}),
     }
+
+
+def cpu_baseline_batched(inst, budget_s):
+    """The oracle's float64 k-d tree per instance (build not timed), instances in order until the budget."""
+    import oracle
+    threads = oracle.max_threads()
+    q = 0
+    t = 0.0
+    used = 0
+    for P, Q, k, _ in inst:
+        tree = oracle.KdTree64(P, 32)
+        t0 = time.perf_counter()
+        tree.query(Q, k)
+        t += time.perf_counter() - t0
+        q += len(Q)
+        used += 1
+        if t >= budget_s:
+            break
+    return {"value": q / t, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"all queries of the first {used} of {len(inst)} instances; float64 k-d tree per instance, "
+                      f"leaf size 32, OpenMP over queries ({threads} threads, {cpu_model()})"}
 
 
 def run_served(args, torch, bkd):

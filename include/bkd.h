@@ -236,8 +236,8 @@ typedef struct bkd_instance {
 typedef struct bkd_tuning {
     int32_t leaves_per_task; /* buffered leaves per scan task (1..256); 0: default 8          */
     int32_t groups_per_cu;   /* persistent workgroups per compute unit (1..16); 0: default 4  */
-    int32_t solo_max;        /* rounds with at most this many active queries of an instance  */
-                             /* run whole inside one workgroup; 0: default 2048             */
+    int32_t solo_max;        /* once an instance has at most this many active queries, each  */
+                             /* finishes its traversal alone (one wave per query); 0: 2048   */
 } bkd_tuning;
 
 typedef struct bkd_batch_stats {
@@ -249,6 +249,8 @@ typedef struct bkd_batch_stats {
     double run_ms;      /* device time of the last run (graph launch)               */
     int32_t error;      /* nonzero: the last run stopped early (queue overflow or   */
                         /* stall guard); its results are not valid                  */
+    int32_t workgroups; /* persistent workgroups of the last run                    */
+    double claim_wait_ms; /* time workgroups spent waiting for a task, summed       */
 } bkd_batch_stats;
 
 typedef struct bkd_batch bkd_batch;

@@ -271,7 +271,8 @@ class Tuning(ctypes.Structure):
 class BatchStats(ctypes.Structure):
     _fields_ = [("instances", ctypes.c_int64), ("queries", ctypes.c_int64), ("tasks", ctypes.c_int64),
                 ("rounds", ctypes.c_int64), ("pairs", ctypes.c_int64), ("flops", ctypes.c_int64),
-                ("run_ms", ctypes.c_double), ("error", ctypes.c_int32)]
+                ("run_ms", ctypes.c_double), ("error", ctypes.c_int32), ("workgroups", ctypes.c_int32),
+                ("claim_wait_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -12,6 +12,11 @@
 //                    registers (lanes over points) while the wave walks the
 //                    leaf's buffered queries; each query's k best keys are
 //                    spread over the lanes and merged with ballots.
+//   TAIL(i, j0, j1)  once an instance has at most solo_max active queries
+//                    (or from the start, when it is that small): one wave per
+//                    query walks that query's traversal to the end, lanes over
+//                    each leaf's points, so the end of an instance is the
+//                    longest single traversal rather than a chain of rounds.
 // The last task of a phase enqueues the next phase of the same instance.
 // Instances therefore advance independently; nothing waits for a global
 // round.  Tasks are published with release stores of a per-slot sequence word
@@ -43,8 +48,9 @@ constexpr int BATCH_MAX_LEAVES = 4096;  // height <= 12
 constexpr int TASK_FIND = 1;
 constexpr int TASK_ORGANIZE = 2;
 constexpr int TASK_SCAN = 3;
-constexpr int TASK_SOLO = 4;
+constexpr int TASK_TAIL = 5;
 constexpr int FIND_CHUNK = 2048;  // active queries per FIND task
+constexpr int TAIL_CHUNK = 16;    // queries per TAIL task (four per wave)
 
 struct BInst {
     int32_t d, k, h, nleaf, m, n;
@@ -60,6 +66,7 @@ struct BQueue {
     unsigned long long head, tail;
     int32_t done, error, active, pad;
     unsigned long long tasks, pairs, flops, rounds;
+    unsigned long long wait_ticks;  // wall-clock ticks spent waiting for a task, summed over workgroups
 };
 
 struct BatchArgs {
@@ -81,7 +88,7 @@ struct BatchArgs {
     int32_t *ne;
     int32_t *cnt;
     int32_t leaves_per_task;
-    int32_t solo_max;  // rounds with at most this many active queries run inside one workgroup
+    int32_t solo_max;  // instances with at most this many active queries finish per query (TAIL)
     int32_t count;
     unsigned long long spin_ticks;
 };
@@ -175,8 +182,19 @@ struct RouteLds {
     int32_t E;
 };
 
+// The instance's split values (at most 4095) in LDS for the walks of one task.
+__device__ __forceinline__ const float *stage_split(const BatchArgs &a, const BInst &I, RouteLds &L)
+{
+    float *sl = reinterpret_cast<float *>(L.hist);
+    const float *split = a.split + I.split_off;
+    __syncthreads();  // the previous task may still read L
+    for (int v = threadIdx.x; v < I.nleaf - 1; v += BT) sl[v] = split[v];
+    __syncthreads();
+    return sl;
+}
+
 // FindLeafBatch over active entries [j0, j1) of instance i's current round.
-__device__ __forceinline__ void find_task(const BatchArgs &a, int i, int j0, int j1)
+__device__ __forceinline__ void find_task(const BatchArgs &a, int i, int j0, int j1, RouteLds &L)
 {
     const BInst I = a.inst[i];
     const int round = a.state[i].round;
@@ -188,13 +206,14 @@ __device__ __forceinline__ void find_task(const BatchArgs &a, int i, int j0, int
     const uint64_t *keys = a.keys + I.key_off;
     const float *Q = a.Q + I.q_off;
     const int first = I.nleaf - 1;
+    const float *sl = stage_split(a, I, L);
     for (int jb = j0; jb < j1; jb += BT) {
         const int j = jb + (int)threadIdx.x;
         int32_t lf = -1;
         if (j < j1) {
             const int32_t q = round == 0 ? j : inb[j];
-            const int32_t v =
-                next_leaf(node[q], Q + (int64_t)q * I.d, keys + (int64_t)q * I.k + (I.k - 1), split, nullptr, 0, I.h, I.d);
+            const int32_t v = next_leaf(node[q], Q + (int64_t)q * I.d, keys + (int64_t)q * I.k + (I.k - 1), split, sl,
+                                        I.nleaf - 1, I.h, I.d);
             node[q] = v;
             lf = v >= 0 ? v - first : -1;
             tmp[j] = lf;
@@ -211,11 +230,11 @@ __device__ __forceinline__ void find_task(const BatchArgs &a, int i, int j0, int
     }
 }
 
-// Buffer offsets, buffered-leaf list and scatter of instance i's round.  The
-// buffer fills are in the global counters (pipeline) or already in L.hist
-// (solo round).  Returns the number of buffered queries V; an instance with
-// V = 0 is finished.  On V > 0 the instance state moves to the next round.
-__device__ __forceinline__ int organize_core(const BatchArgs &a, int i, RouteLds &L, bool fills_in_lds)
+// Buffer offsets, buffered-leaf list and scatter of instance i's round, from
+// the buffer fills in the global counters.  Returns the number of buffered
+// queries V; an instance with V = 0 is finished.  On V > 0 the instance state
+// moves to the next round.
+__device__ __forceinline__ int organize_core(const BatchArgs &a, int i, RouteLds &L)
 {
     const BInst I = a.inst[i];
     BState *st = a.state + i;
@@ -233,13 +252,8 @@ __device__ __forceinline__ int organize_core(const BatchArgs &a, int i, RouteLds
 
     unsigned long long pr = 0;
     for (int l = tid; l < nleaf; l += BT) {
-        int32_t c;
-        if (fills_in_lds) {
-            c = L.hist[l];
-        } else {
-            c = cnt[l];
-            cnt[l] = 0;
-        }
+        const int32_t c = cnt[l];
+        cnt[l] = 0;
         L.cur[l] = c;
         pr += (unsigned long long)c * (unsigned)(loffs[l + 1] - loffs[l]);
     }
@@ -290,7 +304,7 @@ __device__ __forceinline__ int organize_core(const BatchArgs &a, int i, RouteLds
 
 __device__ __forceinline__ void organize_task(const BatchArgs &a, int i, RouteLds &L)
 {
-    if (organize_core(a, i, L, false) == 0) return;
+    if (organize_core(a, i, L) == 0) return;
     const int E = L.E;
     const int lpt = a.leaves_per_task;
     const int T = (E + lpt - 1) / lpt;
@@ -298,48 +312,6 @@ __device__ __forceinline__ void organize_task(const BatchArgs &a, int i, RouteLd
     push_tasks(a, T, [&](int j) { return make_int4(TASK_SCAN, i, j * lpt, min(E, (j + 1) * lpt)); }, &L.base);
 }
 
-__device__ __forceinline__ void scan_task(const BatchArgs &a, int i, int e0, int e1);
-
-// Whole rounds of a small instance inside one workgroup: FindLeafBatch with the
-// fills counted in LDS, buffer organisation, and the scan of every buffered
-// leaf (one wave per leaf), until the instance is finished.
-__device__ __forceinline__ void solo_task(const BatchArgs &a, int i, RouteLds &L)
-{
-    const BInst I = a.inst[i];
-    BState *st = a.state + i;
-    const int tid = threadIdx.x;
-    const int first = I.nleaf - 1;
-    const float *split = a.split + I.split_off;
-    int32_t *tmp = a.tmp + I.tmp_off;
-    int32_t *node = a.node + I.node_off;
-    const uint64_t *keys = a.keys + I.key_off;
-    const float *Q = a.Q + I.q_off;
-    for (;;) {
-        const int round = st->round;
-        const int A = round == 0 ? I.m : st->V;
-        const int32_t *inb = a.buf + I.buf_off + (int64_t)(round & 1) * I.m;
-        for (int l = tid; l < I.nleaf; l += BT) L.hist[l] = 0;
-        __syncthreads();
-        for (int j = tid; j < A; j += BT) {
-            const int32_t q = round == 0 ? j : inb[j];
-            const int32_t v =
-                next_leaf(node[q], Q + (int64_t)q * I.d, keys + (int64_t)q * I.k + (I.k - 1), split, nullptr, 0, I.h, I.d);
-            node[q] = v;
-            const int32_t lf = v >= 0 ? v - first : -1;
-            tmp[j] = lf;
-            if (lf >= 0) atomicAdd(&L.hist[lf], 1);
-        }
-        __threadfence();
-        __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // other waves' tmp[] writes
-        if (organize_core(a, i, L, true) == 0) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        scan_task(a, i, 0, L.E);
-        __threadfence();
-        __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-}
 
 // One wave per buffered leaf; G groups of 64 points per pass held in registers.
 template <int D, int G> __device__ __forceinline__ void scan_leaves(const BatchArgs &a, int i, int e0, int e1)
@@ -374,33 +346,151 @@ template <int D, int G> __device__ __forceinline__ void scan_leaves(const BatchA
                 for (int j = 0; j < D; j++) x[g][j] = (v[g] && j < d) ? X[j * len + p] : 0.0f;
                 o[g] = v[g] ? (uint32_t)orig[p] : 0u;
             }
-            for (int jq = qs; jq < qe; jq++) {
-                const int32_t q = __builtin_amdgcn_readfirstlane(buf[jq]);
-                const float *qp = Q + (int64_t)q * d;
-                float acc[G];
+            // The leaf's buffered queries, 64 ids at a time in the lanes.  Each query's
+            // coordinates (lane j: coordinate j) and key list are loaded four queries
+            // ahead, so the loads of later queries overlap the merges of earlier ones.
+            for (int jb = qs; jb < qe; jb += 64) {
+                const int nq = min(64, qe - jb);
+                const int32_t qid = lane < nq ? buf[jb + lane] : 0;
+                auto fetch = [&](int t, float &qr, uint64_t &lr) {
+                    if (t < nq) {
+                        const int32_t qq = __builtin_amdgcn_readlane(qid, t);
+                        qr = lane < d ? Q[(int64_t)qq * d + lane] : 0.0f;
+                        lr = lane < k ? keys[(int64_t)qq * k + lane] : ~0ull;
+                    }
+                };
+                auto merge = [&](int t, float ql, uint64_t li) {
+                    const int32_t q = __builtin_amdgcn_readlane(qid, t);
+                    float qv[D];
 #pragma unroll
-                for (int g = 0; g < G; g++) acc[g] = 0.0f;
+                    for (int j = 0; j < D; j++)
+                        qv[j] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ql), j));
+                    float acc[G];
 #pragma unroll
-                for (int j = 0; j < D; j++) {
-                    const float qj = j < d ? qp[j] : 0.0f;
+                    for (int g = 0; g < G; g++) acc[g] = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < D; j++) {
+#pragma unroll
+                        for (int g = 0; g < G; g++) {
+                            const float tt = qv[j] - x[g][j];
+                            acc[g] = fmaf(tt, tt, acc[g]);
+                        }
+                    }
+                    uint64_t kth = rdlane64(li, k - 1);
+                    bool dirty = false;
 #pragma unroll
                     for (int g = 0; g < G; g++) {
-                        const float t = qj - x[g][j];
-                        acc[g] = fmaf(t, t, acc[g]);
+                        const uint64_t key = v[g] ? (((uint64_t)__float_as_uint(acc[g]) << 32) | o[g]) : ~0ull;
+                        uint64_t cand = __ballot(key < kth);
+                        while (cand) {
+                            const int c = __ffsll((unsigned long long)cand) - 1;
+                            cand &= cand - 1;
+                            const uint64_t ck = rdlane64(key, c);
+                            if (ck < kth) {
+                                const uint64_t moved = __ballot(li > ck);
+                                const int pos = __ffsll((unsigned long long)moved) - 1;
+                                const uint64_t up = __shfl_up(li, 1);
+                                li = (lane < pos) ? li : (lane == pos ? ck : up);
+                                if (lane >= k) li = ~0ull;
+                                kth = rdlane64(li, k - 1);
+                                dirty = true;
+                            }
+                        }
+                    }
+                    if (dirty && lane < k) keys[(int64_t)q * k + lane] = li;
+                };
+                float q0 = 0.0f, q1 = 0.0f, q2 = 0.0f, q3 = 0.0f;
+                uint64_t l0 = ~0ull, l1 = ~0ull, l2 = ~0ull, l3 = ~0ull;
+                fetch(0, q0, l0);
+                fetch(1, q1, l1);
+                fetch(2, q2, l2);
+                fetch(3, q3, l3);
+                for (int t = 0; t < nq; t += 4) {
+                    merge(t, q0, l0);
+                    fetch(t + 4, q0, l0);
+                    if (t + 1 < nq) {
+                        merge(t + 1, q1, l1);
+                        fetch(t + 5, q1, l1);
+                    }
+                    if (t + 2 < nq) {
+                        merge(t + 2, q2, l2);
+                        fetch(t + 6, q2, l2);
+                    }
+                    if (t + 3 < nq) {
+                        merge(t + 3, q3, l3);
+                        fetch(t + 7, q3, l3);
                     }
                 }
-                uint64_t *kp = keys + (int64_t)q * k;
-                uint64_t li = lane < k ? kp[lane] : ~0ull;
-                uint64_t kth = rdlane64(li, k - 1);
-                bool dirty = false;
+            }
+        }
+    }
+}
+
+// Queries [j0, j1) of instance i's active list (identity in round 0) finish their
+// traversals, one wave per query; the last TAIL task of the instance retires it.
+template <int D, int G>
+__device__ __forceinline__ void tail_queries(const BatchArgs &a, int i, int j0, int j1, RouteLds &L)
+{
+    const BInst I = a.inst[i];
+    const float *sl = stage_split(a, I, L);
+    float *qs = reinterpret_cast<float *>(L.cur) + 32 * (threadIdx.x >> 6);  // this wave's query, for the walk
+    const int round = a.state[i].round;
+    const int32_t *list = a.buf + I.buf_off + (int64_t)(round & 1) * I.m;
+    const int32_t *lo_pos = a.leaf_off + I.leaf_off_off;
+    const int32_t *blk = a.blk + I.blk_off;
+    const float *pts = a.pts + I.pts_off;
+    const float *Q = a.Q + I.q_off;
+    const float *split = a.split + I.split_off;
+    int32_t *node = a.node + I.node_off;
+    uint64_t *keys = a.keys + I.key_off;
+    const int first = I.nleaf - 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int d = I.d, k = I.k;
+    unsigned long long pairs = 0;
+    for (int j = j0 + wave; j < j1; j += BT / 64) {
+        const int32_t q = round == 0 ? j : list[j];
+        const float *qp = Q + (int64_t)q * d;
+        const float ql = lane < d ? qp[lane] : 0.0f;
+        if (lane < d) qs[lane] = ql;
+        float qv[D];
+#pragma unroll
+        for (int c = 0; c < D; c++) qv[c] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ql), c));
+        uint64_t li = lane < k ? keys[(int64_t)q * k + lane] : ~0ull;
+        int32_t st = node[q];
+        for (;;) {
+            const uint64_t kth_key = rdlane64(li, k - 1);
+            const int32_t v = next_leaf(st, qs, &kth_key, split, sl, I.nleaf - 1, I.h, d);
+            if (v == NODE_DONE) break;
+            st = v;
+            const int Lf = v - first;
+            const int len = lo_pos[Lf + 1] - lo_pos[Lf];
+            const float *X = pts + blk[Lf];
+            const int32_t *orig = reinterpret_cast<const int32_t *>(X) + (int64_t)d * len;
+            pairs += (unsigned)len;
+            uint64_t kth = kth_key;
+            for (int gb = 0; gb < len; gb += 64 * G) {
+                uint64_t key[G];
 #pragma unroll
                 for (int g = 0; g < G; g++) {
-                    const uint64_t key = v[g] ? (((uint64_t)__float_as_uint(acc[g]) << 32) | o[g]) : ~0ull;
-                    uint64_t cand = __ballot(key < kth);
+                    const int p = gb + 64 * g + lane;
+                    const bool valid = p < len;
+                    const int pi = valid ? p : 0;
+                    float acc = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < D; c++) {
+                        const float x = X[(c < d ? c : 0) * len + pi];
+                        const float tt = qv[c] - (c < d ? x : 0.0f);
+                        acc = fmaf(tt, tt, acc);
+                    }
+                    key[g] = valid ? (((uint64_t)__float_as_uint(acc) << 32) | (uint32_t)orig[pi]) : ~0ull;
+                }
+#pragma unroll
+                for (int g = 0; g < G; g++) {
+                    uint64_t cand = __ballot(key[g] < kth);
                     while (cand) {
                         const int c = __ffsll((unsigned long long)cand) - 1;
                         cand &= cand - 1;
-                        const uint64_t ck = rdlane64(key, c);
+                        const uint64_t ck = rdlane64(key[g], c);
                         if (ck < kth) {
                             const uint64_t moved = __ballot(li > ck);
                             const int pos = __ffsll((unsigned long long)moved) - 1;
@@ -408,13 +498,38 @@ template <int D, int G> __device__ __forceinline__ void scan_leaves(const BatchA
                             li = (lane < pos) ? li : (lane == pos ? ck : up);
                             if (lane >= k) li = ~0ull;
                             kth = rdlane64(li, k - 1);
-                            dirty = true;
                         }
                     }
                 }
-                if (dirty && lane < k) kp[lane] = li;
             }
         }
+        node[q] = NODE_DONE;
+        if (lane < k) keys[(int64_t)q * k + lane] = li;
+    }
+    if (lane == 0 && pairs) {
+        atomicAdd(&a.q->pairs, pairs);
+        atomicAdd(&a.q->flops, pairs * 3ull * (unsigned)d);
+    }
+}
+
+__device__ __forceinline__ void tail_task(const BatchArgs &a, int i, int j0, int j1, RouteLds &L)
+{
+    switch (a.inst[i].d <= 2 ? 2 : a.inst[i].d <= 3 ? 3 : a.inst[i].d <= 4 ? 4 : a.inst[i].d <= 5 ? 5
+            : a.inst[i].d <= 6 ? 6 : a.inst[i].d <= 8 ? 8 : a.inst[i].d <= 10 ? 10 : a.inst[i].d <= 12 ? 12
+            : a.inst[i].d <= 15 ? 15 : a.inst[i].d <= 16 ? 16 : a.inst[i].d <= 20 ? 20 : a.inst[i].d <= 24 ? 24 : 32) {
+    case 2: tail_queries<2, 2>(a, i, j0, j1, L); break;
+    case 3: tail_queries<3, 2>(a, i, j0, j1, L); break;
+    case 4: tail_queries<4, 2>(a, i, j0, j1, L); break;
+    case 5: tail_queries<5, 2>(a, i, j0, j1, L); break;
+    case 6: tail_queries<6, 2>(a, i, j0, j1, L); break;
+    case 8: tail_queries<8, 2>(a, i, j0, j1, L); break;
+    case 10: tail_queries<10, 2>(a, i, j0, j1, L); break;
+    case 12: tail_queries<12, 2>(a, i, j0, j1, L); break;
+    case 15: tail_queries<15, 2>(a, i, j0, j1, L); break;
+    case 16: tail_queries<16, 2>(a, i, j0, j1, L); break;
+    case 20: tail_queries<20, 1>(a, i, j0, j1, L); break;
+    case 24: tail_queries<24, 1>(a, i, j0, j1, L); break;
+    default: tail_queries<32, 1>(a, i, j0, j1, L); break;
     }
 }
 
@@ -469,6 +584,7 @@ __global__ __launch_bounds__(BT) void k_batch(BatchArgs a)
                 task = a.tasks[slot];
                 st_rel(&a.seq[slot], want + 1);
                 atomicAdd(&a.q->tasks, 1ull);
+                atomicAdd(&a.q->wait_ticks, wall_clock64() - t0);
             }
         }
         __syncthreads();
@@ -478,10 +594,15 @@ __global__ __launch_bounds__(BT) void k_batch(BatchArgs a)
         __syncthreads();
         if (t.x == TASK_ORGANIZE) {
             organize_task(a, t.y, L);
-        } else if (t.x == TASK_SOLO) {
-            solo_task(a, t.y, L);
+        } else if (t.x == TASK_TAIL) {
+            tail_task(a, t.y, t.z, t.w, L);
+            __threadfence();
+            __syncthreads();
+            // the last TAIL task retires the instance
+            if (tid == 0 && atomicSub(&a.state[t.y].pending, 1) == 1 && atomicSub(&a.q->active, 1) == 1)
+                __hip_atomic_store(&a.q->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            if (t.x == TASK_FIND) find_task(a, t.y, t.z, t.w);
+            if (t.x == TASK_FIND) find_task(a, t.y, t.z, t.w, L);
             else scan_task(a, t.y, t.z, t.w);
             // the last task of the phase starts the next phase of this instance
             __threadfence();
@@ -494,7 +615,11 @@ __global__ __launch_bounds__(BT) void k_batch(BatchArgs a)
                 } else {
                     const int V = a.state[t.y].V;
                     if (V <= a.solo_max) {
-                        push_tasks(a, 1, [&](int) { return make_int4(TASK_SOLO, t.y, 0, 0); }, &L.base);
+                        const int T = (V + TAIL_CHUNK - 1) / TAIL_CHUNK;
+                        if (tid == 0) a.state[t.y].pending = T;
+                        push_tasks(a, T, [&](int j) {
+                            return make_int4(TASK_TAIL, t.y, j * TAIL_CHUNK, min(V, (j + 1) * TAIL_CHUNK));
+                        }, &L.base);
                     } else {
                         const int F = (V + FIND_CHUNK - 1) / FIND_CHUNK;
                         if (tid == 0) a.state[t.y].pending = F;
@@ -525,7 +650,8 @@ __global__ void k_batch_seed(BatchArgs a, const int4 *seed, int nseed, int nlive
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j < a.count) {
         const int m = a.inst[j].m;
-        a.state[j] = BState{0, 0, 0, (m + FIND_CHUNK - 1) / FIND_CHUNK};
+        const int chunk = m <= a.solo_max ? TAIL_CHUNK : FIND_CHUNK;  // the seed's task type
+        a.state[j] = BState{0, 0, 0, (m + chunk - 1) / chunk};
     }
     if (j < nseed) {
         a.tasks[j] = seed[j];
@@ -537,7 +663,7 @@ __global__ void k_batch_seed(BatchArgs a, const int4 *seed, int nseed, int nlive
         a.q->done = nlive == 0 ? 1 : 0;
         a.q->error = 0;
         a.q->active = nlive;
-        a.q->tasks = a.q->pairs = a.q->flops = a.q->rounds = 0;
+        a.q->tasks = a.q->pairs = a.q->flops = a.q->rounds = a.q->wait_ticks = 0;
     }
 }
 __global__ void k_batch_finalize(const uint64_t *keys, int64_t count, int64_t *idx, float *dist, int squared)
@@ -578,6 +704,8 @@ struct Batch {
     bool ran = false;
     int cus = 256;
     unsigned long long spin_ticks = 0;
+    double wall_khz = 1.0;     // wall-clock counter rate
+    int32_t last_workgroups = 0;
     ~Batch()
     {
         for (auto &g : graphs) (void)hipGraphExecDestroy(g.second->exec);
@@ -722,6 +850,7 @@ Batch *batch_create(const bkd_instance *in, int32_t count, int32_t device, int32
     int rate_khz = 0;
     BKD_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device));
     b->spin_ticks = (unsigned long long)std::max(rate_khz, 1) * 1000ull * 60ull;  // 60 s guard
+    b->wall_khz = (double)std::max(rate_khz, 1);
     BKD_HIP(hipDeviceSynchronize());
     return b.release();
 }
@@ -771,16 +900,18 @@ void batch_run(Batch &b, const bkd_tuning *tune, hipStream_t s)
 {
     BKD_HIP(hipSetDevice(b.device));
     const bkd_tuning tu = normalise(tune ? tune : (b.have_tuned ? &b.tuned : nullptr));
+    b.last_workgroups = b.cus * tu.groups_per_cu;
     const auto key = std::make_tuple(tu.leaves_per_task, tu.groups_per_cu, tu.solo_max);
     auto it = b.graphs.find(key);
     if (it == b.graphs.end()) {
         auto G = std::make_unique<Batch::Graph>();
-        // first tasks: whole-instance solo rounds for small instances, FIND slices otherwise
+        // first tasks: per-query traversals (TAIL) for small instances, FIND slices otherwise
         std::vector<int4> seed;
         for (int i : b.live) {
             const int64_t m = b.inst[(size_t)i].m;
             if (m <= tu.solo_max) {
-                seed.push_back(make_int4(TASK_SOLO, i, 0, 0));
+                for (int64_t j0 = 0; j0 < m; j0 += TAIL_CHUNK)
+                    seed.push_back(make_int4(TASK_TAIL, i, (int)j0, (int)std::min<int64_t>(m, j0 + TAIL_CHUNK)));
             } else {
                 for (int64_t j0 = 0; j0 < m; j0 += FIND_CHUNK)
                     seed.push_back(make_int4(TASK_FIND, i, (int)j0, (int)std::min<int64_t>(m, j0 + FIND_CHUNK)));
@@ -858,6 +989,8 @@ void batch_stats(Batch &b, bkd_batch_stats *out)
     out->pairs = (int64_t)q.pairs;
     out->flops = (int64_t)q.flops;
     out->error = q.error;
+    out->workgroups = b.last_workgroups;
+    out->claim_wait_ms = (double)q.wait_ticks / b.wall_khz;
     float ms = 0;
     BKD_HIP(hipEventElapsedTime(&ms, b.ev0, b.ev1));
     out->run_ms = ms;
@@ -867,7 +1000,7 @@ void batch_autotune(Batch &b, bkd_tuning *best, double *best_ms)
 {
     const int lpts[] = {4, 16, 64};
     const int gpcs[] = {2, 4};
-    const int solos[] = {512, 2048, 8192};
+    const int solos[] = {512, 2048, 8192, 32768};
     hipStream_t s = b.cap_stream;
     double bm = 1e300;
     bkd_tuning bt{8, 4, 2048};
