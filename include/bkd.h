@@ -83,6 +83,11 @@ typedef struct bkd_tree bkd_tree;
  *                 and the chunked-versus-resident comparison).
  *   device        HIP device ordinal.
  *   flags         BKD_FLAG_* bits.
+ *   tail_max      lock-step schedule on a resident structure: once at most this
+ *                 many queries are pending, the rounds stop and each of them
+ *                 finishes its traversal alone (one workgroup per query).
+ *                 0: the default (32768); < 0: rounds to the end (as
+ *                 BKD_FLAG_NO_TAIL).
  * Results are identical for every value of these options.
  */
 typedef struct bkd_options {
@@ -93,6 +98,7 @@ typedef struct bkd_options {
     int32_t num_chunks;
     int32_t device;
     int32_t flags;
+    int64_t tail_max;
 } bkd_options;
 
 /* Static facts of a built tree. */

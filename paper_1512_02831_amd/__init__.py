@@ -34,7 +34,8 @@ class BkdError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("buffer_size", ctypes.c_int64), ("fetch_size", ctypes.c_int64),
                 ("leaf_budget_bytes", ctypes.c_int64), ("chunk_mode", ctypes.c_int32),
-                ("num_chunks", ctypes.c_int32), ("device", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("num_chunks", ctypes.c_int32), ("device", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("tail_max", ctypes.c_int64)]
 
 
 class TreeInfo(ctypes.Structure):
@@ -134,11 +135,11 @@ def default_options(height: int) -> Options:
 
 
 def make_options(height: int, buffer_size=None, fetch_size=None, leaf_budget_bytes=None, chunk_mode=None,
-                 num_chunks=None, device=None, flags=None) -> Options:
+                 num_chunks=None, device=None, flags=None, tail_max=None) -> Options:
     o = default_options(height)
     for name, val in (("buffer_size", buffer_size), ("fetch_size", fetch_size),
                       ("leaf_budget_bytes", leaf_budget_bytes), ("chunk_mode", chunk_mode),
-                      ("num_chunks", num_chunks), ("device", device), ("flags", flags)):
+                      ("num_chunks", num_chunks), ("device", device), ("flags", flags), ("tail_max", tail_max)):
         if val is not None:
             setattr(o, name, val)
     return o

@@ -227,8 +227,9 @@ struct ScanArgs {
     int32_t *done_list;
 };
 
-// Pending queries at or below which the lock-step rounds hand over to the tail kernel.
-constexpr int64_t TAIL_MAX = 2048;
+// Default number of pending queries at or below which the lock-step rounds hand over to
+// the tail kernel (bkd_options.tail_max).
+constexpr int64_t TAIL_MAX = 32768;
 
 // Relative error band c of the dense scan's inner-product filter: 2^-12 for the
 // bfloat16-split matrix-core inner product (derivation beside the kernel).

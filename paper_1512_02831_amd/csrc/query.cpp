@@ -542,7 +542,8 @@ struct Run {
             }
             if (first && !tracing) localize();
             first = false;
-            if (t.resident && !tracing && !(t.opt.flags & BKD_FLAG_NO_TAIL) && P <= TAIL_MAX) {
+            const int64_t tail_max = t.opt.tail_max == 0 ? TAIL_MAX : t.opt.tail_max;
+            if (t.resident && !tracing && !(t.opt.flags & BKD_FLAG_NO_TAIL) && P <= tail_max) {
                 tail(P);
                 end_call();
                 break;

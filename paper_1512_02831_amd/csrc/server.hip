@@ -218,6 +218,11 @@ static int64_t session_admit(Session &S, std::unique_lock<std::mutex> &lk)
     return nnew;
 }
 
+// Pending queries at or below which a session's round hands them all to the tail kernel.
+// Lower than the single-call default: a session keeps admitting work, and its
+// rounds share leaf reads among the queries in flight.
+constexpr int64_t SERVED_TAIL_MAX = 2048;
+
 // One round: route the last round's queries and the new ones, buffer them, scan.
 static void session_round(Session &S, int64_t nnew)
 {
@@ -252,7 +257,7 @@ static void session_round(Session &S, int64_t nnew)
     BKD_HIP(hipMemcpyAsync(hctl, ctl, sizeof(int32_t) * CTL_WORDS, hipMemcpyDeviceToHost, S.s));
     BKD_HIP(hipStreamSynchronize(S.s));
     S.P = hctl[CTL_V];
-    if (S.P > 0 && S.P <= TAIL_MAX) {
+    if (S.P > 0 && S.P <= SERVED_TAIL_MAX) {
         // few queries in flight: each finishes its traversal in one workgroup, and its request
         // completes as its last query does
         ScanArgs a{};

@@ -189,16 +189,17 @@ def test_edge_shapes(n, m, d, k, h):
     check_trace(tr, oracle.replay(P, t_or, Q, k, B=o.buffer_size, M=o.fetch_size))
 
 
-@pytest.mark.parametrize("n,m,d,k,h", [
-    (1 << 16, 6000, 10, 10, 6),   # rounds first, then the tail below 2048 pending queries
-    (20000, 700, 5, 32, 5),       # tail right after the first round's sort
-    (5000, 300, 15, 64, 4),       # largest k in the tail
-    (3000, 2048, 3, 1, 8),        # exactly the hand-over size
+@pytest.mark.parametrize("n,m,d,k,h,tail_max", [
+    (1 << 16, 6000, 10, 10, 6, 2048),  # rounds first, then the tail below 2048 pending queries
+    (20000, 700, 5, 32, 5, 0),         # default threshold: tail right after the first round's sort
+    (5000, 300, 15, 64, 4, 0),         # largest k in the tail
+    (3000, 2048, 3, 1, 8, 2048),       # exactly the hand-over size
+    (40000, 3000, 10, 10, 7, 1),       # a single pending query left for the tail
 ])
-def test_lockstep_tail_matches_rounds_and_oracle(n, m, d, k, h):
-    say(f"case: tail n={n} m={m} d={d} k={k} h={h}")
+def test_lockstep_tail_matches_rounds_and_oracle(n, m, d, k, h, tail_max):
+    say(f"case: tail n={n} m={m} d={d} k={k} h={h} tail_max={tail_max}")
     P, Q = datagen.mixture_pq(seed=n + m, n=n, m=m, d=d, comps=5)
-    tail, _, st_tail, _ = gpu_keys(P, Q, k, h, buffer_size=-1, fetch_size=-1)
+    tail, _, st_tail, _ = gpu_keys(P, Q, k, h, buffer_size=-1, fetch_size=-1, tail_max=tail_max)
     rounds, _, st_rounds, _ = gpu_keys(P, Q, k, h, buffer_size=-1, fetch_size=-1, flags=bkd.FLAG_NO_TAIL)
     assert np.array_equal(tail, rounds)
     assert np.array_equal(tail, oracle.brute_f32c(P, Q, k))
