@@ -23,6 +23,7 @@ inline unsigned grid_for(int64_t count, int threads) { return (unsigned)((count 
 __device__ inline uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
 constexpr int FIND_LDS_SPLITS = 2047;  // heap nodes of the top 11 levels
+constexpr int FIND_LDS_DIMS = 16;      // queries of up to this dimension walk from LDS
 
 // ---------------------------------------------------------------------------
 
@@ -55,8 +56,10 @@ __global__ __launch_bounds__(256) void k_find_leaf(FetchSpec f, const float *__r
                                                    int64_t pend_base, int32_t *__restrict__ cnt,
                                                    int32_t *__restrict__ ctl)
 {
-    // the upper levels of the split array, shared by every walk of the block
+    // the upper levels of the split array, shared by every walk of the block, and each
+    // lane's query (coordinate-major, so lanes at different levels hit distinct banks)
     __shared__ float split_lds[FIND_LDS_SPLITS];
+    __shared__ float q_lds[FIND_LDS_DIMS * 256];
     const int lds_nodes = min((1 << h) - 1, FIND_LDS_SPLITS);
     for (int i = threadIdx.x; i < lds_nodes; i += blockDim.x) split_lds[i] = split[i];
     __syncthreads();
@@ -79,7 +82,14 @@ __global__ __launch_bounds__(256) void k_find_leaf(FetchSpec f, const float *__r
         const float *qp = Q + (int64_t)q * d;
         const int kk = f.kq ? f.kq[q] : k;
         const int32_t st = node[q];
-        const int32_t v = next_leaf(st, qp, keys + (int64_t)q * K + (kk - 1), split, split_lds, lds_nodes, h, d);
+        int32_t v;
+        if (d <= FIND_LDS_DIMS) {
+            float *ql = q_lds + threadIdx.x;
+            for (int c = 0; c < d; c++) ql[c * 256] = qp[c];
+            v = next_leaf(st, ql, keys + (int64_t)q * K + (kk - 1), split, split_lds, lds_nodes, h, d, 256);
+        } else {
+            v = next_leaf(st, qp, keys + (int64_t)q * K + (kk - 1), split, split_lds, lds_nodes, h, d);
+        }
         node[q] = v;
         if (f.req_left && v == NODE_DONE && st != NODE_DONE) {
             // last query of its request: record the request as complete

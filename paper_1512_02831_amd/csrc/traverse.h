@@ -22,9 +22,10 @@ constexpr uint64_t EMPTY_KEY = 0x7F800000FFFFFFFFull;
 // Every loop iteration is one step, up or down, reading one split value and
 // one query coordinate, so that the lanes of a wave advance together whatever
 // the level at which each turns around.  Splits of heap nodes below
-// lds_nodes are read from split_lds (a copy in LDS), the others from split.
+// lds_nodes are read from split_lds (a copy in LDS), the others from split;
+// coordinate j of the query is qp[j * qstride].
 __device__ inline int32_t next_leaf(int32_t st, const float *qp, const uint64_t *kth_key, const float *split,
-                                    const float *split_lds, int lds_nodes, int h, int d)
+                                    const float *split_lds, int lds_nodes, int h, int d, int qstride = 1)
 {
     if (st == NODE_DONE) return NODE_DONE;
     int32_t node, from = -1;
@@ -48,7 +49,7 @@ __device__ inline int32_t next_leaf(int32_t st, const float *qp, const uint64_t 
     }
     for (;;) {
         const float s = node < lds_nodes ? split_lds[node] : split[node];
-        const float qd = qp[dim];
+        const float qd = qp[dim * qstride];
         const int32_t left = 2 * node + 1;
         const int32_t nearc = (qd < s) ? left : left + 1;
         if (down) {
