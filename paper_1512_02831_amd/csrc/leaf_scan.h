@@ -8,25 +8,27 @@
 // Matrix-core filter.  Once every query of a wave has K candidates, a pair is
 // first tested with the expansion |q-x|^2 = |q'|^2 + |x'|^2 - 2<q',x'> on
 // coordinates relative to the leaf centre c (q' = q-c, x' = x-c, rounded to
-// float32).  The inner products of 32 points against the wave's 64 queries
-// are two 32x32 tiles on the matrix cores: every centred coordinate is split
-// into bfloat16 parts hi + lo, and <q',x'> ~ xl.qh + xh.ql + xh.qh takes three
-// v_mfma_f32_32x32x16_bf16 per tile and 16 coordinates, a third of the
-// matrix-core time of float32 MFMA.  The vector unit then does one
-// subtraction and half a max per pair.  A pair passes when
-// <q',x'> - (1-c) |x'|^2/2 >= ((1-c) |q'|^2 - thr)/2 - eta, thr the query's
-// current K-th squared distance.  With S = |q'|^2 + |x'|^2, the dropped split
-// terms are at most 3 2^-16 sum |q'_j x'_j| <= 1.5 2^-16 S per inner product,
-// the float32 accumulation in the matrix unit (any order, rounding either
+// float32).  Every centred coordinate is split into bfloat16 parts hi + lo,
+// and G = <q',x'> - (1-c)|x'|^2/2 is formed on the matrix cores from the
+// 3d + 2 products xh.qh, xl.qh, xh.ql (d each) and bs_hi.1, bs_lo.1 (the
+// split of the point's scaled norm, times one in the query operand), laid end
+// to end and cut into steps of sixteen: one v_mfma_f32_32x32x16_bf16 per step
+// and 32x32 tile of 32 points against 32 of the wave's 64 queries (two steps
+// at d = 10, where three separate products would take three).  The vector
+// unit then takes half a max per pair.  A pair passes when
+// G >= ((1-c) |q'|^2 - thr)/2 - eta, thr the query's current K-th squared
+// distance.  With S = |q'|^2 + |x'|^2, the dropped split terms are at most
+// 3 2^-16 sum |q'_j x'_j| <= 1.5 2^-16 S, the norm's split at most 2^-16 S/2,
+// and the float32 accumulation in the matrix unit (any order, rounding either
 // way) and every other float32 step add well under 2^-16 S, so the expansion
-// is within 2^-14 S of the float32 distance; c = 2^-12 is four times that and
-// also covers the final comparison's rounding (a borderline pair has
-// thr <= 2S).  eta = 2^-100 covers parts and products flushed to zero below
-// the normal range.  Passing pairs go to the lane owning the query, which
-// re-checks them with the exact float32 distance, so keys and results are
-// bit-identical to the exact path.  A wave holding a query whose list is not
-// full yet (a first visit) takes the exact path, every point through the
-// float32 distance, 32 points at a time until all its lists are full.
+// is within 2^-13 S of the float32 distance; c = 2^-12 is twice that and also
+// covers the final comparison's rounding (a borderline pair has thr <= 2S).
+// eta = 2^-100 covers parts and products flushed to zero below the normal
+// range.  Passing pairs go to the lane owning the query, which re-checks them
+// with the exact float32 distance, so keys and results are bit-identical to
+// the exact path.  A wave holding a query whose list is not full yet (a first
+// visit) takes the exact path, every point through the float32 distance, 32
+// points at a time until all its lists are full.
 //
 // Squared distances follow the float32 reading: t = q_j - x_j rounded, then
 // acc = fma(t, t, acc) for j = 0..d-1 from +0.  Padding dimensions hold zero in
@@ -91,18 +93,16 @@ template <int D, int K>
 __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
 {
     constexpr int DS = (D + 3) & ~3;   // row of the exact copy, padded for float4 reads
-    constexpr int KB = (D + 15) / 16;  // matrix-core steps of sixteen coordinates
-    // With a free slot after the coordinates, -bs rides in the point operand
-    // (times 1 in the query operand), so the accumulator already holds
-    // <q',x'> - bs and the vector unit only takes the max.
-    constexpr bool FOLD = D + 1 <= 16 * KB;
+    // Products of the filter's inner product, in operand order: xh.qh, xl.qh,
+    // xh.ql for every coordinate, then the two parts of -bs against 1.
+    constexpr int NT = 3 * D + 2;
+    constexpr int NS = (NT + 15) / 16;  // matrix-core steps of sixteen products
     constexpr int PT = D > 16 ? SCAN_PT / 2 : SCAN_PT;  // points per LDS tile
     constexpr int NB = PT / 32;        // 32-point blocks per tile
     __shared__ float4 xs[PT * DS / 4];  // original coordinates, point-major (exact distances)
-    // centred coordinates in matrix-core operand order, hi and lo parts in separate planes
-    // ([block][step][lane], 16 bytes per lane: every read and write is one contiguous kilobyte)
-    __shared__ bf16x8 xah[NB * KB * 64], xal[NB * KB * 64];
-    __shared__ float bs[FOLD ? 1 : PT];  // (1 - c) |x - centre|^2 / 2, +inf on padding rows
+    // point operands of the filter ([block][step][lane], 16 bytes per lane:
+    // every read and write is one contiguous kilobyte)
+    __shared__ bf16x8 xa[NB * NS * 64];
     __shared__ int32_t os[PT];
 
     int item = xcd_item(blockIdx.x, gridDim.x);
@@ -153,26 +153,26 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
     bool exact_wave = __any(act && isinf(thr));
 
     // Matrix-core operands of the filter.  The wave's 64 queries form two
-    // column tiles of 32; lane l supplies query (32 t + l % 32), coordinates
-    // 16 s + 8 (l / 32) .. + 7 of step s as bfloat16 hi and lo parts, and holds
+    // column tiles of 32; lane l supplies the query part of products
+    // 16 s + 8 (l / 32) .. + 7 of step s for query (32 t + l % 32), and holds
     // that query's threshold.
-    bf16x8 qh[2][KB], ql[2][KB];
+    bf16x8 qb[2][NS];
     float aq[2];
 #pragma unroll
     for (int t = 0; t < 2; t++) {
         const int src = 32 * t + col;
+        __bf16 gh[D], gl[D];
 #pragma unroll
-        for (int s2 = 0; s2 < KB; s2++) {
+        for (int j = 0; j < D; j++) split_bf16(__shfl(qc[j], src), gh[j], gl[j]);
+        auto part = [&](int u) -> __bf16 {  // query factor of product u
+            if (u < 2 * D) return gh[u < D ? u : u - D];
+            if (u < 3 * D) return gl[u - 2 * D];
+            return static_cast<__bf16>(u < NT ? 1.0f : 0.0f);
+        };
 #pragma unroll
-            for (int e = 0; e < 8; e++) {
-                const int j0 = 16 * s2 + e, j1 = 16 * s2 + 8 + e;
-                const float v0 = (j0 < D) ? __shfl(qc[j0 < D ? j0 : 0], src) : (FOLD && j0 == D) ? 1.0f : 0.0f;
-                const float v1 = (j1 < D) ? __shfl(qc[j1 < D ? j1 : 0], src) : (FOLD && j1 == D) ? 1.0f : 0.0f;
-                __bf16 h, l;
-                split_bf16(half ? v1 : v0, h, l);
-                qh[t][s2][e] = h;
-                ql[t][s2][e] = l;
-            }
+        for (int s2 = 0; s2 < NS; s2++) {
+#pragma unroll
+            for (int e = 0; e < 8; e++) qb[t][s2][e] = half ? part(16 * s2 + 8 + e) : part(16 * s2 + e);
         }
         aq[t] = __shfl(own_aq(), src);
     }
@@ -203,59 +203,32 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
     // register r of lane l holds point 32 b + (r % 4) + 8 (r / 4) + 4 (l / 32)
     // against query (32 t + l % 32).
     auto filter_block = [&](int b, int np) {
-        // <q',x'> ~ xl.qh + xh.ql + xh.qh (the lo.lo term and the split
-        // remainders stay within 3 2^-16 sum |q'_j x'_j|)
         f32x16 c0 = {}, c1 = {};
 #pragma unroll
-        for (int s2 = 0; s2 < KB; s2++) {
-            const bf16x8 ah = xah[(b * KB + s2) * 64 + lane];
-            const bf16x8 al = xal[(b * KB + s2) * 64 + lane];
-            c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, qh[0][s2], c0, 0, 0, 0);
-            c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, qh[1][s2], c1, 0, 0, 0);
-            c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, ql[0][s2], c0, 0, 0, 0);
-            c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, ql[1][s2], c1, 0, 0, 0);
-            c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, qh[0][s2], c0, 0, 0, 0);
-            c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, qh[1][s2], c1, 0, 0, 0);
-        }
-        float bv[16];
-#pragma unroll
-        for (int g = 0; g < 4; g++) {
-            if constexpr (FOLD) {
-                bv[4 * g] = bv[4 * g + 1] = bv[4 * g + 2] = bv[4 * g + 3] = 0.0f;
-            } else {
-                const float4 b4 = *reinterpret_cast<const float4 *>(bs + 32 * b + 8 * g + 4 * half);
-                bv[4 * g] = b4.x;
-                bv[4 * g + 1] = b4.y;
-                bv[4 * g + 2] = b4.z;
-                bv[4 * g + 3] = b4.w;
-            }
+        for (int s2 = 0; s2 < NS; s2++) {
+            const bf16x8 av = xa[(b * NS + s2) * 64 + lane];
+            c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, qb[0][s2], c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, qb[1][s2], c1, 0, 0, 0);
         }
         float m0 = -INFINITY, m1 = -INFINITY;
 #pragma unroll
         for (int r = 0; r < 16; r++) {
-            if constexpr (FOLD) {
-                m0 = fmaxf(m0, c0[r]);
-                m1 = fmaxf(m1, c1[r]);
-            } else {
-                m0 = fmaxf(m0, c0[r] - bv[r]);
-                m1 = fmaxf(m1, c1[r] - bv[r]);
-            }
+            m0 = fmaxf(m0, c0[r]);
+            m1 = fmaxf(m1, c1[r]);
         }
         if (!__any(m0 >= aq[0] || m1 >= aq[1])) return;
         // Some pair passed: hand each passing (point, query) to the lane that
         // owns the query (lane 32 t + j for column j of tile t), which
         // re-checks it with the exact float32 distance.
-        // (the per-pair test is taken as <q',x'> >= aq + bs here, so that the
-        // differences above need not stay live; both forms are within the band)
         // (masks are built only for a tile that has a passing pair)
         uint32_t f0 = 0, f1 = 0;
         if (__any(m0 >= aq[0])) {
 #pragma unroll
-            for (int r = 0; r < 16; r++) f0 |= (c0[r] >= aq[0] + bv[r]) ? (1u << r) : 0u;
+            for (int r = 0; r < 16; r++) f0 |= (c0[r] >= aq[0]) ? (1u << r) : 0u;
         }
         if (__any(m1 >= aq[1])) {
 #pragma unroll
-            for (int r = 0; r < 16; r++) f1 |= (c1[r] >= aq[1] + bv[r]) ? (1u << r) : 0u;
+            for (int r = 0; r < 16; r++) f1 |= (c1[r] >= aq[1]) ? (1u << r) : 0u;
         }
         const uint32_t lo0 = __shfl(f0, col), hi0 = __shfl(f0, col + 32);
         const uint32_t lo1 = __shfl(f1, col), hi1 = __shfl(f1, col + 32);
@@ -328,36 +301,39 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
         if (tid < npad) {
             const bool live = tid < np;
             float *ro = reinterpret_cast<float *>(xs) + tid * DS;
-            const int ra = (tid >> 5) * KB * 64 + (tid & 31);
+            const int ra = (tid >> 5) * NS * 64 + (tid & 31);
             float Xn = 0.0f;
-            float cv[16 * KB];
+            __bf16 gh[D], gl[D];
 #pragma unroll
-            for (int j = 0; j < 16 * KB; j++) {
-                cv[j] = (live && j < a.d && j < D) ? pre[j < DS ? j : 0] - cr[j < DS ? j : 0] : 0.0f;
-                Xn = fmaf(cv[j], cv[j], Xn);
+            for (int j = 0; j < D; j++) {
+                const float cv = (live && j < a.d) ? pre[j] - cr[j] : 0.0f;
+                Xn = fmaf(cv, cv, Xn);
+                split_bf16(cv, gh[j], gl[j]);
             }
 #pragma unroll
             for (int c4 = 0; c4 < DS / 4; c4++)
                 reinterpret_cast<float4 *>(ro)[c4] = make_float4(pre[4 * c4], pre[4 * c4 + 1], pre[4 * c4 + 2], pre[4 * c4 + 3]);
-            const float bsv = 0.5f * (coef * Xn);
             // padding rows: a large finite negative value keeps the split free of inf - inf
-            if constexpr (FOLD) cv[D] = live ? -bsv : -0x1p127f;
-            else bs[tid] = live ? bsv : INFINITY;
-            bf16x8 vh[2 * KB], vl[2 * KB];
+            const float nb = live ? -(0.5f * (coef * Xn)) : -0x1p127f;
+            __bf16 bh, bl;
+            split_bf16(nb, bh, bl);
+            auto part = [&](int u) -> __bf16 {  // point factor of product u
+                if (u < D) return gh[u];
+                if (u < 2 * D) return gl[u - D];
+                if (u < 3 * D) return gh[u - 2 * D];
+                if (u == 3 * D) return bh;
+                if (u == 3 * D + 1) return bl;
+                return static_cast<__bf16>(0.0f);
+            };
+            // products 16 s + 8 h .. + 7 of the point go to lane slot (tid % 32) + 32 h of step s
 #pragma unroll
-            for (int j = 0; j < 16 * KB; j++) {
-                __bf16 h, l;
-                split_bf16(cv[j], h, l);
-                vh[j >> 3][j & 7] = h;
-                vl[j >> 3][j & 7] = l;
-            }
-            // step s, half h of the point's coordinates go to lane slot (tid % 32) + 32 h
-#pragma unroll
-            for (int s2 = 0; s2 < KB; s2++) {
+            for (int s2 = 0; s2 < NS; s2++) {
 #pragma unroll
                 for (int h2 = 0; h2 < 2; h2++) {
-                    xah[ra + s2 * 64 + 32 * h2] = vh[2 * s2 + h2];
-                    xal[ra + s2 * 64 + 32 * h2] = vl[2 * s2 + h2];
+                    bf16x8 v;
+#pragma unroll
+                    for (int e = 0; e < 8; e++) v[e] = part(16 * s2 + 8 * h2 + e);
+                    xa[ra + s2 * 64 + 32 * h2] = v;
                 }
             }
             os[tid] = pre_o;

@@ -293,3 +293,78 @@ def test_band_bf16_split_with_folded_norm():
                 if S > 0:
                     worst = max(worst, abs(approx - d2) / bound)
     assert worst < 1
+
+
+def packed_dot(qc, xc, bs, rnd, rng):
+    """<q',x'> - bs as the dense scan forms it: the 3d + 2 bfloat16 products
+    xh.qh, xl.qh, xh.ql (d each) and bs_hi.1, bs_lo.1 laid end to end and cut
+    into matrix-unit steps of sixteen; each step adds its products and the
+    running accumulator in a random order, every sum rounded by rnd."""
+    d = len(qc)
+    qh = [round_bf16(v) for v in qc]
+    ql = [round_bf16(v - h) for v, h in zip(qc, qh)]
+    xh = [round_bf16(v) for v in xc]
+    xl = [round_bf16(v - h) for v, h in zip(xc, xh)]
+    bh = round_bf16(-bs)
+    bl = round_bf16(-bs - bh)
+    prods = ([xh[j] * qh[j] for j in range(d)] + [xl[j] * qh[j] for j in range(d)]
+             + [xh[j] * ql[j] for j in range(d)] + [bh, bl])
+    acc = Fraction(0)
+    for s in range(0, len(prods), 16):
+        group = prods[s:s + 16] + [acc]
+        sacc = Fraction(0)
+        for o in rng.permutation(len(group)):
+            sacc = rnd(sacc + group[o])
+        acc = sacc
+    return acc
+
+
+def test_band_bf16_packed_steps():
+    """The packed, folded form keeps the folded bound 2^-13 S at every padded dimension."""
+    rng = np.random.default_rng(9)
+    worst = Fraction(0)
+    for d in (2, 5, 10, 15, 16, 20, 32):
+        for _ in range(12):
+            cen = (rng.uniform(0, 20, d)).astype(np.float32)
+            spread = rng.choice([1e-3, 0.1, 2.0, 30.0])
+            q = (cen + rng.normal(0, spread, d)).astype(np.float32)
+            x = (cen + rng.normal(0, spread, d)).astype(np.float32)
+            qc = [sub(f(q[j]), f(cen[j])) for j in range(d)]
+            xc = [sub(f(x[j]), f(cen[j])) for j in range(d)]
+            Qn = Xn = Fraction(0)
+            for j in range(d):
+                Qn = fmaf(qc[j], qc[j], Qn)
+                Xn = fmaf(xc[j], xc[j], Xn)
+            bs = Fraction(round_f32(Xn / 2))
+            d2 = Fraction(0)
+            for j in range(d):
+                t = sub(f(q[j]), f(x[j]))
+                d2 = fmaf(t, t, d2)
+            S = Qn + Xn
+            for rnd in (lambda v: Fraction(round_f32(v)), round_rz):
+                approx = Qn - 2 * packed_dot(qc, xc, bs, rnd, rng)
+                bound = Fraction(1, 1 << 13) * S
+                assert abs(approx - d2) <= bound + Fraction(1, 10 ** 40)
+                if S > 0:
+                    worst = max(worst, abs(approx - d2) / bound)
+    assert worst < 1
+
+
+def test_band_bf16_packed_steps_need_every_term():
+    """Negative control: losing the low part of the folded norm (one of the two
+    norm terms) breaks the bound."""
+    rng = np.random.default_rng(10)
+    broke = False
+    for _ in range(20):
+        d = 10
+        qc = [Fraction(float(v)) for v in rng.normal(0, 3, d).astype(np.float32)]
+        xc = [Fraction(float(v)) for v in rng.normal(0, 3, d).astype(np.float32)]
+        Qn = sum(v * v for v in qc)
+        Xn = sum(v * v for v in xc)
+        bs = Fraction(round_f32(Xn / 2))
+        exact = sum(a * b for a, b in zip(qc, xc)) - bs
+        full = packed_dot(qc, xc, bs, lambda v: Fraction(round_f32(v)), rng)
+        lost = full - (round_bf16(-bs - round_bf16(-bs)))
+        assert abs(full - exact) <= Fraction(1, 1 << 14) * (Qn + Xn)
+        broke |= abs(lost - exact) > Fraction(1, 1 << 14) * (Qn + Xn)
+    assert broke
