@@ -134,7 +134,7 @@ struct Tree {
     // query workspace
     DevBuf d_Q, d_outi, d_outd;
     DevBuf d_Qp, d_perm;  // lock-step rounds: queries renumbered in first-leaf order
-    DevBuf d_keys, d_node, d_ring, d_pleaf, d_pq, d_tleaf, d_tq, d_hist;
+    DevBuf d_keys, d_kth, d_node, d_ring, d_pleaf, d_pq, d_tleaf, d_tq, d_hist;
     DevBuf d_cnt, d_cnt0, d_off, d_tiles, d_ctl;  // d_cnt0: run starts of the sorted pending list
     DevBuf d_chunk_of, d_rleaf, d_rq, d_rcnt;  // chunk sweep: leaf -> chunk, per-chunk pending regions
     PinnedBuf h_rcnt;
@@ -154,8 +154,7 @@ struct FetchSpec {
     int64_t ring_head, ring_count, ring_cap;
     int64_t in_start, in_count;  // input queue part: queries in_start .. in_start + in_count - 1
     const int32_t *in_list = nullptr;  // if set, the input part holds in_list[in_start ..] instead
-    // served form: per-query k, owning request, outstanding-query counters and the completion list
-    const int32_t *kq = nullptr;
+    // served form: owning request, outstanding-query counters and the completion list
     const int32_t *req_of = nullptr;
     int32_t *req_left = nullptr;
     int32_t *done_list = nullptr;  // done_list[0] = count, then request table indices
@@ -166,9 +165,9 @@ struct FetchSpec {
     bool count_leaves = true;
 };
 
-void launch_init_state(int32_t *node, uint64_t *keys, int64_t m, int K, hipStream_t s);
+void launch_init_state(int32_t *node, uint64_t *keys, uint32_t *kth, int64_t m, int K, hipStream_t s);
 void launch_check_finite(const float *Q, int64_t count, int32_t *ctl, hipStream_t s);
-void launch_find_leaf(const FetchSpec &f, const float *Q, int d, int32_t *node, const uint64_t *keys, int K, int k,
+void launch_find_leaf(const FetchSpec &f, const float *Q, int d, int32_t *node, const uint32_t *kth,
                       const float *split, int h, uint32_t *pend_leaf, int32_t *pend_q, int64_t pend_base,
                       int32_t *cnt, int32_t *ctl, hipStream_t s);
 // Stable sort of (leaf, query) pairs by leaf; returns which buffer holds the result (0: a, 1: b).
@@ -209,6 +208,7 @@ struct ScanArgs {
     const float *Q;           // [m][d]
     int d;
     uint64_t *keys;           // [m][K]
+    uint32_t *kth;            // [m] high word of each query's k-th key (its pruning distance)
     const float *centers;     // [nleaf][d] leaf centres of the inner-product filter
     float filter_coef;        // 1 - c(d), c(d) the relative error band of the filter
     // tail of the lock-step schedule (resident structure): pending (leaf, query) entries
@@ -220,7 +220,7 @@ struct ScanArgs {
     const float *split;       // [2^h - 1]
     int h, k;                 // tree height; k of the query (pruning uses the k-th key)
     int32_t *ctl;             // visit and pair counters
-    // served form: per-query k, owning request, outstanding-query counters, completion list
+    // served form: per-query k (else k), owning request, outstanding-query counters, completion list
     const int32_t *kq;
     const int32_t *req_of;
     int32_t *req_left;

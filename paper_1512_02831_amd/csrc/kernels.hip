@@ -27,10 +27,13 @@ constexpr int FIND_LDS_DIMS = 16;      // queries of up to this dimension walk f
 
 // ---------------------------------------------------------------------------
 
-__global__ void k_init_state(int32_t *node, uint64_t *keys, int64_t m, int K)
+__global__ void k_init_state(int32_t *node, uint64_t *keys, uint32_t *kth, int64_t m, int K)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m) node[i] = NODE_FRESH;
+    if (i < m) {
+        node[i] = NODE_FRESH;
+        kth[i] = (uint32_t)(EMPTY_KEY >> 32);
+    }
     int64_t total = m * K;
     for (int64_t j = i; j < total; j += (int64_t)gridDim.x * blockDim.x) keys[j] = EMPTY_KEY;
 }
@@ -50,8 +53,8 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t count)
 }
 
 __global__ __launch_bounds__(256) void k_find_leaf(FetchSpec f, const float *__restrict__ Q, int d,
-                                                   int32_t *__restrict__ node, const uint64_t *__restrict__ keys,
-                                                   int K, int k, const float *__restrict__ split, int h,
+                                                   int32_t *__restrict__ node, const uint32_t *__restrict__ kth,
+                                                   const float *__restrict__ split, int h,
                                                    uint32_t *__restrict__ pend_leaf, int32_t *__restrict__ pend_q,
                                                    int64_t pend_base, int32_t *__restrict__ cnt,
                                                    int32_t *__restrict__ ctl)
@@ -80,15 +83,14 @@ __global__ __launch_bounds__(256) void k_find_leaf(FetchSpec f, const float *__r
         else if (f.in_list) q = f.in_list[f.in_start + (j - f.ring_count)];
         else q = (int32_t)(f.in_start + (j - f.ring_count));
         const float *qp = Q + (int64_t)q * d;
-        const int kk = f.kq ? f.kq[q] : k;
         const int32_t st = node[q];
         int32_t v;
         if (d <= FIND_LDS_DIMS) {
             float *ql = q_lds + threadIdx.x;
             for (int c = 0; c < d; c++) ql[c * 256] = qp[c];
-            v = next_leaf(st, ql, keys + (int64_t)q * K + (kk - 1), split, split_lds, lds_nodes, h, d, 256);
+            v = next_leaf(st, ql, kth + q, split, split_lds, lds_nodes, h, d, 256);
         } else {
-            v = next_leaf(st, qp, keys + (int64_t)q * K + (kk - 1), split, split_lds, lds_nodes, h, d);
+            v = next_leaf(st, qp, kth + q, split, split_lds, lds_nodes, h, d);
         }
         node[q] = v;
         if (f.req_left && v == NODE_DONE && st != NODE_DONE) {
@@ -436,10 +438,10 @@ static void check_launch()
     if (e != hipSuccess) fail(BKD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
 }
 
-void launch_init_state(int32_t *node, uint64_t *keys, int64_t m, int K, hipStream_t s)
+void launch_init_state(int32_t *node, uint64_t *keys, uint32_t *kth, int64_t m, int K, hipStream_t s)
 {
     if (m <= 0) return;
-    k_init_state<<<grid_for(m, 256), 256, 0, s>>>(node, keys, m, K);
+    k_init_state<<<grid_for(m, 256), 256, 0, s>>>(node, keys, kth, m, K);
     check_launch();
 }
 
@@ -458,13 +460,13 @@ void launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s)
     check_launch();
 }
 
-void launch_find_leaf(const FetchSpec &f, const float *Q, int d, int32_t *node, const uint64_t *keys, int K, int k,
+void launch_find_leaf(const FetchSpec &f, const float *Q, int d, int32_t *node, const uint32_t *kth,
                       const float *split, int h, uint32_t *pend_leaf, int32_t *pend_q, int64_t pend_base,
                       int32_t *cnt, int32_t *ctl, hipStream_t s)
 {
     int64_t total = f.ring_count + f.in_count;
     if (total <= 0) return;
-    k_find_leaf<<<grid_for(total, 256), 256, 0, s>>>(f, Q, d, node, keys, K, k, split, h, pend_leaf, pend_q,
+    k_find_leaf<<<grid_for(total, 256), 256, 0, s>>>(f, Q, d, node, kth, split, h, pend_leaf, pend_q,
                                                      pend_base, cnt, ctl);
     check_launch();
 }

@@ -89,6 +89,19 @@ __device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo)
     lo = static_cast<__bf16>(x - static_cast<float>(hi));
 }
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two float32 values rounded to bfloat16 (nearest even) in one word: a in the
+// low half, b in the high half.
+__device__ inline uint32_t pack_bf16x2(float a, float b)
+{
+    const f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+__device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
 template <int D, int K>
 __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
 {
@@ -284,12 +297,17 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
     auto load_tile = [&](int64_t pt) {
         if (PT < SCAN_THREADS && tid >= PT) return;
         const int np = (int)min((int64_t)PT, p1 - pt);
-        const bool live = tid < np;
-        const int i = live ? (int)(pt - l0) + tid : first_pt;
+        // rows past the tile load a valid point of the item; they are never read as points
+        const int i = tid < np ? (int)(pt - l0) + tid : first_pt;
+        if (a.d == D) {
 #pragma unroll
-        for (int j = 0; j < DS; j++) {
-            const float x = X[(j < a.d ? j : 0) * len + i];
-            pre[j] = (live && j < a.d) ? x : 0.0f;
+            for (int j = 0; j < DS; j++) pre[j] = (j < D) ? X[(j < D ? j : 0) * len + i] : 0.0f;
+        } else {
+#pragma unroll
+            for (int j = 0; j < DS; j++) {
+                const float x = X[(j < a.d ? j : 0) * len + i];
+                pre[j] = (j < a.d) ? x : 0.0f;
+            }
         }
         pre_o = orig[i];
     };
@@ -302,38 +320,45 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
             const bool live = tid < np;
             float *ro = reinterpret_cast<float *>(xs) + tid * DS;
             const int ra = (tid >> 5) * NS * 64 + (tid & 31);
-            float Xn = 0.0f;
-            __bf16 gh[D], gl[D];
+            // centred coordinates (zero past d), their bfloat16 hi parts H and lo
+            // parts Lo, two coordinates to a word
+            constexpr int DP = (D + 1) / 2;
+            float cv[2 * DP], Xn = 0.0f;
 #pragma unroll
-            for (int j = 0; j < D; j++) {
-                const float cv = (live && j < a.d) ? pre[j] - cr[j] : 0.0f;
-                Xn = fmaf(cv, cv, Xn);
-                split_bf16(cv, gh[j], gl[j]);
+            for (int j = 0; j < 2 * DP; j++) {
+                cv[j] = (j < D) ? pre[j < D ? j : 0] - cr[j < D ? j : 0] : 0.0f;
+                if (j < D) Xn = fmaf(cv[j], cv[j], Xn);
+            }
+            uint32_t H[DP], Lo[DP];
+#pragma unroll
+            for (int w = 0; w < DP; w++) {
+                H[w] = pack_bf16x2(cv[2 * w], cv[2 * w + 1]);
+                Lo[w] = pack_bf16x2(cv[2 * w] - bf16_lo(H[w]), cv[2 * w + 1] - bf16_hi(H[w]));
             }
 #pragma unroll
             for (int c4 = 0; c4 < DS / 4; c4++)
                 reinterpret_cast<float4 *>(ro)[c4] = make_float4(pre[4 * c4], pre[4 * c4 + 1], pre[4 * c4 + 2], pre[4 * c4 + 3]);
-            // padding rows: a large finite negative value keeps the split free of inf - inf
+            // -bs split into (hi, lo); padding rows take a large finite negative
+            // value, which keeps the split free of inf - inf and never passes
             const float nb = live ? -(0.5f * (coef * Xn)) : -0x1p127f;
-            __bf16 bh, bl;
-            split_bf16(nb, bh, bl);
-            auto part = [&](int u) -> __bf16 {  // point factor of product u
-                if (u < D) return gh[u];
-                if (u < 2 * D) return gl[u - D];
-                if (u < 3 * D) return gh[u - 2 * D];
-                if (u == 3 * D) return bh;
-                if (u == 3 * D + 1) return bl;
-                return static_cast<__bf16>(0.0f);
+            const uint32_t NBw = pack_bf16x2(nb, nb - bf16_lo(pack_bf16x2(nb, 0.0f)));
+            auto part = [&](int u) -> uint32_t {  // point factor of product u, in the low 16 bits
+                if (u < D) return (H[u >> 1] >> (16 * (u & 1))) & 0xffffu;
+                if (u < 2 * D) return (Lo[(u - D) >> 1] >> (16 * ((u - D) & 1))) & 0xffffu;
+                if (u < 3 * D) return (H[(u - 2 * D) >> 1] >> (16 * ((u - 2 * D) & 1))) & 0xffffu;
+                if (u == 3 * D) return NBw & 0xffffu;
+                if (u == 3 * D + 1) return NBw >> 16;
+                return 0u;
             };
+            auto word = [&](int w) -> uint32_t { return part(2 * w) | (part(2 * w + 1) << 16); };
             // products 16 s + 8 h .. + 7 of the point go to lane slot (tid % 32) + 32 h of step s
 #pragma unroll
             for (int s2 = 0; s2 < NS; s2++) {
 #pragma unroll
                 for (int h2 = 0; h2 < 2; h2++) {
-                    bf16x8 v;
-#pragma unroll
-                    for (int e = 0; e < 8; e++) v[e] = part(16 * s2 + 8 * h2 + e);
-                    xa[ra + s2 * 64 + 32 * h2] = v;
+                    const int w0 = 8 * s2 + 4 * h2;
+                    reinterpret_cast<uint4 *>(xa)[ra + s2 * 64 + 32 * h2] =
+                        make_uint4(word(w0), word(w0 + 1), word(w0 + 2), word(w0 + 3));
                 }
             }
             os[tid] = pre_o;
@@ -356,8 +381,14 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
         }
     }
     if (act) {
+        const int kk = a.kq ? a.kq[q] : a.k;
+        uint32_t kb = 0;
 #pragma unroll
-        for (int s2 = 0; s2 < K; s2++) a.keys[(int64_t)q * K + s2] = lst[s2];
+        for (int s2 = 0; s2 < K; s2++) {
+            a.keys[(int64_t)q * K + s2] = lst[s2];
+            if (s2 == kk - 1) kb = (uint32_t)(lst[s2] >> 32);
+        }
+        a.kth[q] = kb;
     }
 }
 
@@ -445,6 +476,7 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
         }
     }
     if (lane < K) kp[lane] = li;
+    if (lane == (a.kq ? a.kq[q] : a.k) - 1) a.kth[q] = (uint32_t)(li >> 32);
 }
 
 // Tail of the lock-step schedule.  When only a few queries are pending, a
@@ -559,6 +591,7 @@ template <int D, int K> __global__ __launch_bounds__(TAIL_THREADS) void k_tail(S
         leaf = v - first;
     }
     if (w == 0 && lane < K) kp[lane] = li;
+    if (w == 0 && lane == (a.kq ? a.kq[q] : a.k) - 1) a.kth[q] = (uint32_t)(li >> 32);
     if (threadIdx.x == 0) {
         a.node[q] = NODE_DONE;
         if (a.req_left) {

@@ -284,6 +284,7 @@ struct Run {
           kbits(key_bits_for(t_.nleaf)), tracing((t_.opt.flags & BKD_FLAG_TRACE) != 0)
     {
         t.d_keys.ensure(sizeof(uint64_t) * (size_t)m * K);
+        t.d_kth.ensure(sizeof(uint32_t) * (size_t)m);
         t.d_node.ensure(sizeof(int32_t) * (size_t)m);
         t.d_ring.ensure(sizeof(int32_t) * (size_t)m);
         t.d_pleaf.ensure(sizeof(uint32_t) * (size_t)m);
@@ -321,7 +322,7 @@ struct Run {
 
     void find_leaf_into(const FetchSpec &f, uint32_t *out_leaf, int32_t *out_q, int64_t base)
     {
-        launch_find_leaf(f, dQ, d, t.d_node.as<int32_t>(), t.d_keys.as<uint64_t>(), K, k, t.d_split.as<float>(), h,
+        launch_find_leaf(f, dQ, d, t.d_node.as<int32_t>(), t.d_kth.as<uint32_t>(), t.d_split.as<float>(), h,
                          out_leaf, out_q, base, cnt, ctl, s);
         t.stats.fetches++;
         const int64_t F = f.ring_count + f.in_count;
@@ -379,6 +380,8 @@ struct Run {
         a.Q = dQ;
         a.d = d;
         a.keys = t.d_keys.as<uint64_t>();
+        a.kth = t.d_kth.as<uint32_t>();
+        a.k = k;
         a.centers = t.d_centers.as<float>();
         a.filter_coef = 1.0f - filter_band(d);
         return a;
@@ -695,7 +698,7 @@ void tree_query_device(Tree &t, const float *dQ, int64_t m, int k, int64_t *d_id
     launch_fill_i32(r.ctl, 0, CTL_WORDS, s);
     launch_fill_i32(r.cnt, 0, t.nleaf, s);
     launch_check_finite(dQ, m * t.host.d, r.ctl, s);
-    launch_init_state(t.d_node.as<int32_t>(), t.d_keys.as<uint64_t>(), m, r.K, s);
+    launch_init_state(t.d_node.as<int32_t>(), t.d_keys.as<uint64_t>(), t.d_kth.as<uint32_t>(), m, r.K, s);
     if (t.M < 0) r.lockstep();
     else r.algorithm1();
     launch_finalize(t.d_keys.as<uint64_t>(), r.K, k, m, r.perm, d_idx, d_dist, (t.opt.flags & BKD_FLAG_SQUARED) != 0,

@@ -32,13 +32,15 @@ namespace {
 
 __global__ void k_admit(const float *__restrict__ stage, const int32_t *__restrict__ slots, int64_t m, int d, int K,
                         int k, int32_t table, float *__restrict__ Qpool, uint64_t *__restrict__ keys,
-                        int32_t *__restrict__ node, int32_t *__restrict__ kq, int32_t *__restrict__ req_of)
+                        uint32_t *__restrict__ kth, int32_t *__restrict__ node, int32_t *__restrict__ kq,
+                        int32_t *__restrict__ req_of)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
     const int32_t s = slots[i];
     for (int j = 0; j < d; j++) Qpool[(int64_t)s * d + j] = stage[i * d + j];
     for (int j = 0; j < K; j++) keys[(int64_t)s * K + j] = EMPTY_KEY;
+    kth[s] = (uint32_t)(EMPTY_KEY >> 32);
     node[s] = NODE_FRESH;
     kq[s] = k;
     req_of[s] = table;
@@ -90,7 +92,7 @@ struct Session {
     int max_req = 0;
     hipStream_t s = nullptr;
     // device state
-    DevBuf Qpool, keys, node, kq, req_of, req_left, done, pleaf, pq, tleaf, tq, hist, cnt, cnt0, off, tiles, ctl, newslots,
+    DevBuf Qpool, keys, kth, node, kq, req_of, req_left, done, pleaf, pq, tleaf, tq, hist, cnt, cnt0, off, tiles, ctl, newslots,
         stage, oidx, odist, gslots;
     PinnedBuf hctl, hdone, hstage, hout, hgslots;
     hipEvent_t ev_stage = nullptr;  // after the last admission's staging copies
@@ -129,6 +131,7 @@ static void session_init(Session &S)
     const int nleaf = S.tree->t.nleaf;
     S.Qpool.ensure(sizeof(float) * cap * H.d);
     S.keys.ensure(sizeof(uint64_t) * cap * S.K);
+    S.kth.ensure(sizeof(uint32_t) * cap);
     S.node.ensure(sizeof(int32_t) * cap);
     S.kq.ensure(sizeof(int32_t) * cap);
     S.req_of.ensure(sizeof(int32_t) * cap);
@@ -205,7 +208,8 @@ static int64_t session_admit(Session &S, std::unique_lock<std::mutex> &lk)
         for (Request *r : adm) {
             k_admit<<<(unsigned)((r->m + 255) / 256), 256, 0, S.s>>>(
                 S.stage.as<float>() + nnew * d, S.newslots.as<int32_t>() + nnew, r->m, d, S.K, r->k, r->table,
-                S.Qpool.as<float>(), S.keys.as<uint64_t>(), S.node.as<int32_t>(), S.kq.as<int32_t>(),
+                S.Qpool.as<float>(), S.keys.as<uint64_t>(), S.kth.as<uint32_t>(), S.node.as<int32_t>(),
+                S.kq.as<int32_t>(),
                 S.req_of.as<int32_t>());
             k_set_i32<<<1, 1, 0, S.s>>>(S.req_left.as<int32_t>(), r->table, (int32_t)r->m);
             nnew += r->m;
@@ -237,11 +241,10 @@ static void session_round(Session &S, int64_t nnew)
     FetchSpec f{qbuf[S.cur], 0, S.P, std::max<int64_t>(S.P, 1), 0, nnew};
     f.count_leaves = false;  // per-leaf counts come from the runs of the sorted list
     f.in_list = S.newslots.as<int32_t>();
-    f.kq = S.kq.as<int32_t>();
     f.req_of = S.req_of.as<int32_t>();
     f.req_left = S.req_left.as<int32_t>();
     f.done_list = S.done.as<int32_t>();
-    launch_find_leaf(f, S.Qpool.as<float>(), H.d, S.node.as<int32_t>(), S.keys.as<uint64_t>(), S.K, 1,
+    launch_find_leaf(f, S.Qpool.as<float>(), H.d, S.node.as<int32_t>(), S.kth.as<uint32_t>(),
                      T.d_split.as<float>(), H.h, leafbuf[S.cur], qbuf[S.cur], 0, S.cnt.as<int32_t>(), ctl, S.s);
     const int64_t total = S.P + nnew;
     int which = launch_sort_pairs(leafbuf[S.cur], qbuf[S.cur], leafbuf[1 - S.cur], qbuf[1 - S.cur], total,
@@ -267,6 +270,7 @@ static void session_round(Session &S, int64_t nnew)
         a.Q = S.Qpool.as<float>();
         a.d = H.d;
         a.keys = S.keys.as<uint64_t>();
+        a.kth = S.kth.as<uint32_t>();
         a.tail_leaf = leafbuf[S.cur];
         a.tail_q = qbuf[S.cur];
         a.tail_count = (int32_t)S.P;
@@ -303,6 +307,9 @@ static void session_round(Session &S, int64_t nnew)
         a.Q = S.Qpool.as<float>();
         a.d = H.d;
         a.keys = S.keys.as<uint64_t>();
+        a.kth = S.kth.as<uint32_t>();
+        a.k = S.K;
+        a.kq = S.kq.as<int32_t>();
         a.centers = T.d_centers.as<float>();
         a.filter_coef = 1.0f - filter_band(H.d);
         launch_leaf_scan(a, S.K, 0, S.s);

@@ -16,15 +16,20 @@ constexpr uint64_t EMPTY_KEY = 0x7F800000FFFFFFFFull;
 // left iff q[dim] < split.  After a visit the walk goes back up; at a parent
 // reached from its near child the far child is entered when the float32
 // plane term (q[dim]-s)^2 does not exceed the current k-th squared distance
-// (the high word of *kth_key), and the walk descends from there to its
-// nearest leaf; reaching the root from above ends the traversal.
+// (read through kth: the high word of a key, or those bits alone), and the
+// walk descends from there to its nearest leaf; reaching the root from above
+// ends the traversal.
 //
 // Every loop iteration is one step, up or down, reading one split value and
 // one query coordinate, so that the lanes of a wave advance together whatever
 // the level at which each turns around.  Splits of heap nodes below
 // lds_nodes are read from split_lds (a copy in LDS), the others from split;
 // coordinate j of the query is qp[j * qstride].
-__device__ inline int32_t next_leaf(int32_t st, const float *qp, const uint64_t *kth_key, const float *split,
+__device__ inline float kth_value(const uint64_t *key) { return __uint_as_float((uint32_t)(*key >> 32)); }
+__device__ inline float kth_value(const uint32_t *bits) { return __uint_as_float(*bits); }
+
+template <typename KthPtr>
+__device__ inline int32_t next_leaf(int32_t st, const float *qp, KthPtr kth_ptr, const float *split,
                                     const float *split_lds, int lds_nodes, int h, int d, int qstride = 1)
 {
     if (st == NODE_DONE) return NODE_DONE;
@@ -40,7 +45,7 @@ __device__ inline int32_t next_leaf(int32_t st, const float *qp, const uint64_t 
         down = true;
     } else {
         if (st == 0) return NODE_DONE;
-        kth = __uint_as_float((uint32_t)(*kth_key >> 32));
+        kth = kth_value(kth_ptr);
         from = st;
         node = (st - 1) >> 1;
         lvl = h - 1;
