@@ -55,15 +55,16 @@ namespace bkd {
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_PT = 256;  // points per LDS tile
 
+// Insert key c into the sorted list: every entry above c moves down one place
+// (the last one drops out) and c takes the first vacated place.
 template <int K> __device__ inline void key_insert(uint64_t (&lst)[K], uint64_t c)
 {
+    bool lt[K];
 #pragma unroll
-    for (int s = 0; s < K; s++) {
-        uint64_t a = lst[s];
-        bool lt = c < a;
-        lst[s] = lt ? c : a;
-        c = lt ? a : c;
-    }
+    for (int s = 0; s < K; s++) lt[s] = c < lst[s];
+#pragma unroll
+    for (int s = K - 1; s > 0; s--) lst[s] = lt[s - 1] ? lst[s - 1] : (lt[s] ? c : lst[s]);
+    lst[0] = lt[0] ? c : lst[0];
 }
 
 __device__ inline int xcd_item(int b, int grid)
@@ -232,8 +233,11 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
         if (!__any(m0 >= aq[0] || m1 >= aq[1])) return;
         // Some pair passed: hand each passing (point, query) to the lane that
         // owns the query (lane 32 t + j for column j of tile t), which
-        // re-checks it with the exact float32 distance.
-        // (masks are built only for a tile that has a passing pair)
+        // re-checks it with the exact float32 distance.  Bit r of a tile's
+        // mask is accumulator register r (masks are built only for a tile that
+        // has a passing pair); the owner of tile t (lanes with l / 32 = t)
+        // gets its partner's mask of the same column (lane l ^ 32), and bit
+        // 16 h + r of the merged mask is point (r % 4) + 8 (r / 4) + 4 h.
         uint32_t f0 = 0, f1 = 0;
         if (__any(m0 >= aq[0])) {
 #pragma unroll
@@ -243,22 +247,13 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
 #pragma unroll
             for (int r = 0; r < 16; r++) f1 |= (c1[r] >= aq[1]) ? (1u << r) : 0u;
         }
-        const uint32_t lo0 = __shfl(f0, col), hi0 = __shfl(f0, col + 32);
-        const uint32_t lo1 = __shfl(f1, col), hi1 = __shfl(f1, col + 32);
-        uint32_t mlo = half ? lo1 : lo0, mhi = half ? hi1 : hi0;
+        const uint32_t recv = __shfl_xor(half ? f0 : f1, 32);
+        uint32_t msk = half ? (recv | (f1 << 16)) : (f0 | (recv << 16));
         bool changed = false;
-        while (mlo | mhi) {
-            int r, h;
-            if (mlo) {
-                r = __builtin_ctz(mlo);
-                mlo &= mlo - 1;
-                h = 0;
-            } else {
-                r = __builtin_ctz(mhi);
-                mhi &= mhi - 1;
-                h = 1;
-            }
-            const int p = 32 * b + (r & 3) + 8 * (r >> 2) + 4 * h;
+        while (msk) {
+            const int i = __builtin_ctz(msk);
+            msk &= msk - 1;
+            const int p = 32 * b + (i & 3) + 8 * ((i >> 2) & 3) + 4 * (i >> 4);
             if (p >= np) continue;
             const float4 *xp = xs + p * (DS / 4);
             float acc = 0.0f;
