@@ -174,6 +174,15 @@ void launch_find_leaf(const FetchSpec &f, const float *Q, int d, int32_t *node, 
 int launch_sort_pairs(uint32_t *key_a, int32_t *val_a, uint32_t *key_b, int32_t *val_b, int64_t count, int key_bits,
                       uint32_t *hist, hipStream_t s);
 size_t sort_hist_words(int64_t count);
+// Grouping of (leaf, query) pairs by leaf in one pass, order within a leaf unspecified, for
+// at most bucket_max_keys() distinct keys: launch_bucket_count writes per-block key counts
+// and their column prefixes into hist and returns the key totals (inside hist);
+// launch_bucket_scatter then places the pairs, key k starting at off[k].
+int bucket_max_keys();
+const int32_t *launch_bucket_count(const uint32_t *keys, int64_t count, int nb, int nbits, uint32_t *hist,
+                                   hipStream_t s);
+void launch_bucket_scatter(const uint32_t *kin, const int32_t *vin, uint32_t *kout, int32_t *vout, int64_t count,
+                           int nb, int nbits, const uint32_t *hist, const int32_t *off, hipStream_t s);
 // tiles: [2][nleaf+1] -- dense work-item offsets, then sparse (per buffered query) offsets.
 void launch_leaf_offsets(const int32_t *cnt, const int32_t *start, const int32_t *leaf_off, int nleaf, int qt,
                          int dense_min, int32_t *off, int32_t *tiles, int32_t *sparse, int32_t *ctl, hipStream_t s);

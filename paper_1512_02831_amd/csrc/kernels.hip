@@ -282,6 +282,92 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const uint32_t *
 }
 
 // ---------------------------------------------------------------------------
+// Single-pass grouping by leaf for at most BK_MAX distinct keys.  The lock-step
+// rounds need every buffer's queries together but not in any particular order,
+// so a block claims output positions with LDS atomics (lanes holding the same
+// key are matched with one ballot per key bit and claim together).  Pass 1
+// writes each block's key counts (key-major), the column scan turns them into
+// per-block prefixes and key totals (the per-leaf counts), the buffer offsets
+// follow from the totals, and pass 2 scatters.
+
+constexpr int BK_THREADS = 256;
+constexpr int BK_PER = 32;
+constexpr int BK_TILE = BK_THREADS * BK_PER;
+constexpr int BK_MAX = 2048;
+
+// Lanes of the wave that hold the same key as this one (meaningful for valid lanes).
+__device__ inline uint64_t same_key_lanes(uint32_t key, int nbits, bool valid)
+{
+    uint64_t mask = __ballot(valid);
+    for (int b = 0; b < nbits; b++) {
+        const bool bit = (key >> b) & 1u;
+        const uint64_t bal = __ballot(valid && bit);
+        mask &= bit ? bal : ~bal;
+    }
+    return mask;
+}
+
+__global__ __launch_bounds__(BK_THREADS) void k_bucket_hist(const uint32_t *__restrict__ keys, int64_t count, int nb,
+                                                            int nbits, uint32_t *__restrict__ hist, int nblocks)
+{
+    __shared__ uint32_t h[BK_MAX];
+    for (int i = threadIdx.x; i < nb; i += BK_THREADS) h[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * BK_TILE + threadIdx.x;
+    uint32_t kr[BK_PER];
+#pragma unroll
+    for (int r = 0; r < BK_PER; r++) {
+        const int64_t i = base + (int64_t)r * BK_THREADS;
+        kr[r] = i < count ? keys[i] : 0u;
+    }
+    for (int r = 0; r < BK_PER; r++) {
+        const bool valid = base + (int64_t)r * BK_THREADS < count;
+        const uint64_t same = same_key_lanes(kr[r], nbits, valid);
+        if (valid && (same & lanemask_lt()) == 0) atomicAdd(&h[kr[r]], (uint32_t)__popcll(same));
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += BK_THREADS) hist[(int64_t)i * nblocks + blockIdx.x] = h[i];
+}
+
+// hist: per-block exclusive prefixes within each key (after the column scan);
+// off: start of each key's run in the output.
+__global__ __launch_bounds__(BK_THREADS) void k_bucket_scatter(const uint32_t *__restrict__ kin,
+                                                               const int32_t *__restrict__ vin,
+                                                               uint32_t *__restrict__ kout, int32_t *__restrict__ vout,
+                                                               int64_t count, int nb, int nbits,
+                                                               const uint32_t *__restrict__ hist, int nblocks,
+                                                               const int32_t *__restrict__ off)
+{
+    __shared__ uint32_t run[BK_MAX];
+    for (int i = threadIdx.x; i < nb; i += BK_THREADS)
+        run[i] = (uint32_t)off[i] + hist[(int64_t)i * nblocks + blockIdx.x];
+    __syncthreads();
+    const int lane = __lane_id();
+    const int64_t base = (int64_t)blockIdx.x * BK_TILE + threadIdx.x;
+    uint32_t kr[BK_PER];
+    int32_t vr[BK_PER];
+#pragma unroll
+    for (int r = 0; r < BK_PER; r++) {
+        const int64_t i = base + (int64_t)r * BK_THREADS;
+        kr[r] = i < count ? kin[i] : 0u;
+        vr[r] = i < count ? vin[i] : 0;
+    }
+    for (int r = 0; r < BK_PER; r++) {
+        const bool valid = base + (int64_t)r * BK_THREADS < count;
+        const uint64_t same = same_key_lanes(kr[r], nbits, valid);
+        const int leader = valid ? __ffsll((unsigned long long)same) - 1 : lane;
+        uint32_t p = 0;
+        if (valid && leader == lane) p = atomicAdd(&run[kr[r]], (uint32_t)__popcll(same));
+        p = __shfl(p, leader);
+        if (valid) {
+            const uint32_t pos = p + (uint32_t)__popcll(same & lanemask_lt());
+            kout[pos] = kr[r];
+            vout[pos] = vr[r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 
 // Buffer offsets (exclusive scan of the fills), work items of one call and
 // the pair / visit counters.  A leaf holding at least dense_min buffered
@@ -414,17 +500,25 @@ __global__ void k_finalize(const uint64_t *__restrict__ keys, int K, int k, int6
 // takes query q = ids[i] (perm[i] = q, coordinates copied, node = its leaf) and
 // ids[i] becomes i.  Queries sharing a buffer then have neighbouring numbers,
 // so per-query state is read and written in contiguous runs.
-__global__ void k_localize(int32_t *__restrict__ ids, const uint32_t *__restrict__ leaf, int64_t m, int d,
-                           const float *__restrict__ Q, float *__restrict__ Qp, int32_t *__restrict__ perm,
-                           int32_t *__restrict__ node, int32_t first, uint32_t nleaf)
+__global__ void k_localize(int32_t *__restrict__ ids, const uint32_t *__restrict__ leaf, int64_t m,
+                           int32_t *__restrict__ perm, int32_t *__restrict__ node, int32_t first, uint32_t nleaf)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
-    const int32_t q = ids[i];
-    perm[i] = q;
-    for (int j = 0; j < d; j++) Qp[i * d + j] = Q[(int64_t)q * d + j];
+    perm[i] = ids[i];
     node[i] = leaf[i] < nleaf ? first + (int32_t)leaf[i] : NODE_DONE;
     ids[i] = (int32_t)i;
+}
+
+// Coordinates in the new numbering, one word per thread: consecutive lanes
+// read consecutive words of a row and write consecutive words of the copy.
+__global__ void k_gather_rows(const float *__restrict__ Q, const int32_t *__restrict__ perm, int64_t m, int d,
+                              float *__restrict__ Qp)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m * d) return;
+    const int64_t i = e / d;
+    Qp[e] = Q[(int64_t)perm[i] * d + (e - i * d)];
 }
 
 }  // namespace
@@ -474,7 +568,32 @@ void launch_find_leaf(const FetchSpec &f, const float *Q, int d, int32_t *node, 
 size_t sort_hist_words(int64_t count)
 {
     int64_t nblocks = (count + SORT_TILE - 1) / SORT_TILE;
-    return (size_t)(std::max<int64_t>(nblocks, 1) + 1) * 256;  // histogram + column totals
+    const size_t radix = (size_t)(std::max<int64_t>(nblocks, 1) + 1) * 256;  // histogram + column totals
+    int64_t bblocks = (count + BK_TILE - 1) / BK_TILE;
+    const size_t bucket = (size_t)(std::max<int64_t>(bblocks, 1) + 1) * BK_MAX;
+    return std::max(radix, bucket);
+}
+
+int bucket_max_keys() { return BK_MAX; }
+
+const int32_t *launch_bucket_count(const uint32_t *keys, int64_t count, int nb, int nbits, uint32_t *hist,
+                                   hipStream_t s)
+{
+    const int nblocks = (int)((count + BK_TILE - 1) / BK_TILE);
+    uint32_t *totals = hist + (size_t)nb * nblocks;
+    if (nblocks > 0) k_bucket_hist<<<nblocks, BK_THREADS, 0, s>>>(keys, count, nb, nbits, hist, nblocks);
+    k_scan_columns<<<nb, 256, 0, s>>>(hist, nblocks, totals);
+    check_launch();
+    return reinterpret_cast<const int32_t *>(totals);
+}
+
+void launch_bucket_scatter(const uint32_t *kin, const int32_t *vin, uint32_t *kout, int32_t *vout, int64_t count,
+                           int nb, int nbits, const uint32_t *hist, const int32_t *off, hipStream_t s)
+{
+    const int nblocks = (int)((count + BK_TILE - 1) / BK_TILE);
+    if (nblocks == 0) return;
+    k_bucket_scatter<<<nblocks, BK_THREADS, 0, s>>>(kin, vin, kout, vout, count, nb, nbits, hist, nblocks, off);
+    check_launch();
 }
 
 int launch_sort_pairs(uint32_t *key_a, int32_t *val_a, uint32_t *key_b, int32_t *val_b, int64_t count, int key_bits,
@@ -555,7 +674,8 @@ void launch_localize(int32_t *ids, const uint32_t *leaf, int64_t m, int d, const
                      int32_t *node, int h, hipStream_t s)
 {
     if (m <= 0) return;
-    k_localize<<<grid_for(m, 256), 256, 0, s>>>(ids, leaf, m, d, Q, Qp, perm, node, (1 << h) - 1, 1u << h);
+    k_localize<<<grid_for(m, 256), 256, 0, s>>>(ids, leaf, m, perm, node, (1 << h) - 1, 1u << h);
+    k_gather_rows<<<grid_for(m * d, 256), 256, 0, s>>>(Q, perm, m, d, Qp);
     check_launch();
 }
 

@@ -344,19 +344,28 @@ struct Run {
     // did not count); otherwise from the fetch's counters.
     void sort_and_offsets(int64_t count, bool runs = false)
     {
-        int which = launch_sort_pairs(leafbuf[cur], qbuf[cur], leafbuf[1 - cur], qbuf[1 - cur], count, kbits,
-                                      t.d_hist.as<uint32_t>(), s);
-        if (which) cur = 1 - cur;
-        int32_t *start = nullptr;
-        if (runs) {
-            start = t.d_cnt0.as<int32_t>();
-            launch_fill_i32(cnt, 0, nleaf, s);
-            launch_fill_i32(start, 0, nleaf, s);
-            launch_run_bounds(leafbuf[cur], count, nleaf, start, cnt, s);
+        if (runs && !tracing && nleaf + 1 <= bucket_max_keys()) {
+            // lock-step rounds: group by leaf in one pass (order within a buffer is free)
+            const int nb = nleaf + 1;
+            uint32_t *hist = t.d_hist.as<uint32_t>();
+            const int32_t *counts = launch_bucket_count(leafbuf[cur], count, nb, kbits, hist, s);
+            offsets(counts, nullptr);
+            launch_bucket_scatter(leafbuf[cur], qbuf[cur], leafbuf[1 - cur], qbuf[1 - cur], count, nb, kbits, hist,
+                                  t.d_off.as<int32_t>(), s);
+            cur = 1 - cur;
+        } else {
+            int which = launch_sort_pairs(leafbuf[cur], qbuf[cur], leafbuf[1 - cur], qbuf[1 - cur], count, kbits,
+                                          t.d_hist.as<uint32_t>(), s);
+            if (which) cur = 1 - cur;
+            int32_t *start = nullptr;
+            if (runs) {
+                start = t.d_cnt0.as<int32_t>();
+                launch_fill_i32(cnt, 0, nleaf, s);
+                launch_fill_i32(start, 0, nleaf, s);
+                launch_run_bounds(leafbuf[cur], count, nleaf, start, cnt, s);
+            }
+            offsets(cnt, start);
         }
-        launch_leaf_offsets(cnt, start, t.d_leaf_off.as<int32_t>(), nleaf, SCAN_QT, SCAN_DENSE_MIN,
-                            t.d_off.as<int32_t>(), t.d_tiles.as<int32_t>(), t.d_tiles.as<int32_t>() + nleaf + 1, ctl,
-                            s);
         if (!t.resident) {
             BKD_HIP(hipMemcpyAsync(t.h_tiles.p, t.d_tiles.p, sizeof(int32_t) * 2 * (size_t)(nleaf + 1),
                                    hipMemcpyDeviceToHost, s));
@@ -364,6 +373,15 @@ struct Run {
                                    sizeof(int32_t) * (size_t)(nleaf + 1), hipMemcpyDeviceToHost, s));
         }
         readback();
+    }
+
+    // Buffer offsets, work items and the pending count from per-leaf counts
+    // (cnt, or end - start of each run when start is given).
+    void offsets(const int32_t *counts, const int32_t *start)
+    {
+        launch_leaf_offsets(counts, start, t.d_leaf_off.as<int32_t>(), nleaf, SCAN_QT, SCAN_DENSE_MIN,
+                            t.d_off.as<int32_t>(), t.d_tiles.as<int32_t>(), t.d_tiles.as<int32_t>() + nleaf + 1, ctl,
+                            s);
     }
 
     ScanArgs scan_args(const float *base, int64_t shift) const
