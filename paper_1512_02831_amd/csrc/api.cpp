@@ -131,6 +131,7 @@ int bkd_free(bkd_tree *tree)
             if (tree->t.ev_copied[b]) (void)hipEventDestroy(tree->t.ev_copied[b]);
             if (tree->t.ev_used[b]) (void)hipEventDestroy(tree->t.ev_used[b]);
         }
+        if (tree->t.ev_rb) (void)hipEventDestroy(tree->t.ev_rb);
         delete tree;
     });
 }

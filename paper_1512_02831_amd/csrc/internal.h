@@ -130,6 +130,7 @@ struct Tree {
     hipStream_t copy_stream = nullptr;
     hipEvent_t ev_copied[2] = {nullptr, nullptr};
     hipEvent_t ev_used[2] = {nullptr, nullptr};
+    hipEvent_t ev_rb = nullptr;  // readback of the control words
 
     // query workspace
     DevBuf d_Q, d_outi, d_outd;
@@ -184,8 +185,10 @@ const int32_t *launch_bucket_count(const uint32_t *keys, int64_t count, int nb, 
 void launch_bucket_scatter(const uint32_t *kin, const int32_t *vin, uint32_t *kout, int32_t *vout, int64_t count,
                            int nb, int nbits, const uint32_t *hist, const int32_t *off, hipStream_t s);
 // tiles: [2][nleaf+1] -- dense work-item offsets, then sparse (per buffered query) offsets.
+// count_work: also add the visits and pairs of scanning every buffer to the ctl counters.
 void launch_leaf_offsets(const int32_t *cnt, const int32_t *start, const int32_t *leaf_off, int nleaf, int qt,
-                         int dense_min, int32_t *off, int32_t *tiles, int32_t *sparse, int32_t *ctl, hipStream_t s);
+                         int dense_min, int32_t *off, int32_t *tiles, int32_t *sparse, int32_t *ctl, hipStream_t s,
+                         bool count_work = false);
 void launch_run_bounds(const uint32_t *leaf, int64_t count, int nleaf, int32_t *start, int32_t *end, hipStream_t s);
 void launch_distribute(const uint32_t *leaf, const int32_t *q, int64_t n, int nleaf, const int32_t *chunk_of, int c,
                        uint32_t *rleaf, int32_t *rq, int64_t rcap, int32_t *rcnt, uint32_t *sleaf, int32_t *sq,
@@ -212,6 +215,8 @@ struct ScanArgs {
     int64_t blk_shift;        // added to blk[l] to address the buffer (minus the buffer's first word)
     int64_t chunk_lo, chunk_hi;  // positions served by this launch
     int32_t item_first, item_count;    // dense items of this launch
+    const int32_t *dev_counts;         // if set, the dense item count is dev_counts[CTL_T] and
+                                       // item_count is only an upper bound that sizes the grid
     int32_t sitem_first, sitem_count;  // sparse items of this launch
     int32_t leaf_first, leaf_last;
     const float *Q;           // [m][d]
@@ -225,6 +230,7 @@ struct ScanArgs {
     const uint32_t *tail_leaf;
     const int32_t *tail_q;
     int32_t tail_count;
+    int tail_counted;         // the first visit of each tail entry is already in the work counters
     int32_t *node;            // [m] traversal state, set to DONE at the end
     const float *split;       // [2^h - 1]
     int h, k;                 // tree height; k of the query (pruning uses the k-th key)

@@ -378,24 +378,41 @@ __global__ __launch_bounds__(1024) void k_leaf_offsets(const int32_t *__restrict
                                                        const int32_t *__restrict__ leaf_off, int nleaf, int qt,
                                                        int dense_min, int32_t *__restrict__ off,
                                                        int32_t *__restrict__ tiles, int32_t *__restrict__ sparse,
-                                                       int32_t *__restrict__ ctl)
+                                                       int32_t *__restrict__ ctl, int count_work)
 {
     __shared__ long long lds[1024];
     const int tid = threadIdx.x;
     const int seg = (nleaf + 1023) / 1024;
     const int lo = min(nleaf, tid * seg), hi = min(nleaf, lo + seg);
-    long long sc = 0, st = 0, ss = 0;
+    long long sc = 0, st = 0, ss = 0, pd = 0, ps = 0;
     // count of leaf l: cnt[l], or end - start of its run when start is given
     for (int l = lo; l < hi; l++) {
         int c = cnt[l] - (start ? start[l] : 0);
+        const long long pr = (long long)c * (leaf_off[l + 1] - leaf_off[l]);
         sc += c;
-        if (c >= dense_min) st += (c + qt - 1) / qt;
-        else ss += c;
+        if (c >= dense_min) {
+            st += (c + qt - 1) / qt;
+            pd += pr;
+        } else {
+            ss += c;
+            ps += pr;
+        }
     }
     long long tc, tt, ts;
     long long rc = block_exclusive_scan_1024<long long>(sc, lds, &tc);
     long long rt = block_exclusive_scan_1024<long long>(st, lds, &tt);
     long long rs = block_exclusive_scan_1024<long long>(ss, lds, &ts);
+    if (count_work) {
+        // visits and pairs of a full scan of these buffers (as k_count_work does)
+        long long tpd, tps;
+        (void)block_exclusive_scan_1024<long long>(pd, lds, &tpd);
+        (void)block_exclusive_scan_1024<long long>(ps, lds, &tps);
+        if (tid == 0) {
+            if (tc) atomicAdd((unsigned long long *)(ctl + CTL_VISITS_LO), (unsigned long long)tc);
+            if (tpd) atomicAdd((unsigned long long *)(ctl + CTL_DPAIRS_LO), (unsigned long long)tpd);
+            if (tps) atomicAdd((unsigned long long *)(ctl + CTL_SPAIRS_LO), (unsigned long long)tps);
+        }
+    }
     for (int l = lo; l < hi; l++) {
         int c = cnt[l] - (start ? start[l] : 0);
         off[l] = (int32_t)rc;
@@ -618,9 +635,11 @@ int launch_sort_pairs(uint32_t *key_a, int32_t *val_a, uint32_t *key_b, int32_t 
 }
 
 void launch_leaf_offsets(const int32_t *cnt, const int32_t *start, const int32_t *leaf_off, int nleaf, int qt,
-                         int dense_min, int32_t *off, int32_t *tiles, int32_t *sparse, int32_t *ctl, hipStream_t s)
+                         int dense_min, int32_t *off, int32_t *tiles, int32_t *sparse, int32_t *ctl, hipStream_t s,
+                         bool count_work)
 {
-    k_leaf_offsets<<<1, 1024, 0, s>>>(cnt, start, leaf_off, nleaf, qt, dense_min, off, tiles, sparse, ctl);
+    k_leaf_offsets<<<1, 1024, 0, s>>>(cnt, start, leaf_off, nleaf, qt, dense_min, off, tiles, sparse, ctl,
+                                      count_work ? 1 : 0);
     check_launch();
 }
 

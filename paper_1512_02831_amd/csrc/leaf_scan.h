@@ -67,12 +67,14 @@ template <int K> __device__ inline void key_insert(uint64_t (&lst)[K], uint64_t 
     lst[0] = lt[0] ? c : lst[0];
 }
 
-__device__ inline int xcd_item(int b, int grid)
+__device__ inline int xcd_item(int b, int count)
 {
     // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-    // contiguous range of items so that a leaf's tiles share one L2.
-    int per = grid >> 3;
-    return (b & 7) * per + (b >> 3);
+    // contiguous eighth of the count items so that a leaf's tiles share one
+    // L2.  -1: a workgroup past the items (the grid may be an upper bound).
+    const int per = (count + 7) >> 3;
+    const int j = b >> 3;
+    return j < per ? (b & 7) * per + j : -1;
 }
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -119,8 +121,10 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
     __shared__ bf16x8 xa[NB * NS * 64];
     __shared__ int32_t os[PT];
 
-    int item = xcd_item(blockIdx.x, gridDim.x);
-    if (item >= a.item_count) return;
+    // with dev_counts the item count is read on the device (the grid only bounds it)
+    const int item_count = a.dev_counts ? a.dev_counts[CTL_T] : a.item_count;
+    int item = xcd_item(blockIdx.x, item_count);
+    if (item < 0 || item >= item_count) return;
     item += a.item_first;
 
     // leaf of the item: largest L in [leaf_first, leaf_last] with tiles[L] <= item
@@ -397,8 +401,10 @@ __device__ inline uint64_t readlane_u64(uint64_t v, int lane)
 template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan_sparse(ScanArgs a)
 {
     const int lane = threadIdx.x & 63;
-    int s = __builtin_amdgcn_readfirstlane(xcd_item(blockIdx.x, gridDim.x) * (SCAN_THREADS / 64) +
-                                           (int)(threadIdx.x >> 6));
+    constexpr int WPB = SCAN_THREADS / 64;
+    const int blk = xcd_item(blockIdx.x, (a.sitem_count + WPB - 1) / WPB);
+    if (blk < 0) return;
+    int s = __builtin_amdgcn_readfirstlane(blk * WPB + (int)(threadIdx.x >> 6));
     if (s >= a.sitem_count) return;
     s += a.sitem_first;
     int lo = a.leaf_first, hi = a.leaf_last;
@@ -517,7 +523,7 @@ template <int D, int K> __global__ __launch_bounds__(TAIL_THREADS) void k_tail(S
     uint64_t li = (lane < K) ? kp[lane] : ~0ull;  // the query's list, lane i holds the i-th smallest
     const int kk = a.kq ? a.kq[q] : a.k;
     const int32_t first = (1 << h) - 1;
-    long long visits = 0, pairs = 0;
+    long long visits = 0, pairs = 0, visits_seen = 0;
     for (;;) {
         const int64_t l0 = a.leaf_off[leaf];
         const int len = a.leaf_off[leaf + 1] - (int32_t)l0;
@@ -578,8 +584,11 @@ template <int D, int K> __global__ __launch_bounds__(TAIL_THREADS) void k_tail(S
             }
         }
         __syncthreads();  // cand is written again for the next leaf
-        visits++;
-        pairs += len;
+        if (!(a.tail_counted && visits_seen == 0)) {
+            visits++;
+            pairs += len;
+        }
+        visits_seen++;
         const uint64_t kth_key = readlane_u64(li, kk - 1);
         const int32_t v = next_leaf(first + leaf, qp, &kth_key, a.split, split_lds, lds_nodes, h, a.d);
         if (v == NODE_DONE) break;

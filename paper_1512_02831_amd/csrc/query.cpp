@@ -220,6 +220,7 @@ void tree_build(Tree &t, const float *P, int64_t n, int d, int h, const bkd_opti
     }
     t.d_ctl.ensure(sizeof(int32_t) * CTL_WORDS);
     t.h_ctl.ensure(sizeof(int32_t) * CTL_WORDS);
+    BKD_HIP(hipEventCreateWithFlags(&t.ev_rb, hipEventDisableTiming));
     BKD_HIP(hipDeviceSynchronize());
 }
 
@@ -270,6 +271,7 @@ struct Run {
     const int32_t *perm = nullptr;  // internal number -> caller's query (null: identity)
     int64_t m;
     int k, K, d, h, nleaf, kbits;
+    bool counted = false;  // the last sort_and_offsets already counted a full scan's work
     bool tracing;
     int32_t *ctl, *hctl, *cnt;
     uint32_t *leafbuf[2];
@@ -313,8 +315,23 @@ struct Run {
 
     void readback()
     {
+        readback_issue();
+        readback_wait();
+    }
+
+    void readback_issue()
+    {
         BKD_HIP(hipMemcpyAsync(hctl, ctl, sizeof(int32_t) * CTL_WORDS, hipMemcpyDeviceToHost, s));
-        BKD_HIP(hipStreamSynchronize(s));
+        BKD_HIP(hipEventRecord(t.ev_rb, s));
+    }
+
+    void readback_wait()
+    {
+        for (;;) {
+            const hipError_t e = hipEventQuery(t.ev_rb);
+            if (e == hipSuccess) break;
+            if (e != hipErrorNotReady) BKD_HIP(e);
+        }
         if (hctl[CTL_BAD]) fail(BKD_EINVAL, "query coordinates must be finite");
     }
 
@@ -342,14 +359,17 @@ struct Run {
     // Sort the pending list, compute buffer offsets and work items, read the counters back.
     // With runs, the per-leaf counts come from the runs of the sorted list (the fetch
     // did not count); otherwise from the fetch's counters.
-    void sort_and_offsets(int64_t count, bool runs = false)
+    // wait: read the control words back before returning (else the copy is only issued)
+    void sort_and_offsets(int64_t count, bool runs = false, bool wait = true)
     {
         if (runs && !tracing && nleaf + 1 <= bucket_max_keys()) {
             // lock-step rounds: group by leaf in one pass (order within a buffer is free)
             const int nb = nleaf + 1;
             uint32_t *hist = t.d_hist.as<uint32_t>();
             const int32_t *counts = launch_bucket_count(leafbuf[cur], count, nb, kbits, hist, s);
-            offsets(counts, nullptr);
+            // a resident round scans every buffer (or hands them to the tail): its work is counted here
+            counted = t.resident;
+            offsets(counts, nullptr, counted);
             launch_bucket_scatter(leafbuf[cur], qbuf[cur], leafbuf[1 - cur], qbuf[1 - cur], count, nb, kbits, hist,
                                   t.d_off.as<int32_t>(), s);
             cur = 1 - cur;
@@ -364,7 +384,8 @@ struct Run {
                 launch_fill_i32(start, 0, nleaf, s);
                 launch_run_bounds(leafbuf[cur], count, nleaf, start, cnt, s);
             }
-            offsets(cnt, start);
+            counted = false;
+            offsets(cnt, start, false);
         }
         if (!t.resident) {
             BKD_HIP(hipMemcpyAsync(t.h_tiles.p, t.d_tiles.p, sizeof(int32_t) * 2 * (size_t)(nleaf + 1),
@@ -372,16 +393,17 @@ struct Run {
             BKD_HIP(hipMemcpyAsync(t.h_tiles.as<int32_t>() + 2 * (nleaf + 1), t.d_off.p,
                                    sizeof(int32_t) * (size_t)(nleaf + 1), hipMemcpyDeviceToHost, s));
         }
-        readback();
+        if (wait) readback();
+        else readback_issue();
     }
 
     // Buffer offsets, work items and the pending count from per-leaf counts
     // (cnt, or end - start of each run when start is given).
-    void offsets(const int32_t *counts, const int32_t *start)
+    void offsets(const int32_t *counts, const int32_t *start, bool count_work)
     {
         launch_leaf_offsets(counts, start, t.d_leaf_off.as<int32_t>(), nleaf, SCAN_QT, SCAN_DENSE_MIN,
                             t.d_off.as<int32_t>(), t.d_tiles.as<int32_t>(), t.d_tiles.as<int32_t>() + nleaf + 1, ctl,
-                            s);
+                            s, count_work);
     }
 
     ScanArgs scan_args(const float *base, int64_t shift) const
@@ -429,12 +451,47 @@ struct Run {
     // Scan every buffered query of a resident structure.
     void scan_resident()
     {
-        count_work(0, nleaf - 1);
+        if (!counted) count_work(0, nleaf - 1);
         ScanArgs a = scan_args(t.d_chunk[0].as<float>(), 0);
         a.chunk_lo = 0;
         a.chunk_hi = t.host.n;
         a.item_first = 0;
         a.item_count = hctl[CTL_T];
+        a.sitem_first = 0;
+        a.sitem_count = hctl[CTL_S];
+        a.leaf_first = 0;
+        a.leaf_last = nleaf - 1;
+        run_scan(a);
+    }
+
+    // Dense scan of a resident round queued before its counts reach the host:
+    // the item count is read on the device, the grid is bounded by the list
+    // length (a dense leaf holds at least SCAN_DENSE_MIN queries).
+    void scan_resident_dense_ahead(int64_t list)
+    {
+        if (!counted) count_work(0, nleaf - 1);
+        ScanArgs a = scan_args(t.d_chunk[0].as<float>(), 0);
+        a.chunk_lo = 0;
+        a.chunk_hi = t.host.n;
+        a.item_first = 0;
+        const int64_t bound = list / SCAN_QT + std::min<int64_t>(nleaf, list / SCAN_DENSE_MIN) + 1;
+        a.item_count = (int32_t)std::min<int64_t>(bound, INT32_MAX);
+        a.dev_counts = ctl;
+        a.sitem_first = 0;
+        a.sitem_count = 0;
+        a.leaf_first = 0;
+        a.leaf_last = nleaf - 1;
+        run_scan(a);
+    }
+
+    // The sparse items of the same round, once their count is on the host.
+    void scan_resident_sparse()
+    {
+        ScanArgs a = scan_args(t.d_chunk[0].as<float>(), 0);
+        a.chunk_lo = 0;
+        a.chunk_hi = t.host.n;
+        a.item_first = 0;
+        a.item_count = 0;
         a.sitem_first = 0;
         a.sitem_count = hctl[CTL_S];
         a.leaf_first = 0;
@@ -554,6 +611,39 @@ struct Run {
         }
         int64_t P = m;  // pending entries (leaf order after each sort; finished ones sort last)
         bool first = true;
+        const int64_t tail_max = t.opt.tail_max == 0 ? TAIL_MAX : t.opt.tail_max;
+        const bool use_tail = !(t.opt.flags & BKD_FLAG_NO_TAIL);
+        if (t.resident && !tracing) {
+            // Resident rounds without a host wait before the scan: the dense scan of a round is
+            // queued behind its sort and reads its item count on the device, and the host reads
+            // the round's counts back meanwhile.  The tail takes over once a round's list (the
+            // pending entries routed in the previous round) is at most tail_max long.
+            for (;;) {
+                const int64_t list = P;
+                sort_and_offsets(list, true, false);
+                if (first) localize();
+                first = false;
+                const bool tail_now = use_tail && list <= tail_max;
+                if (!tail_now) scan_resident_dense_ahead(list);
+                readback_wait();
+                P = hctl[CTL_V];
+                if (P == 0) {
+                    end_call();
+                    break;
+                }
+                if (tail_now) {
+                    tail(P);
+                    end_call();
+                    break;
+                }
+                if (hctl[CTL_S] > 0) scan_resident_sparse();
+                end_call();
+                FetchSpec f{qbuf[cur], 0, P, std::max<int64_t>(P, 1), 0, 0};
+                f.count_leaves = false;
+                find_leaf(f, 0);
+            }
+            return;
+        }
         for (;;) {
             sort_and_offsets(P, true);
             P = hctl[CTL_V];
@@ -563,8 +653,7 @@ struct Run {
             }
             if (first && !tracing) localize();
             first = false;
-            const int64_t tail_max = t.opt.tail_max == 0 ? TAIL_MAX : t.opt.tail_max;
-            if (t.resident && !tracing && !(t.opt.flags & BKD_FLAG_NO_TAIL) && P <= tail_max) {
+            if (t.resident && !tracing && use_tail && P <= tail_max) {
                 tail(P);
                 end_call();
                 break;
@@ -585,6 +674,7 @@ struct Run {
         a.tail_leaf = leafbuf[cur];
         a.tail_q = qbuf[cur];
         a.tail_count = (int32_t)P;
+        a.tail_counted = counted ? 1 : 0;
         a.node = t.d_node.as<int32_t>();
         a.split = t.d_split.as<float>();
         a.h = h;
