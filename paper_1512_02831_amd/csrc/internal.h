@@ -180,10 +180,10 @@ size_t sort_hist_words(int64_t count);
 // and their column prefixes into hist and returns the key totals (inside hist);
 // launch_bucket_scatter then places the pairs, key k starting at off[k].
 int bucket_max_keys();
-const int32_t *launch_bucket_count(const uint32_t *keys, int64_t count, int nb, int nbits, uint32_t *hist,
+const int32_t *launch_bucket_count(const uint32_t *keys, int64_t count, int nb, uint32_t *hist,
                                    hipStream_t s);
 void launch_bucket_scatter(const uint32_t *kin, const int32_t *vin, uint32_t *kout, int32_t *vout, int64_t count,
-                           int nb, int nbits, const uint32_t *hist, const int32_t *off, hipStream_t s);
+                           int nb, const uint32_t *hist, const int32_t *off, hipStream_t s);
 // tiles: [2][nleaf+1] -- dense work-item offsets, then sparse (per buffered query) offsets.
 // count_work: also add the visits and pairs of scanning every buffer to the ctl counters.
 void launch_leaf_offsets(const int32_t *cnt, const int32_t *start, const int32_t *leaf_off, int nleaf, int qt,

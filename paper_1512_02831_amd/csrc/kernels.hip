@@ -284,31 +284,18 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const uint32_t *
 // ---------------------------------------------------------------------------
 // Single-pass grouping by leaf for at most BK_MAX distinct keys.  The lock-step
 // rounds need every buffer's queries together but not in any particular order,
-// so a block claims output positions with LDS atomics (lanes holding the same
-// key are matched with one ballot per key bit and claim together).  Pass 1
-// writes each block's key counts (key-major), the column scan turns them into
-// per-block prefixes and key totals (the per-leaf counts), the buffer offsets
-// follow from the totals, and pass 2 scatters.
+// so each element claims its output position with an LDS atomic on its key's
+// running counter.  Pass 1 writes each block's key counts (key-major), the
+// column scan turns them into per-block prefixes and key totals (the per-leaf
+// counts), the buffer offsets follow from the totals, and pass 2 scatters.
 
-constexpr int BK_THREADS = 256;
-constexpr int BK_PER = 32;
+constexpr int BK_THREADS = 1024;
+constexpr int BK_PER = 8;
 constexpr int BK_TILE = BK_THREADS * BK_PER;
 constexpr int BK_MAX = 2048;
 
-// Lanes of the wave that hold the same key as this one (meaningful for valid lanes).
-__device__ inline uint64_t same_key_lanes(uint32_t key, int nbits, bool valid)
-{
-    uint64_t mask = __ballot(valid);
-    for (int b = 0; b < nbits; b++) {
-        const bool bit = (key >> b) & 1u;
-        const uint64_t bal = __ballot(valid && bit);
-        mask &= bit ? bal : ~bal;
-    }
-    return mask;
-}
-
 __global__ __launch_bounds__(BK_THREADS) void k_bucket_hist(const uint32_t *__restrict__ keys, int64_t count, int nb,
-                                                            int nbits, uint32_t *__restrict__ hist, int nblocks)
+                                                            uint32_t *__restrict__ hist, int nblocks)
 {
     __shared__ uint32_t h[BK_MAX];
     for (int i = threadIdx.x; i < nb; i += BK_THREADS) h[i] = 0;
@@ -320,11 +307,9 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_hist(const uint32_t *__re
         const int64_t i = base + (int64_t)r * BK_THREADS;
         kr[r] = i < count ? keys[i] : 0u;
     }
-    for (int r = 0; r < BK_PER; r++) {
-        const bool valid = base + (int64_t)r * BK_THREADS < count;
-        const uint64_t same = same_key_lanes(kr[r], nbits, valid);
-        if (valid && (same & lanemask_lt()) == 0) atomicAdd(&h[kr[r]], (uint32_t)__popcll(same));
-    }
+#pragma unroll
+    for (int r = 0; r < BK_PER; r++)
+        if (base + (int64_t)r * BK_THREADS < count) atomicAdd(&h[kr[r]], 1u);
     __syncthreads();
     for (int i = threadIdx.x; i < nb; i += BK_THREADS) hist[(int64_t)i * nblocks + blockIdx.x] = h[i];
 }
@@ -334,7 +319,7 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_hist(const uint32_t *__re
 __global__ __launch_bounds__(BK_THREADS) void k_bucket_scatter(const uint32_t *__restrict__ kin,
                                                                const int32_t *__restrict__ vin,
                                                                uint32_t *__restrict__ kout, int32_t *__restrict__ vout,
-                                                               int64_t count, int nb, int nbits,
+                                                               int64_t count, int nb,
                                                                const uint32_t *__restrict__ hist, int nblocks,
                                                                const int32_t *__restrict__ off)
 {
@@ -342,7 +327,6 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_scatter(const uint32_t *_
     for (int i = threadIdx.x; i < nb; i += BK_THREADS)
         run[i] = (uint32_t)off[i] + hist[(int64_t)i * nblocks + blockIdx.x];
     __syncthreads();
-    const int lane = __lane_id();
     const int64_t base = (int64_t)blockIdx.x * BK_TILE + threadIdx.x;
     uint32_t kr[BK_PER];
     int32_t vr[BK_PER];
@@ -352,15 +336,10 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_scatter(const uint32_t *_
         kr[r] = i < count ? kin[i] : 0u;
         vr[r] = i < count ? vin[i] : 0;
     }
+#pragma unroll
     for (int r = 0; r < BK_PER; r++) {
-        const bool valid = base + (int64_t)r * BK_THREADS < count;
-        const uint64_t same = same_key_lanes(kr[r], nbits, valid);
-        const int leader = valid ? __ffsll((unsigned long long)same) - 1 : lane;
-        uint32_t p = 0;
-        if (valid && leader == lane) p = atomicAdd(&run[kr[r]], (uint32_t)__popcll(same));
-        p = __shfl(p, leader);
-        if (valid) {
-            const uint32_t pos = p + (uint32_t)__popcll(same & lanemask_lt());
+        if (base + (int64_t)r * BK_THREADS < count) {
+            const uint32_t pos = atomicAdd(&run[kr[r]], 1u);
             kout[pos] = kr[r];
             vout[pos] = vr[r];
         }
@@ -593,23 +572,23 @@ size_t sort_hist_words(int64_t count)
 
 int bucket_max_keys() { return BK_MAX; }
 
-const int32_t *launch_bucket_count(const uint32_t *keys, int64_t count, int nb, int nbits, uint32_t *hist,
+const int32_t *launch_bucket_count(const uint32_t *keys, int64_t count, int nb, uint32_t *hist,
                                    hipStream_t s)
 {
     const int nblocks = (int)((count + BK_TILE - 1) / BK_TILE);
     uint32_t *totals = hist + (size_t)nb * nblocks;
-    if (nblocks > 0) k_bucket_hist<<<nblocks, BK_THREADS, 0, s>>>(keys, count, nb, nbits, hist, nblocks);
+    if (nblocks > 0) k_bucket_hist<<<nblocks, BK_THREADS, 0, s>>>(keys, count, nb, hist, nblocks);
     k_scan_columns<<<nb, 256, 0, s>>>(hist, nblocks, totals);
     check_launch();
     return reinterpret_cast<const int32_t *>(totals);
 }
 
 void launch_bucket_scatter(const uint32_t *kin, const int32_t *vin, uint32_t *kout, int32_t *vout, int64_t count,
-                           int nb, int nbits, const uint32_t *hist, const int32_t *off, hipStream_t s)
+                           int nb, const uint32_t *hist, const int32_t *off, hipStream_t s)
 {
     const int nblocks = (int)((count + BK_TILE - 1) / BK_TILE);
     if (nblocks == 0) return;
-    k_bucket_scatter<<<nblocks, BK_THREADS, 0, s>>>(kin, vin, kout, vout, count, nb, nbits, hist, nblocks, off);
+    k_bucket_scatter<<<nblocks, BK_THREADS, 0, s>>>(kin, vin, kout, vout, count, nb, hist, nblocks, off);
     check_launch();
 }
 

@@ -366,11 +366,11 @@ struct Run {
             // lock-step rounds: group by leaf in one pass (order within a buffer is free)
             const int nb = nleaf + 1;
             uint32_t *hist = t.d_hist.as<uint32_t>();
-            const int32_t *counts = launch_bucket_count(leafbuf[cur], count, nb, kbits, hist, s);
+            const int32_t *counts = launch_bucket_count(leafbuf[cur], count, nb, hist, s);
             // a resident round scans every buffer (or hands them to the tail): its work is counted here
             counted = t.resident;
             offsets(counts, nullptr, counted);
-            launch_bucket_scatter(leafbuf[cur], qbuf[cur], leafbuf[1 - cur], qbuf[1 - cur], count, nb, kbits, hist,
+            launch_bucket_scatter(leafbuf[cur], qbuf[cur], leafbuf[1 - cur], qbuf[1 - cur], count, nb, hist,
                                   t.d_off.as<int32_t>(), s);
             cur = 1 - cur;
         } else {
