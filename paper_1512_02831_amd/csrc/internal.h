@@ -217,6 +217,9 @@ struct ScanArgs {
     int32_t item_first, item_count;    // dense items of this launch
     const int32_t *dev_counts;         // if set, the dense item count is dev_counts[CTL_T] and
                                        // item_count is only an upper bound that sizes the grid
+    // lock-step rounds: if set, every scanned query also takes its next FindLeafBatch step
+    // here (node[q] updated, its next leaf, or 2^h when done, stored at its list position)
+    uint32_t *route_leaf;
     int32_t sitem_first, sitem_count;  // sparse items of this launch
     int32_t leaf_first, leaf_last;
     const float *Q;           // [m][d]

@@ -54,6 +54,7 @@ namespace bkd {
 
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_PT = 256;  // points per LDS tile
+constexpr int ROUTE_LDS_SPLITS = 1023;  // split values of the top ten levels, staged for the routing walk
 
 // Insert key c into the sorted list: every entry above c moves down one place
 // (the last one drops out) and c takes the first vacated place.
@@ -106,7 +107,7 @@ __device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
 template <int D, int K>
-__global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
+__global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
 {
     constexpr int DS = (D + 3) & ~3;   // row of the exact copy, padded for float4 reads
     // Products of the filter's inner product, in operand order: xh.qh, xl.qh,
@@ -120,6 +121,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
     // every read and write is one contiguous kilobyte)
     __shared__ bf16x8 xa[NB * NS * 64];
     __shared__ int32_t os[PT];
+    __shared__ float route_splits[ROUTE_LDS_SPLITS];
 
     // with dev_counts the item count is read on the device (the grid only bounds it)
     const int item_count = a.dev_counts ? a.dev_counts[CTL_T] : a.item_count;
@@ -379,15 +381,39 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_scan(ScanArgs a)
             }
         }
     }
+    uint32_t kb = 0;
     if (act) {
         const int kk = a.kq ? a.kq[q] : a.k;
-        uint32_t kb = 0;
 #pragma unroll
         for (int s2 = 0; s2 < K; s2++) {
             a.keys[(int64_t)q * K + s2] = lst[s2];
             if (s2 == kk - 1) kb = (uint32_t)(lst[s2] >> 32);
         }
         a.kth[q] = kb;
+    }
+    if (a.route_leaf) {
+        // next leaf of every query of the item (the FindLeafBatch step of the next round),
+        // walked from LDS: the split values of the top levels and, in place of the point
+        // tile, the lanes' query coordinates (coordinate-major)
+        constexpr bool QL = SCAN_THREADS * D <= PT * DS;
+        float *qlds = reinterpret_cast<float *>(xs);
+        const int lds_nodes = min((1 << a.h) - 1, ROUTE_LDS_SPLITS);
+        __syncthreads();  // every wave is done with the tile
+        if constexpr (QL) {
+#pragma unroll
+            for (int j = 0; j < D; j++) qlds[j * SCAN_THREADS + tid] = qv[j];
+        }
+        for (int i = tid; i < lds_nodes; i += SCAN_THREADS) route_splits[i] = a.split[i];
+        __syncthreads();
+        if (act) {
+            const int32_t first = (1 << a.h) - 1;
+            const int32_t v = QL ? next_leaf(first + L, qlds + tid, &kb, a.split, route_splits, lds_nodes, a.h, a.d,
+                                             SCAN_THREADS)
+                                 : next_leaf(first + L, a.Q + (int64_t)q * a.d, &kb, a.split, route_splits,
+                                             lds_nodes, a.h, a.d);
+            a.node[q] = v;
+            a.route_leaf[qbase + tid] = v >= 0 ? (uint32_t)(v - first) : (uint32_t)(1 << a.h);
+        }
     }
 }
 
@@ -477,7 +503,18 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
         }
     }
     if (lane < K) kp[lane] = li;
-    if (lane == (a.kq ? a.kq[q] : a.k) - 1) a.kth[q] = (uint32_t)(li >> 32);
+    const int kk = a.kq ? a.kq[q] : a.k;
+    if (lane == kk - 1) a.kth[q] = (uint32_t)(li >> 32);
+    if (a.route_leaf) {
+        // next leaf of the query (the FindLeafBatch step of the next round), walked by every lane alike
+        const uint32_t kb = (uint32_t)(readlane_u64(li, kk - 1) >> 32);
+        const int32_t first = (1 << a.h) - 1;
+        const int32_t v = next_leaf(first + L, qp, &kb, a.split, a.split, 0, a.h, a.d);
+        if (lane == 0) {
+            a.node[q] = v;
+            a.route_leaf[a.off[L] + (s - a.sparse[L])] = v >= 0 ? (uint32_t)(v - first) : (uint32_t)(1 << a.h);
+        }
+    }
 }
 
 // Tail of the lock-step schedule.  When only a few queries are pending, a

@@ -464,6 +464,16 @@ struct Run {
         run_scan(a);
     }
 
+    // Scans of the pipelined rounds also route their queries (the next FindLeafBatch
+    // step), in place in the sorted list, which the next round sorts again.
+    void route_args(ScanArgs &a) const
+    {
+        a.route_leaf = leafbuf[cur];
+        a.node = t.d_node.as<int32_t>();
+        a.split = t.d_split.as<float>();
+        a.h = h;
+    }
+
     // Dense scan of a resident round queued before its counts reach the host:
     // the item count is read on the device, the grid is bounded by the list
     // length (a dense leaf holds at least SCAN_DENSE_MIN queries).
@@ -477,6 +487,7 @@ struct Run {
         const int64_t bound = list / SCAN_QT + std::min<int64_t>(nleaf, list / SCAN_DENSE_MIN) + 1;
         a.item_count = (int32_t)std::min<int64_t>(bound, INT32_MAX);
         a.dev_counts = ctl;
+        route_args(a);
         a.sitem_first = 0;
         a.sitem_count = 0;
         a.leaf_first = 0;
@@ -492,6 +503,7 @@ struct Run {
         a.chunk_hi = t.host.n;
         a.item_first = 0;
         a.item_count = 0;
+        route_args(a);
         a.sitem_first = 0;
         a.sitem_count = hctl[CTL_S];
         a.leaf_first = 0;
@@ -638,9 +650,7 @@ struct Run {
                 }
                 if (hctl[CTL_S] > 0) scan_resident_sparse();
                 end_call();
-                FetchSpec f{qbuf[cur], 0, P, std::max<int64_t>(P, 1), 0, 0};
-                f.count_leaves = false;
-                find_leaf(f, 0);
+                t.stats.fetches++;  // the scans routed every pending query
             }
             return;
         }
