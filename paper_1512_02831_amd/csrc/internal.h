@@ -90,7 +90,7 @@ struct Chunk {
 // Device control words (one small array per tree, read back by the host).
 enum Ctl : int {
     CTL_MAXCNT = 0,   // largest buffer fill since the last call
-    // word 1 is unused
+    CTL_WIDE = 1,     // a query coordinate beyond +-FILTER_RANGE seen (the dense scan then skips its filter)
     CTL_V = 2,        // buffered entries of the current call
     CTL_T = 3,        // work items of the current call
     CTL_BAD = 4,      // non-finite query coordinate seen
@@ -121,6 +121,7 @@ struct Tree {
     DevBuf d_leaf_blk;
     DevBuf d_centers;              // [nleaf][d] float32: bounding-box midpoint of each leaf
     bool resident = true;
+    bool wide = false;             // a reference coordinate beyond +-FILTER_RANGE
     bool sweep = false;            // streaming with the chunk-sweep schedule
     std::vector<Chunk> chunks;
     size_t chunk_cap_bytes = 0;
@@ -215,6 +216,8 @@ struct ScanArgs {
     int64_t blk_shift;        // added to blk[l] to address the buffer (minus the buffer's first word)
     int64_t chunk_lo, chunk_hi;  // positions served by this launch
     int32_t item_first, item_count;    // dense items of this launch
+    int exact_only;                    // dense scan: exact distances for every pair, no filter
+    const int32_t *wide_flag;          // dense scan: if set and nonzero on the device, likewise
     const int32_t *dev_counts;         // if set, the dense item count is dev_counts[CTL_T] and
                                        // item_count is only an upper bound that sizes the grid
     // lock-step rounds: if set, every scanned query also takes its next FindLeafBatch step
@@ -248,6 +251,12 @@ struct ScanArgs {
 // Default number of pending queries at or below which the lock-step rounds hand over to
 // the tail kernel (bkd_options.tail_max).
 constexpr int64_t TAIL_MAX = 32768;
+
+// Coordinates up to this magnitude keep every quantity of the dense scan's
+// inner-product filter (centred coordinates, their squares and norms, the
+// bfloat16 products) finite and normal-ranged at d <= 32; beyond it the scan
+// takes its exact path for every point.
+constexpr float FILTER_RANGE = 0x1p59f;
 
 // Relative error band c of the dense scan's inner-product filter: 2^-12 for the
 // bfloat16-split matrix-core inner product (derivation beside the kernel).

@@ -40,10 +40,14 @@ __global__ void k_init_state(int32_t *node, uint64_t *keys, uint32_t *kth, int64
 
 __global__ void k_check_finite(const float *Q, int64_t count, int32_t *ctl)
 {
-    bool bad = false;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-        bad |= !isfinite(Q[i]);
+    bool bad = false, wide = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = Q[i];
+        bad |= !isfinite(v);
+        wide |= fabsf(v) > FILTER_RANGE;
+    }
     if (__ballot(bad) != 0ull && __lane_id() == 0) atomicOr(&ctl[CTL_BAD], 1);
+    if (__ballot(wide) != 0ull && __lane_id() == 0) atomicOr(&ctl[CTL_WIDE], 1);
 }
 
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t count)

@@ -169,8 +169,10 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
     const bool wave_busy = (tid & ~63) < qcnt;
     // A wave with a query whose list is not full yet (K-th key EMPTY, first
     // visit) accepts every point: it takes the exact path, 32 points at a time,
-    // until every list is full, then the filter.
-    bool exact_wave = __any(act && isinf(thr));
+    // until every list is full, then the filter.  Coordinates beyond the
+    // filter's range keep every wave on the exact path.
+    const bool no_filter = a.exact_only || (a.wide_flag && *a.wide_flag);
+    bool exact_wave = no_filter || __any(act && isinf(thr));
 
     // Matrix-core operands of the filter.  The wave's 64 queries form two
     // column tiles of 32; lane l supplies the query part of products
@@ -374,7 +376,7 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
             }
             exact_points(32 * b, min(32 * b + 32, np));
             thr = __uint_as_float((uint32_t)(lst[K - 1] >> 32));
-            exact_wave = __any(act && isinf(thr));
+            exact_wave = no_filter || __any(act && isinf(thr));
             if (!exact_wave) {
                 aq[0] = __shfl(own_aq(), col);
                 aq[1] = __shfl(own_aq(), 32 + col);

@@ -26,6 +26,7 @@
 // own data, so both schedules visit the same (query, leaf) pairs and give the
 // same results; the sweep copies each chunk once per pass instead of once per
 // round.
+#include <atomic>
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -175,7 +176,9 @@ void tree_build(Tree &t, const float *P, int64_t n, int d, int h, const bkd_opti
     {
         // leaf centres (bounding-box midpoints) for the inner-product filter of the dense scan
         std::vector<float> cen((size_t)t.nleaf * d);
+        std::atomic<bool> wide{false};
         parallel_for(t.nleaf, [&](int64_t b, int64_t e) {
+            bool w = false;
             for (int64_t l = b; l < e; l++) {
                 for (int j = 0; j < d; j++) {
                     float lo = INFINITY, hi = -INFINITY;
@@ -185,9 +188,12 @@ void tree_build(Tree &t, const float *P, int64_t n, int d, int h, const bkd_opti
                         hi = std::max(hi, v);
                     }
                     cen[(size_t)l * d + j] = 0.5f * lo + 0.5f * hi;
+                    w |= -lo > FILTER_RANGE || hi > FILTER_RANGE;
                 }
             }
+            if (w) wide = true;
         });
+        t.wide = wide;
         t.d_centers.ensure(sizeof(float) * cen.size());
         BKD_HIP(hipMemcpy(t.d_centers.p, cen.data(), sizeof(float) * cen.size(), hipMemcpyHostToDevice));
     }
@@ -424,6 +430,8 @@ struct Run {
         a.k = k;
         a.centers = t.d_centers.as<float>();
         a.filter_coef = 1.0f - filter_band(d);
+        a.exact_only = t.wide ? 1 : 0;
+        a.wide_flag = ctl + CTL_WIDE;
         return a;
     }
 

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -80,6 +81,7 @@ struct Request {
     int32_t table = -1;
     std::vector<int32_t> slots;
     bool cancel = false;
+    bool wide = false;  // a coordinate beyond +-FILTER_RANGE
 };
 
 struct Server;
@@ -97,6 +99,7 @@ struct Session {
     PinnedBuf hctl, hdone, hstage, hout, hgslots;
     hipEvent_t ev_stage = nullptr;  // after the last admission's staging copies
     bool stage_pending = false;
+    bool wide = false;  // a request with coordinates beyond +-FILTER_RANGE was admitted: exact scans from then on
     // host state
     std::vector<int32_t> free_slots, free_tables;
     std::deque<Request *> waiting;
@@ -206,6 +209,7 @@ static int64_t session_admit(Session &S, std::unique_lock<std::mutex> &lk)
         BKD_HIP(hipMemcpyAsync(S.stage.p, hs, qb, hipMemcpyHostToDevice, S.s));
         BKD_HIP(hipMemcpyAsync(S.newslots.p, hs + qb, sizeof(int32_t) * (size_t)total, hipMemcpyHostToDevice, S.s));
         for (Request *r : adm) {
+            S.wide |= r->wide;
             k_admit<<<(unsigned)((r->m + 255) / 256), 256, 0, S.s>>>(
                 S.stage.as<float>() + nnew * d, S.newslots.as<int32_t>() + nnew, r->m, d, S.K, r->k, r->table,
                 S.Qpool.as<float>(), S.keys.as<uint64_t>(), S.kth.as<uint32_t>(), S.node.as<int32_t>(),
@@ -310,6 +314,7 @@ static void session_round(Session &S, int64_t nnew)
         a.kth = S.kth.as<uint32_t>();
         a.k = S.K;
         a.kq = S.kq.as<int32_t>();
+        a.exact_only = (T.wide || S.wide) ? 1 : 0;
         a.centers = T.d_centers.as<float>();
         a.filter_coef = 1.0f - filter_band(H.d);
         launch_leaf_scan(a, S.K, 0, S.s);
@@ -494,8 +499,11 @@ int bkd_submit(bkd_server *srv, int32_t tree_id, const float *Q, int64_t m, int3
         if (m < 1 || !Q || !out_idx || !out_dist) bkd::fail(BKD_EINVAL, "need m >= 1 and non-NULL Q and outputs");
         if (k < 1 || k > BKD_MAX_K || k > t->t.host.n) bkd::fail(BKD_EINVAL, "k must be in [1, min(n, 64)]");
         if (m > V.slots_per_session) bkd::fail(BKD_EBUSY, "request larger than a session's query slots");
-        for (int64_t i = 0; i < m * d; i++)
+        bool wide = false;
+        for (int64_t i = 0; i < m * d; i++) {
             if (!std::isfinite(Q[i])) bkd::fail(BKD_EINVAL, "query coordinates must be finite");
+            wide |= std::fabs(Q[i]) > bkd::FILTER_RANGE;
+        }
         const int K = bkd::key_capacity(k);
         auto r = std::make_unique<bkd::Request>();
         r->id = V.next_id++;
@@ -503,6 +511,7 @@ int bkd_submit(bkd_server *srv, int32_t tree_id, const float *Q, int64_t m, int3
         r->k = k;
         r->K = K;
         r->m = m;
+        r->wide = wide;
         r->Q.assign(Q, Q + m * d);
         r->out_idx = out_idx;
         r->out_dist = out_dist;

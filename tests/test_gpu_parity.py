@@ -207,6 +207,33 @@ def test_lockstep_tail_matches_rounds_and_oracle(n, m, d, k, h, tail_max):
     assert st_tail["visits"] == st_rounds["visits"] and st_tail["pairs"] == st_rounds["pairs"]
 
 
+def test_wide_reference_coordinates_keep_results_exact():
+    """Reference points in clusters around +-1e20 (beyond the dense filter's range): the dense scan
+    takes its exact path, and keys stay bit-exact (finite distances inside a cluster, +inf across)."""
+    say("case: wide reference coordinates")
+    rng = np.random.default_rng(11)
+    d, n, m, k = 5, 12000, 3000, 10
+    centres = rng.choice([-1e20, 1e20], size=(4, d))
+    P = (centres[rng.integers(0, 4, n)] + rng.normal(0, 1e17, (n, d))).astype(np.float32)
+    Q = (centres[rng.integers(0, 4, m)] + rng.normal(0, 1e17, (m, d))).astype(np.float32)
+    keys, _, st, _ = gpu_keys(P, Q, k, 5, buffer_size=-1, fetch_size=-1, flags=bkd.FLAG_NO_TAIL)
+    assert st["dense_pairs"] > 0
+    assert np.array_equal(keys, oracle.brute_f32c(P, Q, k))
+
+
+def test_one_wide_query_keeps_results_exact():
+    """A single query beyond the filter's range switches the whole call to exact dense scans."""
+    say("case: one wide query")
+    P, Q = datagen.mixture_pq(seed=77, n=30000, m=2000, d=10, comps=5)
+    Q = Q.copy()
+    Q[5] = np.float32(3e19)
+    Q[6, 0] = np.float32(-7e18)
+    k = 10
+    keys, _, st, _ = gpu_keys(P, Q, k, 6, buffer_size=-1, fetch_size=-1, flags=bkd.FLAG_NO_TAIL)
+    assert st["dense_pairs"] > 0
+    assert np.array_equal(keys, oracle.brute_f32c(P, Q, k))
+
+
 def test_lattice_exact_including_ties():
     say("case: lattice ties")
     P = datagen.lattice(2, 1, 6000, 5, side=5)
