@@ -83,9 +83,13 @@ typedef struct bkd_tree bkd_tree;
  *                 and the chunked-versus-resident comparison).
  *   device        HIP device ordinal.
  *   flags         BKD_FLAG_* bits.
- *   tail_max      lock-step schedule on a resident structure: once at most this
- *                 many queries are pending, the rounds stop and each of them
- *                 finishes its traversal alone (one workgroup per query).
+ *   tail_max      lock-step schedule: on a resident structure, once a round
+ *                 starts with at most this many pending queries, the rounds
+ *                 stop and each of them finishes its traversal alone (one
+ *                 workgroup per query); on a structure streamed in N
+ *                 leaf-aligned chunks, a resident chunk with at most
+ *                 max(1, tail_max / N) pending queries is drained that way
+ *                 (each query walks on while its next leaf is in the chunk).
  *                 0: the default (32768); < 0: rounds to the end (as
  *                 BKD_FLAG_NO_TAIL).
  * Results are identical for every value of these options.

@@ -527,7 +527,10 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
 // query's K-th) as lane-distributed lists, and merge them into the query's
 // list in LDS order; then every lane walks to the next leaf with the same
 // state (Sections 2.3, 2.4), so the walk is uniform.  Results do not depend
-// on the schedule: a query's visits and its list are its own.
+// on the schedule: a query's visits and its list are its own.  With
+// route_leaf set (a streamed structure), only the leaves [leaf_first,
+// leaf_last] of the resident chunk are available: a query stops at its first
+// next leaf outside them and leaves that leaf (2^h when done) in its entry.
 constexpr int TAIL_THREADS = 256;
 constexpr int TAIL_LDS_SPLITS = 2047;
 
@@ -563,10 +566,11 @@ template <int D, int K> __global__ __launch_bounds__(TAIL_THREADS) void k_tail(S
     const int kk = a.kq ? a.kq[q] : a.k;
     const int32_t first = (1 << h) - 1;
     long long visits = 0, pairs = 0, visits_seen = 0;
+    int32_t next = NODE_DONE;
     for (;;) {
         const int64_t l0 = a.leaf_off[leaf];
         const int len = a.leaf_off[leaf + 1] - (int32_t)l0;
-        const float *X = a.base + a.blk[leaf];
+        const float *X = a.base + (a.blk[leaf] + a.blk_shift);
         const int32_t *orig = reinterpret_cast<const int32_t *>(X) + (int64_t)a.d * len;
         const uint64_t kthK = readlane_u64(li, K - 1);
         // this wave's part of the leaf; its new candidates all lie below kthK
@@ -632,12 +636,17 @@ template <int D, int K> __global__ __launch_bounds__(TAIL_THREADS) void k_tail(S
         const int32_t v = next_leaf(first + leaf, qp, &kth_key, a.split, split_lds, lds_nodes, h, a.d);
         if (v == NODE_DONE) break;
         leaf = v - first;
+        if (a.route_leaf && (leaf < a.leaf_first || leaf > a.leaf_last)) {
+            next = v;  // not resident: the query waits for that leaf's chunk
+            break;
+        }
     }
     if (w == 0 && lane < K) kp[lane] = li;
     if (w == 0 && lane == (a.kq ? a.kq[q] : a.k) - 1) a.kth[q] = (uint32_t)(li >> 32);
     if (threadIdx.x == 0) {
-        a.node[q] = NODE_DONE;
-        if (a.req_left) {
+        a.node[q] = next;
+        if (a.route_leaf) a.route_leaf[blockIdx.x] = next >= 0 ? (uint32_t)(next - first) : (uint32_t)(1 << h);
+        if (a.req_left && next == NODE_DONE) {
             // last query of its request: record the request as complete
             const int32_t r = a.req_of[q];
             if (atomicSub(&a.req_left[r], 1) == 1) a.done_list[1 + atomicAdd(&a.done_list[0], 1)] = r;

@@ -539,7 +539,9 @@ struct Run {
     }
 
     // Scan the buffered queries of chunk j's leaves; prefetch chunk nj (-1: none) into the other buffer.
-    void scan_chunk(int j, int nj)
+    // Make chunk j resident (copy it unless a buffer holds it) and order the query stream
+    // after its copy; returns the buffer.
+    int chunk_buffer(int j, int nj)
     {
         int b = (t.chunk_in[0] == j) ? 0 : (t.chunk_in[1] == j) ? 1 : -1;
         if (b < 0) {
@@ -547,6 +549,44 @@ struct Run {
             issue_copy(b, j);
         }
         BKD_HIP(hipStreamWaitEvent(s, t.ev_copied[b], 0));
+        return b;
+    }
+
+    // After the work on buffer b: record its use and prefetch chunk nj into the other buffer.
+    void chunk_done(int b, int j, int nj)
+    {
+        BKD_HIP(hipEventRecord(t.ev_used[b], s));
+        if (nj >= 0 && nj != j && t.chunk_in[1 - b] != nj) issue_copy(1 - b, nj);
+    }
+
+    // Drain the n pending entries (Rl, Rq) of resident chunk j with the tail kernel: each query
+    // walks on while its next leaf lies in j and leaves in its entry the first leaf outside j
+    // (or the finished sentinel).
+    void tail_chunk(int j, int nj, uint32_t *Rl, int32_t *Rq, int64_t n)
+    {
+        const int b = chunk_buffer(j, nj);
+        const Chunk &c = t.chunks[(size_t)j];
+        ScanArgs a = scan_args(t.d_chunk[b].as<float>(), -c.word_lo);
+        a.leaf_first = c.leaf_first;
+        a.leaf_last = c.leaf_last;
+        a.tail_leaf = Rl;
+        a.tail_q = Rq;
+        a.tail_count = (int32_t)n;
+        a.route_leaf = Rl;
+        a.node = t.d_node.as<int32_t>();
+        a.split = t.d_split.as<float>();
+        a.h = h;
+        a.ctl = ctl;
+        tsparse.begin(s);
+        launch_leaf_scan(a, K, 2, s);
+        tsparse.end(s);
+        t.stats.sparse_launches++;
+        chunk_done(b, j, nj);
+    }
+
+    void scan_chunk(int j, int nj)
+    {
+        const int b = chunk_buffer(j, nj);
         const Chunk &c = t.chunks[(size_t)j];
         ScanArgs a = scan_args(t.d_chunk[b].as<float>(), -c.word_lo);
         a.chunk_lo = c.lo;
@@ -558,8 +598,7 @@ struct Run {
         a.sitem_first = hsparse()[c.leaf_first];
         a.sitem_count = hsparse()[c.leaf_last + 1] - hsparse()[c.leaf_first];
         run_scan(a);
-        BKD_HIP(hipEventRecord(t.ev_used[b], s));
-        if (nj >= 0 && nj != j && t.chunk_in[1 - b] != nj) issue_copy(1 - b, nj);
+        chunk_done(b, j, nj);
     }
 
     // ProcessAllBuffers over a streamed structure: every chunk holding a buffered leaf, in order.
@@ -735,6 +774,10 @@ struct Run {
         int32_t *rcnt = t.d_rcnt.as<int32_t>();
         int32_t *hr = t.h_rcnt.as<int32_t>();
         const int32_t *chunk_of = t.d_chunk_of.as<int32_t>();
+        // a chunk's pending queries go to the tail kernel at the chunk's share of tail_max: a tail
+        // query reads each of its leaves alone, which pays only for a few queries per chunk
+        const int64_t tail_max = std::max<int64_t>(1, (t.opt.tail_max == 0 ? TAIL_MAX : t.opt.tail_max) / N);
+        const bool use_tail = !tracing && !(t.opt.flags & BKD_FLAG_NO_TAIL) && t.opt.tail_max >= 0;
         uint32_t *sleaf = leafbuf[1 - cur];
         int32_t *sq = qbuf[1 - cur];
         auto read_counts = [&]() {
@@ -773,6 +816,16 @@ struct Run {
             const int64_t n = hr[c];
             uint32_t *Rl = rleaf + (int64_t)c * m;
             int32_t *Rq = rq + (int64_t)c * m;
+            if (use_tail && n <= tail_max) {
+                // few queries left in c: the tail kernel drains the chunk in one launch
+                tail_chunk(c, nc, Rl, Rq, n);
+                end_call();
+                launch_distribute(Rl, Rq, n, nleaf, chunk_of, c, rleaf, rq, m, rcnt, sleaf, sq, N, s);
+                launch_restore(sleaf, sq, n, Rl, Rq, rcnt, c, N, s);
+                launch_fill_i32(rcnt + N, 0, 1, s);
+                read_counts();
+                continue;
+            }
             // sort the region by leaf, then offsets and work items of chunk c's leaves
             if (launch_sort_pairs(Rl, Rq, sleaf, sq, n, kbits, t.d_hist.as<uint32_t>(), s)) {
                 BKD_HIP(hipMemcpyAsync(Rl, sleaf, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));

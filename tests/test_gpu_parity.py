@@ -150,6 +150,23 @@ def test_streamed_lockstep_identical_to_resident(mode, budget, N):
     assert np.array_equal(keys, oracle.brute_f32c(P, Q, k))
 
 
+@pytest.mark.parametrize("budget,N,tail_max", [(0, 5, 0), (0, 12, 300), (200_000, 0, 1), (0, 3, 2)])
+def test_streamed_sweep_tail_matches_resident(budget, N, tail_max):
+    # The chunk sweep hands a resident chunk's pending queries to the tail kernel once at most
+    # tail_max are left there; each walks on while its next leaf is in that chunk.  Keys, visits and
+    # pairs equal a resident run that keeps rounds to the end.
+    say(f"case: sweep tail budget={budget} N={N} tail_max={tail_max}")
+    P, Q = datagen.mixture_pq(seed=9, n=40_000, m=3000, d=6, comps=6)
+    k, h = 10, 7
+    ref, _, st_ref, _ = gpu_keys(P, Q, k, h, fetch_size=-1, buffer_size=-1, flags=bkd.FLAG_NO_TAIL)
+    keys, _, st, info = gpu_keys(P, Q, k, h, fetch_size=-1, buffer_size=-1, chunk_mode=bkd.CHUNK_LEAF,
+                                 leaf_budget_bytes=budget, num_chunks=N, tail_max=tail_max)
+    assert info.resident == 0 and info.num_chunks >= 2
+    assert np.array_equal(keys, ref)
+    assert st["visits"] == st_ref["visits"] and st["pairs"] == st_ref["pairs"]
+    assert np.array_equal(keys, oracle.brute_f32c(P, Q, k))
+
+
 @pytest.mark.parametrize("mode,N,B,M", [(bkd.CHUNK_LEAF, 5, 64, 500), (bkd.CHUNK_POSITION, 4, 0, 0),
                                         (bkd.CHUNK_POSITION, 9, 16, 100)])
 def test_streamed_algorithm1_matches_replay(mode, N, B, M):
