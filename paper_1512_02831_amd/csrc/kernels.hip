@@ -176,24 +176,6 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__r
     hist[(int64_t)tid * nblocks + blockIdx.x] = hcount[tid];
 }
 
-// Exclusive scan of n words with one workgroup of 1024 threads.
-template <class T> __device__ T block_exclusive_scan_1024(T v, T *lds, T *total)
-{
-    const int tid = threadIdx.x;
-    lds[tid] = v;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        T add = (tid >= o) ? lds[tid - o] : T(0);
-        __syncthreads();
-        lds[tid] += add;
-        __syncthreads();
-    }
-    T incl = lds[tid];
-    if (total) *total = lds[1023];
-    __syncthreads();
-    return incl - v;
-}
-
 // Exclusive scan of each digit's column of the histogram (hist is digit-major:
 // hist[digit * nblocks + block]); totals[digit] receives the column sum.
 __global__ __launch_bounds__(256) void k_scan_columns(uint32_t *__restrict__ hist, int nblocks,
@@ -363,7 +345,7 @@ __global__ __launch_bounds__(1024) void k_leaf_offsets(const int32_t *__restrict
                                                        int32_t *__restrict__ tiles, int32_t *__restrict__ sparse,
                                                        int32_t *__restrict__ ctl, int count_work)
 {
-    __shared__ long long lds[1024];
+    __shared__ long long wsum[16][5], wpre[16][3], wtot[5];
     const int tid = threadIdx.x;
     const int seg = (nleaf + 1023) / 1024;
     const int lo = min(nleaf, tid * seg), hi = min(nleaf, lo + seg);
@@ -381,20 +363,53 @@ __global__ __launch_bounds__(1024) void k_leaf_offsets(const int32_t *__restrict
             ps += pr;
         }
     }
-    long long tc, tt, ts;
-    long long rc = block_exclusive_scan_1024<long long>(sc, lds, &tc);
-    long long rt = block_exclusive_scan_1024<long long>(st, lds, &tt);
-    long long rs = block_exclusive_scan_1024<long long>(ss, lds, &ts);
-    if (count_work) {
-        // visits and pairs of a full scan of these buffers (as k_count_work does)
-        long long tpd, tps;
-        (void)block_exclusive_scan_1024<long long>(pd, lds, &tpd);
-        (void)block_exclusive_scan_1024<long long>(ps, lds, &tps);
-        if (tid == 0) {
-            if (tc) atomicAdd((unsigned long long *)(ctl + CTL_VISITS_LO), (unsigned long long)tc);
-            if (tpd) atomicAdd((unsigned long long *)(ctl + CTL_DPAIRS_LO), (unsigned long long)tpd);
-            if (tps) atomicAdd((unsigned long long *)(ctl + CTL_SPAIRS_LO), (unsigned long long)tps);
+    // one pass: inclusive sums of the three running counts within each wave
+    // (shuffles), the wave totals through LDS, and sixteen threads turn those
+    // into per-wave prefixes and the block totals
+    const int lane = tid & 63, wave = tid >> 6;
+    int32_t inc[3] = {(int32_t)sc, (int32_t)st, (int32_t)ss};
+    long long red[2] = {pd, ps};
+    for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            const int32_t u = __shfl_up(inc[i], o);
+            if (lane >= o) inc[i] += u;
         }
+    }
+    if (count_work) {
+        for (int o = 32; o > 0; o >>= 1) {
+            red[0] += __shfl_xor(red[0], o);
+            red[1] += __shfl_xor(red[1], o);
+        }
+    }
+    if (lane == 63) {
+        wsum[wave][0] = inc[0];
+        wsum[wave][1] = inc[1];
+        wsum[wave][2] = inc[2];
+    }
+    if (lane == 0) {
+        wsum[wave][3] = red[0];
+        wsum[wave][4] = red[1];
+    }
+    __syncthreads();
+    if (tid < 5) {
+        // column tid: exclusive prefix over the waves (counts) or the total (pairs)
+        long long run = 0;
+        for (int w = 0; w < 16; w++) {
+            const long long v = wsum[w][tid];
+            if (tid < 3) wpre[w][tid] = run;
+            run += v;
+        }
+        wtot[tid] = run;
+    }
+    __syncthreads();
+    long long rc = wpre[wave][0] + inc[0] - sc, rt = wpre[wave][1] + inc[1] - st, rs = wpre[wave][2] + inc[2] - ss;
+    const long long tc = wtot[0], tt = wtot[1], ts = wtot[2];
+    if (count_work && tid == 0) {
+        // visits and pairs of a full scan of these buffers (as k_count_work does)
+        if (tc) atomicAdd((unsigned long long *)(ctl + CTL_VISITS_LO), (unsigned long long)tc);
+        if (wtot[3]) atomicAdd((unsigned long long *)(ctl + CTL_DPAIRS_LO), (unsigned long long)wtot[3]);
+        if (wtot[4]) atomicAdd((unsigned long long *)(ctl + CTL_SPAIRS_LO), (unsigned long long)wtot[4]);
     }
     for (int l = lo; l < hi; l++) {
         int c = cnt[l] - (start ? start[l] : 0);
