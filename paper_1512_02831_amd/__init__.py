@@ -101,7 +101,7 @@ def lib():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+        raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_1512_02831_amd.compile (hipcc, gfx950)")
     try:  # share torch's HIP runtime when torch is present (one runtime per process)
         import torch  # noqa: F401
     except ImportError:
