@@ -549,15 +549,17 @@ template <int D, int K> __global__ __launch_bounds__(TAIL_THREADS) void k_tail(S
     constexpr int U = 4;
     __shared__ float split_lds[TAIL_LDS_SPLITS];
     __shared__ uint64_t cand[W][K];
+    __shared__ float q_lds[D];  // the query, read by every step of the walk
     const int h = a.h;
     const int lds_nodes = min((1 << h) - 1, TAIL_LDS_SPLITS);
     for (int i = threadIdx.x; i < lds_nodes; i += TAIL_THREADS) split_lds[i] = a.split[i];
-    __syncthreads();
 
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int32_t q = a.tail_q[blockIdx.x];
     int32_t leaf = (int32_t)a.tail_leaf[blockIdx.x];
     const float *qp = a.Q + (int64_t)q * a.d;
+    if (threadIdx.x < D) q_lds[threadIdx.x] = (threadIdx.x < a.d) ? qp[threadIdx.x] : 0.0f;
+    __syncthreads();
     float qv[D];
 #pragma unroll
     for (int j = 0; j < D; j++) qv[j] = (j < a.d) ? qp[j] : 0.0f;
@@ -633,7 +635,7 @@ template <int D, int K> __global__ __launch_bounds__(TAIL_THREADS) void k_tail(S
         }
         visits_seen++;
         const uint64_t kth_key = readlane_u64(li, kk - 1);
-        const int32_t v = next_leaf(first + leaf, qp, &kth_key, a.split, split_lds, lds_nodes, h, a.d);
+        const int32_t v = next_leaf(first + leaf, q_lds, &kth_key, a.split, split_lds, lds_nodes, h, a.d);
         if (v == NODE_DONE) break;
         leaf = v - first;
         if (a.route_leaf && (leaf < a.leaf_first || leaf > a.leaf_last)) {
