@@ -119,7 +119,7 @@ struct Tree {
     // leaf structure
     std::vector<int64_t> leaf_blk; // [nleaf+1] word offsets of the leaf blocks
     DevBuf d_leaf_blk;
-    DevBuf d_centers;              // [nleaf][d] float32: bounding-box midpoint of each leaf
+    DevBuf d_centers;              // [nleaf][d] float32 bounding-box midpoints, then [nleaf] leaf scales
     bool resident = true;
     bool wide = false;             // a reference coordinate beyond +-FILTER_RANGE
     bool sweep = false;            // streaming with the chunk-sweep schedule
@@ -230,7 +230,7 @@ struct ScanArgs {
     uint64_t *keys;           // [m][K]
     uint32_t *kth;            // [m] high word of each query's k-th key (its pruning distance)
     const float *centers;     // [nleaf][d] leaf centres of the inner-product filter
-    float filter_coef;        // 1 - c(d), c(d) the relative error band of the filter
+    const float *scales;      // [nleaf] power of two bringing a leaf's centred coordinates into [-1, 1]
     // tail of the lock-step schedule (resident structure): pending (leaf, query) entries
     // that each finish their whole traversal in one workgroup
     const uint32_t *tail_leaf;
@@ -253,14 +253,10 @@ struct ScanArgs {
 constexpr int64_t TAIL_MAX = 32768;
 
 // Coordinates up to this magnitude keep every quantity of the dense scan's
-// inner-product filter (centred coordinates, their squares and norms, the
-// bfloat16 products) finite and normal-ranged at d <= 32; beyond it the scan
-// takes its exact path for every point.
+// inner-product filter (centred coordinates, the leaf scales and the scaled
+// query offsets) finite and normal-ranged at d <= 32; beyond it the scan takes
+// its exact path for every point.
 constexpr float FILTER_RANGE = 0x1p59f;
-
-// Relative error band c of the dense scan's inner-product filter: 2^-12 for the
-// bfloat16-split matrix-core inner product (derivation beside the kernel).
-float filter_band(int d);
 
 // Dispatch on padded dimension and key capacity; sparse = 0: dense items, 1: sparse items,
 // 2: the tail (tail_count pending entries, one workgroup each).

@@ -6,29 +6,29 @@
 // points (the part held by the current chunk) stream through LDS in tiles.
 //
 // Matrix-core filter.  Once every query of a wave has K candidates, a pair is
-// first tested with the expansion |q-x|^2 = |q'|^2 + |x'|^2 - 2<q',x'> on
-// coordinates relative to the leaf centre c (q' = q-c, x' = x-c, rounded to
-// float32).  Every centred coordinate is split into bfloat16 parts hi + lo,
-// and G = <q',x'> - (1-c)|x'|^2/2 is formed on the matrix cores from the
-// 3d + 2 products xh.qh, xl.qh, xh.ql (d each) and bs_hi.1, bs_lo.1 (the
-// split of the point's scaled norm, times one in the query operand), laid end
-// to end and cut into steps of sixteen: one v_mfma_f32_32x32x16_bf16 per step
-// and 32x32 tile of 32 points against 32 of the wave's 64 queries (two steps
-// at d = 10, where three separate products would take three).  The vector
-// unit then takes half a max per pair.  A pair passes when
-// G >= ((1-c) |q'|^2 - thr)/2 - eta, thr the query's current K-th squared
-// distance.  With S = |q'|^2 + |x'|^2, the dropped split terms are at most
-// 3 2^-16 sum |q'_j x'_j| <= 1.5 2^-16 S, the norm's split at most 2^-16 S/2,
-// and the float32 accumulation in the matrix unit (any order, rounding either
-// way) and every other float32 step add well under 2^-16 S, so the expansion
-// is within 2^-13 S of the float32 distance; c = 2^-12 is twice that and also
-// covers the final comparison's rounding (a borderline pair has thr <= 2S).
-// eta = 2^-100 covers parts and products flushed to zero below the normal
-// range.  Passing pairs go to the lane owning the query, which re-checks them
-// with the exact float32 distance, so keys and results are bit-identical to
-// the exact path.  A wave holding a query whose list is not full yet (a first
-// visit) takes the exact path, every point through the float32 distance, 32
-// points at a time until all its lists are full.
+// first tested in the leaf's own frame: centred coordinates (relative to the
+// leaf's bounding-box centre c, rounded to float32) times the leaf's scale s,
+// a power of two that brings every centred point coordinate into [-1, 1], so
+// u = fl32(x - c) s and p = fl32(q - c) s exactly.  Both are rounded to
+// float16 (x~, q~), and G = <q~,x~> - |x~|^2/2 is formed on the matrix cores
+// from d + 2 products (the norm term as a float16 hi and lo part against a
+// one), one v_mfma_f32_32x32x16_f16 per step of sixteen and 32x32 tile (one
+// step at d <= 14).  The vector unit then takes half a max per pair.  The
+// rounding moves the scaled distance by at most
+// delta = 2^-10 (1 + 2^-8)(|p| + sqrt d) + 2^-13 sqrt d (either rounding
+// mode, float16 subnormals kept or flushed), so a pair whose float32 distance
+// is within the query's K-th, thr, has |q~ - x~|^2 <= T = (sqrt(thr s^2) +
+// delta)^2, and it passes G >= (|q~|^2 - T)/2 - 2^-18 (|q~|^2 + d + 1) - eta;
+// the 2^-18 term covers the float32 accumulations (products of float16 are
+// exact), eta = 2^-100 underflow.  The band is relative to the leaf, not to
+// |q'|^2 + |x'|^2: a query at distance r from the leaf centre moves its radius
+// by about delta ~ 2^-10 (r + sqrt d) leaf radii.  A query with a scaled
+// offset beyond 2^14 (far outside its leaf, or a leaf of tiny extent) takes
+// the exact path.  Passing pairs go to the lane owning the query, which
+// re-checks them with the exact float32 distance, so keys and results are
+// bit-identical to the exact path.  A wave holding a query whose list is not
+// full yet (a first visit) takes the exact path, every point through the
+// float32 distance, 32 points at a time until all its lists are full.
 //
 // Squared distances follow the float32 reading: t = q_j - x_j rounded, then
 // acc = fma(t, t, acc) for j = 0..d-1 from +0.  Padding dimensions hold zero in
@@ -79,47 +79,39 @@ __device__ inline int xcd_item(int b, int count)
 }
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-// Absolute slack of the matrix-core filter: covers split parts and products
-// that may be flushed to zero below the normal range (for any finite S).
-constexpr float FILTER_ABS_SLACK = 0x1p-100f;
-
-// A float32 value as the sum of two bfloat16 values (round to nearest even
-// twice); hi + lo differs from x by at most 2^-16 |x|.
-__device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo)
-{
-    hi = static_cast<__bf16>(x);
-    lo = static_cast<__bf16>(x - static_cast<float>(hi));
-}
-
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
-// Two float32 values rounded to bfloat16 (nearest even) in one word: a in the
-// low half, b in the high half.
-__device__ inline uint32_t pack_bf16x2(float a, float b)
+// Absolute slack of the matrix-core filter (underflow of its float32 terms).
+constexpr float FILTER_ABS_SLACK = 0x1p-100f;
+// Scaled query offsets beyond this take the exact path (float16 range and band).
+constexpr float FILTER_FAR = 0x1p14f;
+
+// Two float32 values rounded to float16 in one word: a in the low half, b in
+// the high half.
+__device__ inline uint32_t pack_f16x2(float a, float b)
 {
     const f32x2 v = {a, b};
-    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
 }
-__device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
-__device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+__device__ inline float f16_word_lo(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu)); }
+__device__ inline float f16_word_hi(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)); }
 
 template <int D, int K>
 __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
 {
     constexpr int DS = (D + 3) & ~3;   // row of the exact copy, padded for float4 reads
-    // Products of the filter's inner product, in operand order: xh.qh, xl.qh,
-    // xh.ql for every coordinate, then the two parts of -bs against 1.
-    constexpr int NT = 3 * D + 2;
+    // Products of the filter's inner product, in operand order: x~_j q~_j for
+    // every coordinate, then the two float16 parts of -|x~|^2/2 against 1.
+    constexpr int NT = D + 2;
     constexpr int NS = (NT + 15) / 16;  // matrix-core steps of sixteen products
     constexpr int PT = D > 16 ? SCAN_PT / 2 : SCAN_PT;  // points per LDS tile
     constexpr int NB = PT / 32;        // 32-point blocks per tile
     __shared__ float4 xs[PT * DS / 4];  // original coordinates, point-major (exact distances)
     // point operands of the filter ([block][step][lane], 16 bytes per lane:
     // every read and write is one contiguous kilobyte)
-    __shared__ bf16x8 xa[NB * NS * 64];
+    __shared__ f16x8 xa[NB * NS * 64];
     __shared__ int32_t os[PT];
     __shared__ float route_splits[ROUTE_LDS_SPLITS];
 
@@ -146,25 +138,36 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
     const float *X = a.base + (a.blk[L] + a.blk_shift);
     const int32_t *orig = reinterpret_cast<const int32_t *>(X) + (int64_t)a.d * len;
     const float *cen = a.centers + (int64_t)L * a.d;
-    const float coef = a.filter_coef;
+    const float sc = a.scales[L];  // power of two: exact scaling
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, half = lane >> 5, col = lane & 31;
     const bool act = tid < qcnt;
     const int32_t q = act ? a.bufq[qbase + tid] : 0;
-    float qv[D], qc[D], Qn = 0.0f;
+    // qs: the scaled centred query p; Qn = |q~|^2 of its float16 rounding; Pn = |p|^2
+    float qv[D], qs[D], Qn = 0.0f, Pn = 0.0f;
+    bool far = false;
 #pragma unroll
     for (int j = 0; j < D; j++) {
         qv[j] = (act && j < a.d) ? a.Q[(int64_t)q * a.d + j] : 0.0f;
-        qc[j] = (act && j < a.d) ? qv[j] - cen[j] : 0.0f;
-        Qn = fmaf(qc[j], qc[j], Qn);
+        qs[j] = (act && j < a.d) ? (qv[j] - cen[j]) * sc : 0.0f;
+        far |= !(fabsf(qs[j]) <= FILTER_FAR);
+        const float r = (float)(_Float16)qs[j];
+        Qn = fmaf(r, r, Qn);
+        Pn = fmaf(qs[j], qs[j], Pn);
     }
+    const float sqd = sqrtf((float)a.d);
+    const float delta = 0x1.01p-10f * (sqrtf(Pn) + sqd) + 0x1p-13f * sqd;
     uint64_t lst[K];
 #pragma unroll
     for (int s2 = 0; s2 < K; s2++) lst[s2] = act ? a.keys[(int64_t)q * K + s2] : 0ull;  // 0: nothing enters
     float thr = __uint_as_float((uint32_t)(lst[K - 1] >> 32));
-    // filter threshold of this lane's query: a pair passes when <q',x'> - bs >= aq
-    auto own_aq = [&]() { return act ? 0.5f * (coef * Qn - thr) - FILTER_ABS_SLACK : INFINITY; };
+    // filter threshold of this lane's query: a pair passes when G >= aq
+    auto own_aq = [&]() {
+        if (!act) return INFINITY;
+        const float r = sqrtf(thr * sc * sc) + delta;
+        return 0.5f * (Qn - r * r) - 0x1p-18f * (Qn + (float)(a.d + 1)) - FILTER_ABS_SLACK;
+    };
 
     const bool wave_busy = (tid & ~63) < qcnt;
     // A wave with a query whose list is not full yet (K-th key EMPTY, first
@@ -172,24 +175,23 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
     // until every list is full, then the filter.  Coordinates beyond the
     // filter's range keep every wave on the exact path.
     const bool no_filter = a.exact_only || (a.wide_flag && *a.wide_flag);
-    bool exact_wave = no_filter || __any(act && isinf(thr));
+    bool exact_wave = no_filter || __any(act && (isinf(thr) || far));
 
     // Matrix-core operands of the filter.  The wave's 64 queries form two
     // column tiles of 32; lane l supplies the query part of products
     // 16 s + 8 (l / 32) .. + 7 of step s for query (32 t + l % 32), and holds
     // that query's threshold.
-    bf16x8 qb[2][NS];
+    f16x8 qb[2][NS];
     float aq[2];
 #pragma unroll
     for (int t = 0; t < 2; t++) {
         const int src = 32 * t + col;
-        __bf16 gh[D], gl[D];
+        _Float16 g[D];
 #pragma unroll
-        for (int j = 0; j < D; j++) split_bf16(__shfl(qc[j], src), gh[j], gl[j]);
-        auto part = [&](int u) -> __bf16 {  // query factor of product u
-            if (u < 2 * D) return gh[u < D ? u : u - D];
-            if (u < 3 * D) return gl[u - 2 * D];
-            return static_cast<__bf16>(u < NT ? 1.0f : 0.0f);
+        for (int j = 0; j < D; j++) g[j] = (_Float16)__shfl(qs[j], src);
+        auto part = [&](int u) -> _Float16 {  // query factor of product u
+            if (u < D) return g[u];
+            return (_Float16)(u < NT ? 1.0f : 0.0f);
         };
 #pragma unroll
         for (int s2 = 0; s2 < NS; s2++) {
@@ -228,9 +230,9 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
         f32x16 c0 = {}, c1 = {};
 #pragma unroll
         for (int s2 = 0; s2 < NS; s2++) {
-            const bf16x8 av = xa[(b * NS + s2) * 64 + lane];
-            c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, qb[0][s2], c0, 0, 0, 0);
-            c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, qb[1][s2], c1, 0, 0, 0);
+            const f16x8 av = xa[(b * NS + s2) * 64 + lane];
+            c0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, qb[0][s2], c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, qb[1][s2], c1, 0, 0, 0);
         }
         float m0 = -INFINITY, m1 = -INFINITY;
 #pragma unroll
@@ -323,34 +325,33 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
             const bool live = tid < np;
             float *ro = reinterpret_cast<float *>(xs) + tid * DS;
             const int ra = (tid >> 5) * NS * 64 + (tid & 31);
-            // centred coordinates (zero past d), their bfloat16 hi parts H and lo
-            // parts Lo, two coordinates to a word
+            // scaled centred coordinates (zero past d) rounded to float16, two to a word,
+            // and |x~|^2 of the rounded values
             constexpr int DP = (D + 1) / 2;
-            float cv[2 * DP], Xn = 0.0f;
-#pragma unroll
-            for (int j = 0; j < 2 * DP; j++) {
-                cv[j] = (j < D) ? pre[j < D ? j : 0] - cr[j < D ? j : 0] : 0.0f;
-                if (j < D) Xn = fmaf(cv[j], cv[j], Xn);
-            }
-            uint32_t H[DP], Lo[DP];
+            uint32_t H[DP];
+            float Xn = 0.0f;
 #pragma unroll
             for (int w = 0; w < DP; w++) {
-                H[w] = pack_bf16x2(cv[2 * w], cv[2 * w + 1]);
-                Lo[w] = pack_bf16x2(cv[2 * w] - bf16_lo(H[w]), cv[2 * w + 1] - bf16_hi(H[w]));
+                const int j0 = 2 * w, j1 = 2 * w + 1;
+                const float u0 = (j0 < D) ? (pre[j0 < D ? j0 : 0] - cr[j0 < D ? j0 : 0]) * sc : 0.0f;
+                const float u1 = (j1 < D) ? (pre[j1 < D ? j1 : 0] - cr[j1 < D ? j1 : 0]) * sc : 0.0f;
+                H[w] = pack_f16x2(u0, u1);
+                const float r0 = f16_word_lo(H[w]), r1 = f16_word_hi(H[w]);
+                Xn = fmaf(r0, r0, Xn);
+                Xn = fmaf(r1, r1, Xn);
             }
 #pragma unroll
             for (int c4 = 0; c4 < DS / 4; c4++)
                 reinterpret_cast<float4 *>(ro)[c4] = make_float4(pre[4 * c4], pre[4 * c4 + 1], pre[4 * c4 + 2], pre[4 * c4 + 3]);
-            // -bs split into (hi, lo); padding rows take a large finite negative
-            // value, which keeps the split free of inf - inf and never passes
-            const float nb = live ? -(0.5f * (coef * Xn)) : -0x1p127f;
-            const uint32_t NBw = pack_bf16x2(nb, nb - bf16_lo(pack_bf16x2(nb, 0.0f)));
+            // -|x~|^2/2 as float16 hi + lo; padding rows take the most negative float16 in
+            // both parts and never pass
+            const float nb = -0.5f * Xn;
+            const uint32_t t0 = pack_f16x2(nb, 0.0f);
+            const uint32_t NBw = live ? pack_f16x2(nb, nb - f16_word_lo(t0)) : 0xfbfffbffu;
             auto part = [&](int u) -> uint32_t {  // point factor of product u, in the low 16 bits
                 if (u < D) return (H[u >> 1] >> (16 * (u & 1))) & 0xffffu;
-                if (u < 2 * D) return (Lo[(u - D) >> 1] >> (16 * ((u - D) & 1))) & 0xffffu;
-                if (u < 3 * D) return (H[(u - 2 * D) >> 1] >> (16 * ((u - 2 * D) & 1))) & 0xffffu;
-                if (u == 3 * D) return NBw & 0xffffu;
-                if (u == 3 * D + 1) return NBw >> 16;
+                if (u == D) return NBw & 0xffffu;
+                if (u == D + 1) return NBw >> 16;
                 return 0u;
             };
             auto word = [&](int w) -> uint32_t { return part(2 * w) | (part(2 * w + 1) << 16); };
@@ -376,7 +377,7 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
             }
             exact_points(32 * b, min(32 * b + 32, np));
             thr = __uint_as_float((uint32_t)(lst[K - 1] >> 32));
-            exact_wave = no_filter || __any(act && isinf(thr));
+            exact_wave = no_filter || __any(act && (isinf(thr) || far));
             if (!exact_wave) {
                 aq[0] = __shfl(own_aq(), col);
                 aq[1] = __shfl(own_aq(), 32 + col);

@@ -175,11 +175,15 @@ void tree_build(Tree &t, const float *P, int64_t n, int d, int h, const bkd_opti
     BKD_HIP(hipMemcpy(t.d_leaf_blk.p, t.leaf_blk.data(), sizeof(int64_t) * t.leaf_blk.size(), hipMemcpyHostToDevice));
     {
         // leaf centres (bounding-box midpoints) for the inner-product filter of the dense scan
-        std::vector<float> cen((size_t)t.nleaf * d);
+        // leaf centres, then each leaf's scale: the power of two 2^-e with 2^e at least its
+        // largest centred coordinate |fl32(x - c)| (attained at the box's lo or hi, since
+        // rounding is monotone), so that scaled centred coordinates lie in [-1, 1]
+        std::vector<float> cen((size_t)t.nleaf * d + t.nleaf);
         std::atomic<bool> wide{false};
         parallel_for(t.nleaf, [&](int64_t b, int64_t e) {
             bool w = false;
             for (int64_t l = b; l < e; l++) {
+                float mx = 0.0f;
                 for (int j = 0; j < d; j++) {
                     float lo = INFINITY, hi = -INFINITY;
                     for (int64_t p = H.leaf_off[(size_t)l]; p < H.leaf_off[(size_t)l + 1]; p++) {
@@ -187,9 +191,16 @@ void tree_build(Tree &t, const float *P, int64_t n, int d, int h, const bkd_opti
                         lo = std::min(lo, v);
                         hi = std::max(hi, v);
                     }
-                    cen[(size_t)l * d + j] = 0.5f * lo + 0.5f * hi;
+                    const float c = 0.5f * lo + 0.5f * hi;
+                    cen[(size_t)l * d + j] = c;
+                    mx = std::max(mx, std::max(std::fabs(lo - c), std::fabs(hi - c)));
                     w |= -lo > FILTER_RANGE || hi > FILTER_RANGE;
                 }
+                int ex = 0;
+                const float m = std::frexp(mx, &ex);  // mx = m 2^ex, m in [0.5, 1)
+                int pe = (mx == 0.0f) ? 0 : (m == 0.5f ? ex - 1 : ex);
+                pe = std::min(126, std::max(-126, pe));
+                cen[(size_t)t.nleaf * d + l] = std::ldexp(1.0f, -pe);
             }
             if (w) wide = true;
         });
@@ -429,7 +440,7 @@ struct Run {
         a.kth = t.d_kth.as<uint32_t>();
         a.k = k;
         a.centers = t.d_centers.as<float>();
-        a.filter_coef = 1.0f - filter_band(d);
+        a.scales = a.centers + (size_t)nleaf * d;
         a.exact_only = t.wide ? 1 : 0;
         a.wide_flag = ctl + CTL_WIDE;
         return a;

@@ -11,8 +11,6 @@ BKD_DECL(15) BKD_DECL(16) BKD_DECL(20) BKD_DECL(24) BKD_DECL(32)
 static const int kDims[] = {2, 3, 4, 5, 6, 8, 10, 12, 15, 16, 20, 24, 32};
 static const int kCaps[] = {1, 2, 4, 5, 8, 10, 16, 32, 64};
 
-float filter_band(int) { return 0x1p-12f; }
-
 int padded_dim(int d)
 {
     for (int D : kDims)

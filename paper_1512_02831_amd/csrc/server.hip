@@ -316,7 +316,7 @@ static void session_round(Session &S, int64_t nnew)
         a.kq = S.kq.as<int32_t>();
         a.exact_only = (T.wide || S.wide) ? 1 : 0;
         a.centers = T.d_centers.as<float>();
-        a.filter_coef = 1.0f - filter_band(H.d);
+        a.scales = a.centers + (size_t)nleaf * H.d;
         launch_leaf_scan(a, S.K, 0, S.s);
         launch_leaf_scan(a, S.K, 1, S.s);
         S.scans++;
