@@ -20,9 +20,11 @@
 // is within the query's K-th, thr, has |q~ - x~|^2 <= T = (sqrt(thr s^2) +
 // delta)^2, and it passes G >= (|q~|^2 - T)/2 - 2^-18 (|q~|^2 + d + 1) - eta;
 // the 2^-18 term covers the float32 accumulations (products of float16 are
-// exact), eta = 2^-100 underflow.  The band is relative to the leaf, not to
-// |q'|^2 + |x'|^2: a query at distance r from the leaf centre moves its radius
-// by about delta ~ 2^-10 (r + sqrt d) leaf radii.  A query with a scaled
+// exact), eta = 2^-100 underflow; the square root in T is the hardware's
+// (within 2^-21 relative, flushed below 2^-126), covered by delta's 1 + 2^-8.
+// The band is relative to the leaf, not to |q'|^2 + |x'|^2: a query at
+// distance r from the leaf centre moves its radius by about
+// delta ~ 2^-10 (r + sqrt d) leaf radii.  A query with a scaled
 // offset beyond 2^14 (far outside its leaf, or a leaf of tiny extent) takes
 // the exact path.  Passing pairs go to the lane owning the query, which
 // re-checks them with the exact float32 distance, so keys and results are
@@ -163,9 +165,11 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
     for (int s2 = 0; s2 < K; s2++) lst[s2] = act ? a.keys[(int64_t)q * K + s2] : 0ull;  // 0: nothing enters
     float thr = __uint_as_float((uint32_t)(lst[K - 1] >> 32));
     // filter threshold of this lane's query: a pair passes when G >= aq
+    // (the hardware square root here: its error, at most 2^-21 relative and a
+    // flush below 2^-126, is covered by the factor 1 + 2^-8 in delta)
     auto own_aq = [&]() {
         if (!act) return INFINITY;
-        const float r = sqrtf(thr * sc * sc) + delta;
+        const float r = __builtin_amdgcn_sqrtf(thr * sc * sc) + delta;
         return 0.5f * (Qn - r * r) - 0x1p-18f * (Qn + (float)(a.d + 1)) - FILTER_ABS_SLACK;
     };
 
@@ -198,7 +202,11 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
 #pragma unroll
             for (int e = 0; e < 8; e++) qb[t][s2][e] = half ? part(16 * s2 + 8 + e) : part(16 * s2 + e);
         }
-        aq[t] = __shfl(own_aq(), src);
+    }
+    {
+        const float o = own_aq();
+        aq[0] = __shfl(o, col);
+        aq[1] = __shfl(o, 32 + col);
     }
 
     auto exact_points = [&](int i0, int i1) {
@@ -287,8 +295,9 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
         }
         if (__any(changed)) {
             thr = __uint_as_float((uint32_t)(lst[K - 1] >> 32));
-            aq[0] = __shfl(own_aq(), col);
-            aq[1] = __shfl(own_aq(), 32 + col);
+            const float o = own_aq();
+            aq[0] = __shfl(o, col);
+            aq[1] = __shfl(o, 32 + col);
         }
     };
 
@@ -379,8 +388,9 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
             thr = __uint_as_float((uint32_t)(lst[K - 1] >> 32));
             exact_wave = no_filter || __any(act && (isinf(thr) || far));
             if (!exact_wave) {
-                aq[0] = __shfl(own_aq(), col);
-                aq[1] = __shfl(own_aq(), 32 + col);
+                const float o = own_aq();
+                aq[0] = __shfl(o, col);
+                aq[1] = __shfl(o, 32 + col);
             }
         }
     }

@@ -13,8 +13,10 @@ A pair passes when
     delta = 2^-10 (1 + 2^-8)(|p| + sqrt d) + 2^-13 sqrt d,
 
 with p the scaled query offset and thr the query's current K-th float32
-squared distance.  The claim: every pair whose float32 distance (the oracle's
-arithmetic) is at most thr passes.  These tests emulate every rounding
+squared distance; the square root in T is the hardware's approximate one,
+modelled at its worst (2^-21 relative low, zero below 2^-126).  The claim:
+every pair whose float32 distance (the oracle's arithmetic) is at most thr
+passes.  These tests emulate every rounding
 exactly with rationals, float16 rounding to nearest even, toward zero, or
 with subnormals flushed, at thresholds equal to the pair's own distance and
 one ulp either side, and check the claim; a negative control shows that the
@@ -68,6 +70,14 @@ def sqrt32(x: F) -> F:
     return F(float(np.sqrt(np.float32(float(x)))))
 
 
+def hw_sqrt(v: F) -> F:
+    """The kernel's approximate square root, taken at its worst: two float32 ulps low
+    (2^-21 relative), and zero for inputs below the normal range."""
+    if v < F(2) ** -126:
+        return F(0)
+    return f32(sqrt32(v) * (1 - F(2) ** -21))
+
+
 def filter_margin(q, x, c, e, thr: F, rng, mode: str, widen: bool = True):
     """min over accumulation orders and roundings of G - aq (>= 0: the pair passes), and the
     pair's float32 squared distance."""
@@ -93,7 +103,7 @@ def filter_margin(q, x, c, e, thr: F, rng, mode: str, widen: bool = True):
     prods = [qt[j] * xt[j] for j in range(d)] + [bh, bl]
     sqd = sqrt32(F(d))
     delta = f32(f32(F(2) ** -10 * F(257, 256) * f32(sqrt32(Pn) + sqd)) + f32(F(2) ** -13 * sqd)) if widen else F(0)
-    r = f32(sqrt32(f32(f32(thr * s) * s)) + delta)
+    r = f32(hw_sqrt(f32(f32(thr * s) * s)) + delta)
     aq = f32(f32(F(1, 2) * f32(Qn - f32(r * r))) - f32(F(2) ** -18 * f32(Qn + d + 1))) - F(2) ** -100
     worst = None
     for rnd in (lambda v: F(round_f32(v)), round_rz):
