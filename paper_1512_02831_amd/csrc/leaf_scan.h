@@ -234,11 +234,11 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
     // One 32-point block against the wave's 64 queries.  The accumulator
     // register r of lane l holds point 32 b + (r % 4) + 8 (r / 4) + 4 (l / 32)
     // against query (32 t + l % 32).
-    auto filter_block = [&](int b, int np) {
+    auto filter_block = [&](int b, int np, const f16x8 *avs) {
         f32x16 c0 = {}, c1 = {};
 #pragma unroll
         for (int s2 = 0; s2 < NS; s2++) {
-            const f16x8 av = xa[(b * NS + s2) * 64 + lane];
+            const f16x8 av = avs[s2];
             c0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, qb[0][s2], c0, 0, 0, 0);
             c1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, qb[1][s2], c1, 0, 0, 0);
         }
@@ -308,14 +308,22 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
     int32_t pre_o = 0;
 #pragma unroll
     for (int j = 0; j < DS; j++) cr[j] = (j < a.d) ? cen[j] : 0.0f;
+    // A column base (uniform) plus one 32-bit byte offset per thread: the loads
+    // take the scalar-base form, so the scan below never has to wait for them
+    // before reusing an address register.
+    auto at = [](const void *base, uint32_t bo) {
+        return reinterpret_cast<const char *>(base) + bo;
+    };
     auto load_tile = [&](int64_t pt) {
         if (PT < SCAN_THREADS && tid >= PT) return;
         const int np = (int)min((int64_t)PT, p1 - pt);
         // rows past the tile load a valid point of the item; they are never read as points
         const int i = tid < np ? (int)(pt - l0) + tid : first_pt;
         if (a.d == D) {
+            const uint32_t bo = (uint32_t)i * 4u;
 #pragma unroll
-            for (int j = 0; j < DS; j++) pre[j] = (j < D) ? X[(j < D ? j : 0) * len + i] : 0.0f;
+            for (int j = 0; j < DS; j++)
+                pre[j] = (j < D) ? *reinterpret_cast<const float *>(at(X + (int64_t)(j < D ? j : 0) * len, bo)) : 0.0f;
         } else {
 #pragma unroll
             for (int j = 0; j < DS; j++) {
@@ -323,7 +331,7 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
                 pre[j] = (j < a.d) ? x : 0.0f;
             }
         }
-        pre_o = orig[i];
+        pre_o = *reinterpret_cast<const int32_t *>(at(orig, (uint32_t)i * 4u));
     };
     load_tile(p0);
     for (int64_t pt = p0; pt < p1; pt += PT) {
@@ -379,15 +387,29 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
         __syncthreads();
         if (pt + PT < p1) load_tile(pt + PT);
         if (!wave_busy) continue;  // whole wave without queries: only helps staging
-        for (int b = 0; b < npad / 32; b++) {
+        // the point operand of block b + 1 is read from LDS while block b is filtered
+        const int nbl = npad / 32;
+        f16x8 avn[NS];
+        auto fetch_operand = [&](int b) {
+            const int bn = min(b, nbl - 1);
+#pragma unroll
+            for (int s2 = 0; s2 < NS; s2++) avn[s2] = xa[(bn * NS + s2) * 64 + lane];
+        };
+        fetch_operand(0);
+        for (int b = 0; b < nbl; b++) {
             if (!exact_wave) {
-                filter_block(b, np);
+                f16x8 av[NS];
+#pragma unroll
+                for (int s2 = 0; s2 < NS; s2++) av[s2] = avn[s2];
+                fetch_operand(b + 1);
+                filter_block(b, np, av);
                 continue;
             }
             exact_points(32 * b, min(32 * b + 32, np));
             thr = __uint_as_float((uint32_t)(lst[K - 1] >> 32));
             exact_wave = no_filter || __any(act && (isinf(thr) || far));
             if (!exact_wave) {
+                fetch_operand(b + 1);
                 const float o = own_aq();
                 aq[0] = __shfl(o, col);
                 aq[1] = __shfl(o, 32 + col);
