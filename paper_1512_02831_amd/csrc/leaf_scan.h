@@ -170,7 +170,8 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
     auto own_aq = [&]() {
         if (!act) return INFINITY;
         const float r = __builtin_amdgcn_sqrtf(thr * sc * sc) + delta;
-        return 0.5f * (Qn - r * r) - 0x1p-18f * (Qn + (float)(a.d + 1)) - FILTER_ABS_SLACK;
+        const float v = 0.5f * (Qn - r * r) - 0x1p-18f * (Qn + (float)(a.d + 1)) - FILTER_ABS_SLACK;
+        return v == 0.0f ? -0x1p-149f : v;  // never zero: the mask test below reads a sign
     };
 
     const bool wave_busy = (tid & ~63) < qcnt;
@@ -253,17 +254,24 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
         // owns the query (lane 32 t + j for column j of tile t), which
         // re-checks it with the exact float32 distance.  Bit r of a tile's
         // mask is accumulator register r (masks are built only for a tile that
-        // has a passing pair); the owner of tile t (lanes with l / 32 = t)
+        // has a passing pair): the sign of G - aq, shifted in by alignbit, is
+        // clear exactly when G >= aq, since aq is never zero and float32
+        // subtraction keeps subnormals (x - y is +0 only for x == y, and -0
+        // never arises with y != 0).  The owner of tile t (lanes with l / 32 = t)
         // gets its partner's mask of the same column (lane l ^ 32), and bit
         // 16 h + r of the merged mask is point (r % 4) + 8 (r / 4) + 4 h.
         uint32_t f0 = 0, f1 = 0;
         if (__any(m0 >= aq[0])) {
+            uint32_t nf = 0;
 #pragma unroll
-            for (int r = 0; r < 16; r++) f0 |= (c0[r] >= aq[0]) ? (1u << r) : 0u;
+            for (int r = 15; r >= 0; r--) nf = __builtin_amdgcn_alignbit(nf, __float_as_uint(c0[r] - aq[0]), 31);
+            f0 = ~nf & 0xffffu;
         }
         if (__any(m1 >= aq[1])) {
+            uint32_t nf = 0;
 #pragma unroll
-            for (int r = 0; r < 16; r++) f1 |= (c1[r] >= aq[1]) ? (1u << r) : 0u;
+            for (int r = 15; r >= 0; r--) nf = __builtin_amdgcn_alignbit(nf, __float_as_uint(c1[r] - aq[1]), 31);
+            f1 = ~nf & 0xffffu;
         }
         const uint32_t recv = __shfl_xor(half ? f0 : f1, 32);
         uint32_t msk = half ? (recv | (f1 << 16)) : (f0 | (recv << 16));

@@ -185,3 +185,33 @@ def test_threshold_widening_is_small_for_typical_geometry():
     for pnorm in (0.5, 1.0, 3.0, 10.0):
         delta = 2 ** -10 * (1 + 2 ** -8) * (pnorm + np.sqrt(10)) + 2 ** -13 * np.sqrt(10)
         assert ((0.5 + delta) / 0.5) ** 2 < 1.06
+
+
+def _sign_test(c, aq):
+    """The dense scan's mask bit: the sign of c - aq (float32) is clear."""
+    with np.errstate(invalid="ignore", over="ignore"):
+        t = np.float32(c) - np.float32(aq)
+    return not np.signbit(t)
+
+
+def test_mask_sign_bit_matches_comparison():
+    """With aq never zero, 'sign of G - aq clear' is exactly G >= aq in float32, subnormals kept:
+    x - y is +0 only for x == y and is never -0 for y != 0."""
+    rng = np.random.default_rng(4)
+    f32v = np.float32
+    specials = [f32v(0.0), f32v(-0.0), f32v(1e-45), f32v(-1e-45), f32v(1.17549435e-38), f32v(-3e-39),
+                f32v(1.0), f32v(-1.0), f32v(3.4e38), f32v(-3.4e38)]
+    aqs = [v for v in specials if v != 0] + [f32v(np.inf), f32v(-np.inf), f32v(-1e-45)]
+    vals = specials + list(rng.standard_normal(200).astype(np.float32)) + \
+        list((rng.standard_normal(100) * 1e-40).astype(np.float32))
+    checked = 0
+    for aq in aqs + list(rng.standard_normal(50).astype(np.float32)):
+        near = [aq, np.nextafter(aq, f32v(np.inf)), np.nextafter(aq, f32v(-np.inf))] if np.isfinite(aq) else []
+        for c in vals + near:
+            if not np.isfinite(c):
+                continue
+            assert _sign_test(c, aq) == bool(c >= aq), (float(c), float(aq))
+            checked += 1
+    assert checked > 10000
+    # the guard is needed: with aq = +0, G = -0 passes the comparison but not the sign test
+    assert f32v(-0.0) >= f32v(0.0) and not _sign_test(f32v(-0.0), f32v(0.0))
