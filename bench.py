@@ -375,6 +375,20 @@ def main():
                      "t_streamed_over_t_resident": round(wall / rwall, 4),
                      "schedule": "lock-step rounds, chunk sweep (each resident chunk drained before the next)"}
 
+    end_to_end = None
+    if not budget:
+        # host queries in, host results out: the blocking bkd_query, host-link transfers included
+        # (reported beside the device-resident value, never as it)
+        bkd.query(tree, Q, k)
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            bkd.query(tree, Q, k)
+            times.append(time.perf_counter() - t0)
+        t_e2e = sorted(times)[1]
+        end_to_end = {"queries_per_s": round(m / t_e2e, 1), "ms_per_call": round(t_e2e * 1e3, 3),
+                      "what": "bkd_query on host arrays (Q in, idx and dist out), median of 3 calls"}
+
     ms_per_step = wall * 1e3 / args.steps
     value = m * args.steps / wall
     # Dominant kernel: the dense leaf scan.  Algorithmic work per (query, leaf point) pair is
@@ -432,6 +446,7 @@ def main():
                    "streaming": streaming,
                    "pairs_per_query": acc["pairs"] / (args.steps * m)},
         "roofline": roofline,
+        "end_to_end": end_to_end,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, Q, k, args.cpu_seconds)

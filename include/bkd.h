@@ -190,6 +190,30 @@ int bkd_query(bkd_tree *tree, const float *Q, int64_t m, int32_t k, int64_t *out
 int bkd_query_async(bkd_tree *tree, const float *dQ, int64_t m, int32_t k, int64_t *d_idx, float *d_dist,
                     void *stream);
 
+/*
+ * Proximity-based outlier scores (Section 4, large-scale outlier detection):
+ * the all-nearest-neighbours problem over the tree's own reference set.  The
+ * score of reference point i is the mean of the float32 distances (as
+ * bkd_query returns them) to its k nearest other reference points: the k + 1
+ * nearest are searched with the tree's query path, i's own entry is dropped
+ * (when more than k other points share i's coordinates with smaller indices
+ * it is not among them, and the first k are kept), and the k distances are
+ * summed in ascending order in float64 and divided by k.  The ranking lists
+ * the points by score, largest first, equal scores by smaller index.
+ *   tree       built from P.
+ *   P          host [n][d] float32, row-major: the same array the tree was
+ *              built from (rows are matched to tree points by index).
+ *   n          must equal the tree's n.
+ *   k          1 <= k <= min(n - 1, BKD_MAX_K - 1).
+ *   out_score  host [n] float32, caller-owned: out_score[i] is point i's score.
+ *   out_order  host [n] int64, caller-owned: point indices, highest score first.
+ * Blocking.  Uses the tree's host-pointer stream, like bkd_query, and
+ * allocates device memory for the sort during the call.
+ * Errors: BKD_EINVAL (NULL pointers, n or k out of range, non-finite P),
+ * BKD_ENOMEM, BKD_EDEVICE.
+ */
+int bkd_outlier_scores(bkd_tree *tree, const float *P, int64_t n, int32_t k, float *out_score, int64_t *out_order);
+
 /* Static facts of the tree. */
 int bkd_tree_info_get(const bkd_tree *tree, bkd_tree_info *out);
 

@@ -252,3 +252,31 @@ def keys_split(keys: np.ndarray):
     d2 = (keys >> np.uint64(32)).astype(np.uint32).view(np.float32)
     idx = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
     return d2, idx
+
+
+def outlier_scores(P, k: int, threads: int = 0):
+    """Proximity-based outlier scores (Section 4, large-scale outlier detection; the score of
+    a point is its mean distance to its k nearest neighbours among the other reference points,
+    and points are ranked by it).  Written from the definition: exhaustive float32-contract
+    kNN of every reference point against the reference set with k + 1 neighbours, the point's
+    own entry dropped once (the first k kept when it is absent), distances sqrt(d2) in
+    float32, their float64 sum in ascending order divided by k, rounded to float32.
+    Returns (score float32 [n], order int64 [n]): order lists indices by score, largest first,
+    equal scores by smaller index."""
+    P = _f32(P)
+    n = P.shape[0]
+    keys = brute_f32c(P, P, k + 1, threads)
+    d2, idx = keys_split(keys)
+    dist = np.sqrt(d2)  # float32, correctly rounded
+    score = np.empty(n, dtype=np.float32)
+    for i in range(n):
+        row = [j for j in range(k + 1)]
+        own = np.nonzero(idx[i] == i)[0]
+        if len(own):
+            row.remove(int(own[0]))
+        s = 0.0
+        for j in row[:k]:
+            s += float(dist[i, j])
+        score[i] = np.float32(s / k)
+    order = np.lexsort((np.arange(n), -score.astype(np.float64)))
+    return score, order.astype(np.int64)

@@ -66,6 +66,7 @@ _PROTOS = {
     "bkd_free": (ctypes.c_int, [_V]),
     "bkd_query": (ctypes.c_int, [_V, _V, _I64, _I32, _V, _V]),
     "bkd_query_async": (ctypes.c_int, [_V, _V, _I64, _I32, _V, _V, _V]),
+    "bkd_outlier_scores": (ctypes.c_int, [_V, _V, _I64, _I32, _V, _V]),
     "bkd_tree_info_get": (ctypes.c_int, [_V, _V]),
     "bkd_tree_export": (ctypes.c_int, [_V, _V, _V, _V]),
     "bkd_chunk_plan": (ctypes.c_int, [_V, _V, _V]),
@@ -199,6 +200,19 @@ def query(tree: Tree, Q, k: int):
     dist = np.empty((m, k), dtype=np.float32)
     _check(lib().bkd_query(tree.handle, _p(Q), m, k, _p(idx), _p(dist)))
     return idx, dist
+
+
+def outlier_scores(tree: Tree, P, k: int):
+    """``bkd_outlier_scores``: the tree's own reference set P float32 [n, d] ->
+    (score float32 [n], order int64 [n], highest score first)."""
+    P = np.ascontiguousarray(P, dtype=np.float32)
+    if P.ndim != 2 or P.shape[1] != tree.d:
+        raise ValueError("P must be [n, d] with the tree's d")
+    n = P.shape[0]
+    score = np.empty(n, dtype=np.float32)
+    order = np.empty(n, dtype=np.int64)
+    _check(lib().bkd_outlier_scores(tree.handle, _p(P), n, k, _p(score), _p(order)))
+    return score, order
 
 
 def query_async(tree: Tree, dQ, k: int, d_idx, d_dist, stream=None):

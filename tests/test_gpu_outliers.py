@@ -1,0 +1,68 @@
+"""Parity of bkd_outlier_scores (Section 4, proximity-based outlier detection) with the oracle:
+scores bit-identical (the same float32 distances summed in the same order in float64) and the
+ranking identical, on a clustered set with planted outliers, on exact duplicates (a point's own
+entry missing from its k + 1 nearest), through a streamed tree and with the squared-distance
+output flag set on the tree."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+import paper_1512_02831_amd as bkd
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def planted(n, d, seed):
+    P, _ = datagen.mixture_pq(seed, n, 16, d, 8)
+    rng = np.random.default_rng(seed)
+    far = P[rng.integers(0, n, 12)] + rng.normal(0, 40.0, (12, d)).astype(np.float32)
+    P = P.copy()
+    P[rng.choice(n, 12, replace=False)] = far
+    return P
+
+
+@pytest.mark.parametrize("n,d,h,k,opts", [
+    (1 << 14, 10, 6, 10, {}),
+    (20000, 5, 7, 5, {"flags": bkd.FLAG_SQUARED}),
+    (1 << 14, 10, 6, 10, {"leaf_budget_bytes": 200_000}),
+])
+def test_outlier_scores_match_oracle(n, d, h, k, opts):
+    say(f"outliers n={n} d={d} h={h} k={k} opts={opts}")
+    P = planted(n, d, 1512 + d)
+    with bkd.build(P, h, buffer_size=-1, fetch_size=-1, **opts) as t:
+        score, order = bkd.outlier_scores(t, P, k)
+    ref_s, ref_o = oracle.outlier_scores(P, k)
+    assert np.array_equal(score.view(np.uint32), ref_s.view(np.uint32))
+    assert np.array_equal(order, ref_o)
+
+
+def test_outlier_scores_with_duplicates():
+    say("outliers with duplicates")
+    rng = np.random.default_rng(7)
+    base = rng.standard_normal((3000, 4)).astype(np.float32)
+    P = np.vstack([base, np.repeat(base[:5], 9, axis=0)])  # ten copies of five points
+    P = P[rng.permutation(len(P))]
+    with bkd.build(P, 5, buffer_size=-1, fetch_size=-1) as t:
+        score, order = bkd.outlier_scores(t, P, 6)
+    ref_s, ref_o = oracle.outlier_scores(P, 6)
+    assert np.array_equal(score.view(np.uint32), ref_s.view(np.uint32))
+    assert np.array_equal(order, ref_o)
+
+
+def test_outlier_scores_rejects_bad_arguments():
+    P = np.random.default_rng(3).standard_normal((100, 3)).astype(np.float32)
+    with bkd.build(P, 2) as t:
+        with pytest.raises(bkd.BkdError):
+            bkd.outlier_scores(t, P[:50], 3)  # not the tree's n
+        with pytest.raises(bkd.BkdError):
+            bkd.outlier_scores(t, P, 64)  # k + 1 beyond the key capacity
