@@ -311,12 +311,57 @@ def run_served(args, torch, bkd):
     }
 
 
+def run_outliers(args, torch, bkd):
+    """Proximity-based outlier scores of the on-device reference set: every point of the
+    n = 2^22 mixture is a query (k + 1 = 11 nearest), scored and ranked by bkd_outlier_scores
+    (host arrays in and out, so the host link is inside the timed calls)."""
+    w = WORKLOADS["ondevice"]
+    n, d, k, h = w["n"], w["d"], w["k"], w["h"]
+    P, _ = make_inputs(w, args.seed)
+    tree = bkd.build(P, h, buffer_size=-1, fetch_size=-1, flags=bkd.FLAG_TIMING)
+    for _ in range(args.warmup):
+        bkd.outlier_scores(tree, P, k)
+    times, dense_ms, dense_pairs, dense_launches = [], 0.0, 0, 0
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        bkd.outlier_scores(tree, P, k)
+        times.append(time.perf_counter() - t0)
+        st = bkd.last_stats(tree)
+        dense_ms += st["dense_ms"]
+        dense_pairs += st["dense_pairs"]
+        dense_launches += st["dense_launches"]
+    tree.free()
+    wall = sum(times)
+    achieved = 3.0 * d * dense_pairs / max(dense_ms * 1e-3, 1e-12) / 1e12
+    out = {
+        "metric": "outlier scores/s (all-nearest-neighbours, d=10, k=10)",
+        "value": round(n * args.steps / wall, 1), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"outliers: the on-device reference set (n={n} d={d}, 16-component Gaussian "
+                               f"mixture, seed {args.seed}, height {h}) scored against itself, k={k}, "
+                               "host arrays in and out",
+                   "n": n, "d": d, "k": k, "height": h},
+        "roofline": {"kernel": f"k_leaf_scan<{d},{k + 1}> (dense leaf scan)", "bound": "mfma",
+                     "achieved": round(achieved, 3), "peak": F16_MATRIX_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / F16_MATRIX_PEAK_TFLOPS, 4), "traffic": None,
+                     "avg_launch_ms": round(dense_ms / max(dense_launches, 1), 4),
+                     "share_of_step": round(dense_ms * 1e-3 / wall, 4)},
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(P, P, k + 1, args.cpu_seconds)
+        cb["unit"] = "points/s"
+        cb["sample"] += " (the k + 1 nearest of each sampled point; the scoring itself is not timed)"
+        out["cpu_baseline"] = cb
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ondevice", choices=sorted(WORKLOADS) + ["batched", "served"])
+    ap.add_argument("--workload", default="ondevice", choices=sorted(WORKLOADS) + ["batched", "served", "outliers"])
     ap.add_argument("--served-requests", type=int, default=2000, help="requests per open-loop level")
     ap.add_argument("--seed", type=int, default=datagen.DEFAULT_SEED)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU baseline sample size in seconds")
@@ -345,6 +390,9 @@ def main():
         return
     if args.workload == "served":
         print(json.dumps(run_served(args, torch, bkd)), flush=True)
+        return
+    if args.workload == "outliers":
+        print(json.dumps(run_outliers(args, torch, bkd)), flush=True)
         return
     w = WORKLOADS[args.workload]
     n, m, d, k, h = w["n"], w["m"], w["d"], w["k"], w["h"]
