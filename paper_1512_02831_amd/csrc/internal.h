@@ -205,6 +205,9 @@ void launch_localize(int32_t *ids, const uint32_t *leaf, int64_t m, int d, const
                      int32_t *node, int h, hipStream_t s);
 void launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s);
 
+// Leaves at least this large get the tail kernel's 512-lane workgroups.
+constexpr int TAIL_WIDE_LEAF = 2048;
+
 struct ScanArgs {
     const int32_t *tiles;     // [nleaf+1] dense work-item offsets
     const int32_t *sparse;    // [nleaf+1] sparse work-item offsets
@@ -237,6 +240,7 @@ struct ScanArgs {
     const int32_t *tail_q;
     int32_t tail_count;
     int tail_counted;         // the first visit of each tail entry is already in the work counters
+    int tail_wide;            // tail workgroups of 512 lanes (leaves of TAIL_WIDE_LEAF points and more)
     int32_t *node;            // [m] traversal state, set to DONE at the end
     const float *split;       // [2^h - 1]
     int h, k;                 // tree height; k of the query (pruning uses the k-th key)

@@ -572,7 +572,10 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
 // route_leaf set (a streamed structure), only the leaves [leaf_first,
 // leaf_last] of the resident chunk are available: a query stops at its first
 // next leaf outside them and leaves that leaf (2^h when done) in its entry.
+// TT lanes per entry: 256, or 512 for leaves of 2048 points and more, where
+// twice the loads in flight per leaf visit pay for the wider merge.
 constexpr int TAIL_THREADS = 256;
+constexpr int TAIL_THREADS_WIDE = 512;
 constexpr int TAIL_LDS_SPLITS = 2047;
 
 template <int K> __device__ inline void lane_list_insert(uint64_t &li, uint64_t ck, int lane)
@@ -584,16 +587,16 @@ template <int K> __device__ inline void lane_list_insert(uint64_t &li, uint64_t 
     if (lane >= K) li = ~0ull;
 }
 
-template <int D, int K> __global__ __launch_bounds__(TAIL_THREADS) void k_tail(ScanArgs a)
+template <int D, int K, int TT> __global__ __launch_bounds__(TT) void k_tail(ScanArgs a)
 {
-    constexpr int W = TAIL_THREADS / 64;
+    constexpr int W = TT / 64;
     constexpr int U = 4;
     __shared__ float split_lds[TAIL_LDS_SPLITS];
     __shared__ uint64_t cand[W][K];
     __shared__ float q_lds[D];  // the query, read by every step of the walk
     const int h = a.h;
     const int lds_nodes = min((1 << h) - 1, TAIL_LDS_SPLITS);
-    for (int i = threadIdx.x; i < lds_nodes; i += TAIL_THREADS) split_lds[i] = a.split[i];
+    for (int i = threadIdx.x; i < lds_nodes; i += TT) split_lds[i] = a.split[i];
 
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int32_t q = a.tail_q[blockIdx.x];

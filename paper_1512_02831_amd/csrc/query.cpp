@@ -583,6 +583,7 @@ struct Run {
         a.tail_leaf = Rl;
         a.tail_q = Rq;
         a.tail_count = (int32_t)n;
+        a.tail_wide = (t.host.n >> h) >= TAIL_WIDE_LEAF;
         a.route_leaf = Rl;
         a.node = t.d_node.as<int32_t>();
         a.split = t.d_split.as<float>();
@@ -742,6 +743,7 @@ struct Run {
         a.tail_leaf = leafbuf[cur];
         a.tail_q = qbuf[cur];
         a.tail_count = (int32_t)P;
+        a.tail_wide = (t.host.n >> h) >= TAIL_WIDE_LEAF;
         a.tail_counted = counted ? 1 : 0;
         a.node = t.d_node.as<int32_t>();
         a.split = t.d_split.as<float>();

@@ -6,7 +6,10 @@
     case KK:                                                                                        \
         if (!sparse && a.item_count > 0) k_leaf_scan<D, KK><<<grid, SCAN_THREADS, 0, s>>>(a);      \
         if (sparse == 1 && a.sitem_count > 0) k_leaf_scan_sparse<D, KK><<<sgrid, SCAN_THREADS, 0, s>>>(a); \
-        if (sparse == 2 && a.tail_count > 0) k_tail<D, KK><<<(unsigned)a.tail_count, TAIL_THREADS, 0, s>>>(a); \
+        if (sparse == 2 && a.tail_count > 0 && a.tail_wide)                                       \
+            k_tail<D, KK, TAIL_THREADS_WIDE><<<(unsigned)a.tail_count, TAIL_THREADS_WIDE, 0, s>>>(a); \
+        if (sparse == 2 && a.tail_count > 0 && !a.tail_wide)                                      \
+            k_tail<D, KK, TAIL_THREADS><<<(unsigned)a.tail_count, TAIL_THREADS, 0, s>>>(a);       \
         break;
 
 #define BKD_SCAN_INSTANTIATE(D)                                                                     \

@@ -167,6 +167,20 @@ def test_streamed_sweep_tail_matches_resident(budget, N, tail_max):
     assert np.array_equal(keys, oracle.brute_f32c(P, Q, k))
 
 
+def test_streamed_sweep_wide_tail_matches_oracle():
+    # leaves of 4096 points: the chunk sweep's tail runs 512-lane workgroups
+    say("case: sweep tail with 4096-point leaves, N=3")
+    P, Q = datagen.mixture_pq(seed=21, n=1 << 16, m=4000, d=10, comps=6)
+    k, h = 10, 4
+    ref, _, st_ref, _ = gpu_keys(P, Q, k, h, fetch_size=-1, buffer_size=-1, flags=bkd.FLAG_NO_TAIL)
+    keys, _, st, info = gpu_keys(P, Q, k, h, fetch_size=-1, buffer_size=-1, chunk_mode=bkd.CHUNK_LEAF,
+                                 num_chunks=3, tail_max=0)
+    assert info.resident == 0 and info.num_chunks >= 2
+    assert np.array_equal(keys, ref)
+    assert st["visits"] == st_ref["visits"] and st["pairs"] == st_ref["pairs"]
+    assert np.array_equal(keys, oracle.brute_f32c(P, Q, k))
+
+
 @pytest.mark.parametrize("mode,N,B,M", [(bkd.CHUNK_LEAF, 5, 64, 500), (bkd.CHUNK_POSITION, 4, 0, 0),
                                         (bkd.CHUNK_POSITION, 9, 16, 100)])
 def test_streamed_algorithm1_matches_replay(mode, N, B, M):
@@ -212,6 +226,8 @@ def test_edge_shapes(n, m, d, k, h):
     (5000, 300, 15, 64, 4, 0),         # largest k in the tail
     (3000, 2048, 3, 1, 8, 2048),       # exactly the hand-over size
     (40000, 3000, 10, 10, 7, 1),       # a single pending query left for the tail
+    (1 << 16, 5000, 10, 10, 4, 0),     # leaves of 4096 points: 512-lane tail workgroups
+    (1 << 15, 1000, 5, 64, 3, 0),      # the same with the largest k
 ])
 def test_lockstep_tail_matches_rounds_and_oracle(n, m, d, k, h, tail_max):
     say(f"case: tail n={n} m={m} d={d} k={k} h={h} tail_max={tail_max}")
