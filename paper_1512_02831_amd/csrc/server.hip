@@ -278,6 +278,7 @@ static void session_round(Session &S, int64_t nnew)
         a.tail_leaf = leafbuf[S.cur];
         a.tail_q = qbuf[S.cur];
         a.tail_count = (int32_t)S.P;
+        a.tail_wide = (H.n >> H.h) >= TAIL_WIDE_LEAF;
         a.node = S.node.as<int32_t>();
         a.split = T.d_split.as<float>();
         a.h = H.h;

@@ -27,9 +27,10 @@ def trees():
     return (PA, 7), (PB, 5)
 
 
-def test_requests_same_alone_and_in_the_mix():
-    say("case: 80 requests, two trees, mixed k, two submitting threads")
-    (PA, hA), (PB, hB) = trees()
+@pytest.mark.parametrize("hA", [7, 4])  # h = 4: leaves of 2500 points, 512-lane tail workgroups
+def test_requests_same_alone_and_in_the_mix(hA):
+    say(f"case: 80 requests, two trees (hA={hA}), mixed k, two submitting threads")
+    (PA, _), (PB, hB) = trees()
     ta = bkd.build(PA, hA, flags=bkd.FLAG_SQUARED)
     tb = bkd.build(PB, hB, flags=bkd.FLAG_SQUARED)
     rng = np.random.default_rng(5)
