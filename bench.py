@@ -65,7 +65,7 @@ def dense_scan_traffic(kernel_src="paper_1512_02831_amd/csrc/leaf_scan.h",
 
 
 def h2d_rate_gbs(torch, nbytes=1 << 30):
-    """Pinned host-to-device copy rate of this box (one 1 GiB copy after a warm-up)."""
+    """Pinned host-to-device copy rate of this machine (one 1 GiB copy after a warm-up)."""
     src = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
     dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst.copy_(src, non_blocking=True)
