@@ -405,7 +405,20 @@ def main():
     P, Q = make_inputs(w, args.seed)
     # lock-step rounds: every active query is fetched each iteration (results do not depend on B, M)
     budget = w.get("budget", 0)
+    t_build = time.perf_counter()
     tree = bkd.build(P, h, buffer_size=-1, fetch_size=-1, flags=bkd.FLAG_TIMING, leaf_budget_bytes=budget)
+    t_build = time.perf_counter() - t_build
+    build = None
+    if not budget:
+        # the same tree built on the device (both times include the leaf structure's upload)
+        t_dev = time.perf_counter()
+        dtree = bkd.build(P, h, buffer_size=-1, fetch_size=-1, flags=bkd.FLAG_DEVICE_BUILD)
+        t_dev = time.perf_counter() - t_dev
+        same = all(np.array_equal(a, b) for a, b in zip(bkd.tree_export(tree), bkd.tree_export(dtree)))
+        dtree.free()
+        build = {"host_s": round(t_build, 3), "device_s": round(t_dev, 3), "same_tree": same,
+                 "what": "bkd_build wall time: canonical tree (host, or device with BKD_FLAG_DEVICE_BUILD) "
+                         "plus the leaf structure's upload"}
     dQ = torch.from_numpy(Q).to("cuda")
     di = torch.empty((m, k), dtype=torch.int64, device="cuda")
     dd = torch.empty((m, k), dtype=torch.float32, device="cuda")
@@ -501,6 +514,7 @@ def main():
                    "pairs_per_query": acc["pairs"] / (args.steps * m)},
         "roofline": roofline,
         "end_to_end": end_to_end,
+        "build": build,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, Q, k, args.cpu_seconds)

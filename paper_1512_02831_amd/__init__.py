@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libbkd.so")
 
 OK, EINVAL, ENOMEM, EBUDGET, EDEVICE, EBUSY, ETIMEOUT, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7
 CHUNK_LEAF, CHUNK_POSITION = 0, 1
-FLAG_TRACE, FLAG_TIMING, FLAG_SQUARED, FLAG_NO_TAIL = 1, 2, 4, 8
+FLAG_TRACE, FLAG_TIMING, FLAG_SQUARED, FLAG_NO_TAIL, FLAG_DEVICE_BUILD = 1, 2, 4, 8, 16
 MAX_DIM, MAX_K, MAX_HEIGHT = 32, 64, 24
 
 _lib = None

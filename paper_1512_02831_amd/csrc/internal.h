@@ -73,6 +73,8 @@ struct HostTree {
 
 // Build the canonical tree of P (row-major n x d); parallel = use the host thread pool.
 void build_canonical(const float *P, int64_t n, int d, int h, HostTree &t, bool parallel = true);
+// The same tree built on the current device (one segmented sort per level); blocking on s.
+void build_canonical_device(const float *P, int64_t n, int d, int h, HostTree &t, hipStream_t s);
 
 // Leaf-block layout of the leaf structure: leaf l occupies 4-byte words
 // [blk[l], blk[l+1]): d rows of len_l float32 coordinates (row j holds

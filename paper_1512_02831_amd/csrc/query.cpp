@@ -159,7 +159,8 @@ void tree_build(Tree &t, const float *P, int64_t n, int d, int h, const bkd_opti
     if (opt.fetch_size == 0) t.M = t.B > 0 ? 10 * t.B : -1;
     else t.M = opt.fetch_size < 0 ? -1 : opt.fetch_size;
 
-    build_canonical(P, n, d, h, t.host);
+    if (opt.flags & BKD_FLAG_DEVICE_BUILD) build_canonical_device(P, n, d, h, t.host, nullptr);
+    else build_canonical(P, n, d, h, t.host);
     plan_chunks(t);
     t.sweep = !t.resident && t.opt.chunk_mode == BKD_CHUNK_LEAF;
 

@@ -355,3 +355,31 @@ def test_on_device_config_sampled_parity():
     assert np.array_equal(f32_keys(idx[sample], d2[sample]), okeys)
     sub = sample[:200]
     check_fp64(P, Q[sub], idx[sub], np.sqrt(d2[sub]), k)
+
+
+@pytest.mark.parametrize("n,d,h,kind", [
+    (1000, 3, 0, "normal"),
+    (5000, 4, 5, "normal"),
+    (33_333, 10, 9, "normal"),
+    (4096, 2, 12, "normal"),        # leaves of one point
+    (20_000, 5, 7, "duplicates"),   # many equal coordinates: ties by index
+    (6000, 3, 6, "signed_zeros"),   # -0 and +0 compare equal
+])
+def test_device_build_matches_oracle(n, d, h, kind):
+    say(f"case: device build n={n} d={d} h={h} {kind}")
+    rng = np.random.default_rng(n + d + h)
+    P = rng.standard_normal((n, d)).astype(np.float32)
+    if kind == "duplicates":
+        P = np.round(P * 2.0).astype(np.float32)
+    if kind == "signed_zeros":
+        P[rng.random((n, d)) < 0.3] = np.float32(0.0)
+        P[rng.random((n, d)) < 0.3] = np.float32(-0.0)
+    t_or = oracle.build_tree(P, h)
+    with bkd.build(P, h, flags=bkd.FLAG_DEVICE_BUILD | bkd.FLAG_SQUARED) as t:
+        split, leaf_off, perm = bkd.tree_export(t)
+        Q = P[rng.choice(n, 200)] + np.float32(0.01)
+        idx, d2 = bkd.query(t, Q, 5)
+    assert np.array_equal(split.view(np.uint32), t_or.split.view(np.uint32))
+    assert np.array_equal(leaf_off, t_or.leaf_off)
+    assert np.array_equal(perm, t_or.perm)
+    assert np.array_equal(f32_keys(idx, d2), oracle.brute_f32c(P, Q, 5))
