@@ -5,11 +5,14 @@
 // index); the split value is the coordinate of the smallest point on the right,
 // and every leaf keeps its points in ascending index.
 //
-// Every level is one segmented sort of all n points by the 64-bit key
-// (ordered coordinate bits, index), one segment per node: the key is unique,
-// so no stability is assumed of the sort.  The node ranges depend on n and h
-// only and are computed on the host.  A last segmented sort by index orders
-// the leaves.
+// Each point carries the index of its node in the current level.  A level is
+// one stable radix sort of all points, listed in index order, by the key
+// (node, ordered coordinate bits): stability turns equal coordinates into
+// ascending index, and the node ranges come out in place.  One pass over the
+// sorted order then reads the split values and moves every point to its
+// child.  A last stable sort by leaf, again over points in index order, gives
+// each leaf its points in ascending index.  Coordinates are read from a
+// column-major copy of P.
 #include <hipcub/hipcub.hpp>
 
 #include <numeric>
@@ -27,29 +30,42 @@ __device__ inline uint32_t ordered_bits(float x)
     return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
-__global__ void k_level_keys(const float *P, int64_t n, int d, int dim, const uint64_t *prev, uint64_t *keys)
+__global__ void k_columns(const float *P, int64_t n, int d, float *X)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const uint32_t o = prev ? (uint32_t)prev[i] : (uint32_t)i;
-    keys[i] = ((uint64_t)ordered_bits(P[(int64_t)o * d + dim]) << 32) | o;
+    for (int j = 0; j < d; j++) X[(int64_t)j * n + i] = P[i * d + j];
 }
 
-// split value of each node of a level: the coordinate of its point of rank floor(c/2)
-__global__ void k_level_splits(const uint64_t *sorted, const int32_t *off, int count, const float *P, int d, int dim,
-                               float *split)
-{
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= count) return;
-    const int32_t a = off[x], c = off[x + 1] - a;
-    const uint32_t o = (uint32_t)sorted[a + c / 2];
-    split[x] = P[(int64_t)o * d + dim];
-}
-
-__global__ void k_low_words(const uint64_t *keys, int64_t n, uint32_t *idx)
+// keys of the points in index order: (node in this level, ordered coordinate); values: the index
+__global__ void k_node_keys(const float *col, const uint32_t *node, int64_t n, uint64_t *keys, uint32_t *vals)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) idx[i] = (uint32_t)keys[i];
+    if (i >= n) return;
+    keys[i] = ((uint64_t)(node ? node[i] : 0u) << 32) | ordered_bits(col[i]);
+    vals[i] = (uint32_t)i;
+}
+
+// Over the sorted order: node v holds positions [off[v], off[v+1]); its point of
+// rank floor(c/2) gives the split value; the first floor(c/2) go to child 2v.
+__global__ void k_split_children(const uint64_t *keys, const uint32_t *vals, int64_t n, const int32_t *off,
+                                 const float *col, float *split, uint32_t *node)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t v = (uint32_t)(keys[p] >> 32);
+    const int32_t a = off[v], half = (off[v + 1] - a) / 2;
+    const uint32_t o = vals[p];
+    node[o] = 2 * v + ((p - a) >= half ? 1u : 0u);
+    if (p - a == half) split[v] = col[o];
+}
+
+__global__ void k_leaf_keys(const uint32_t *node, int64_t n, uint32_t *keys, uint32_t *vals)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = node[i];
+    vals[i] = (uint32_t)i;
 }
 
 struct Mem {
@@ -95,53 +111,53 @@ void build_canonical_device(const float *P, int64_t n, int d, int h, HostTree &t
         return;
     }
 
-    Mem dP(sizeof(float) * (size_t)n * d), ka(sizeof(uint64_t) * n), kb(sizeof(uint64_t) * n);
-    Mem doff(sizeof(int32_t) * (nleaf + 1)), dsplit(sizeof(float) * std::max<int64_t>(1, nleaf - 1));
-    Mem ia(sizeof(uint32_t) * n), ib(sizeof(uint32_t) * n);
-    BKD_HIP(hipMemcpyAsync(dP.p, P, sizeof(float) * (size_t)n * d, hipMemcpyHostToDevice, s));
-    // temporary storage: the largest of every sort below
-    size_t temp_bytes = 0;
-    for (int l = 0; l < h; l++) {
-        size_t b = 0;
-        BKD_HIP(hipcub::DeviceSegmentedRadixSort::SortKeys(nullptr, b, ka.as<uint64_t>(), kb.as<uint64_t>(), (int)n,
-                                                             1 << l, doff.as<int32_t>(), doff.as<int32_t>() + 1, 0,
-                                                             64, s));
-        temp_bytes = std::max(temp_bytes, b);
-    }
-    {
-        size_t b = 0;
-        BKD_HIP(hipcub::DeviceSegmentedRadixSort::SortKeys(nullptr, b, ia.as<uint32_t>(), ib.as<uint32_t>(), (int)n,
-                                                             (int)nleaf, doff.as<int32_t>(), doff.as<int32_t>() + 1,
-                                                             0, 32, s));
-        temp_bytes = std::max(temp_bytes, b);
-    }
-    Mem temp(temp_bytes);
     const int T = 256;
-    for (int l = 0; l < h; l++) {
-        const int count = 1 << l, dim = l % d;
-        BKD_HIP(hipMemcpyAsync(doff.p, off[(size_t)l].data(), sizeof(int32_t) * (count + 1), hipMemcpyHostToDevice, s));
-        k_level_keys<<<blocks(n, T), T, 0, s>>>(dP.as<float>(), n, d, dim, l ? kb.as<uint64_t>() : nullptr,
-                                                ka.as<uint64_t>());
+    Mem dX(sizeof(float) * (size_t)n * d);
+    {
+        Mem dP(sizeof(float) * (size_t)n * d);
+        BKD_HIP(hipMemcpyAsync(dP.p, P, sizeof(float) * (size_t)n * d, hipMemcpyHostToDevice, s));
+        k_columns<<<blocks(n, T), T, 0, s>>>(dP.as<float>(), n, d, dX.as<float>());
         BKD_HIP(hipGetLastError());
-        size_t b = temp_bytes;
-        BKD_HIP(hipcub::DeviceSegmentedRadixSort::SortKeys(temp.p, b, ka.as<uint64_t>(), kb.as<uint64_t>(), (int)n,
-                                                             count, doff.as<int32_t>(), doff.as<int32_t>() + 1, 0, 64,
-                                                             s));
-        k_level_splits<<<blocks(count, T), T, 0, s>>>(kb.as<uint64_t>(), doff.as<int32_t>(), count, dP.as<float>(),
-                                                      d, dim, dsplit.as<float>() + (count - 1));
-        BKD_HIP(hipGetLastError());
-        // the host range array is reused by the next copy only after this level's kernels ran
         BKD_HIP(hipStreamSynchronize(s));
     }
-    // leaves in ascending index
-    k_low_words<<<blocks(n, T), T, 0, s>>>(kb.as<uint64_t>(), n, ia.as<uint32_t>());
-    BKD_HIP(hipGetLastError());
-    BKD_HIP(hipMemcpyAsync(doff.p, off[(size_t)h].data(), sizeof(int32_t) * (nleaf + 1), hipMemcpyHostToDevice, s));
-    size_t b = temp_bytes;
-    BKD_HIP(hipcub::DeviceSegmentedRadixSort::SortKeys(temp.p, b, ia.as<uint32_t>(), ib.as<uint32_t>(), (int)n,
-                                                         (int)nleaf, doff.as<int32_t>(), doff.as<int32_t>() + 1, 0, 32,
-                                                         s));
-    BKD_HIP(hipMemcpyAsync(t.perm.data(), ib.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    Mem ka(sizeof(uint64_t) * n), kb(sizeof(uint64_t) * n), va(sizeof(uint32_t) * n), vb(sizeof(uint32_t) * n);
+    Mem node(sizeof(uint32_t) * n), doff(sizeof(int32_t) * (nleaf + 1));
+    Mem dsplit(sizeof(float) * std::max<int64_t>(1, nleaf - 1));
+    // temporary storage: the larger of the two sorts' needs
+    size_t temp_bytes = 0, leaf_bytes = 0;
+    BKD_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, ka.as<uint64_t>(), kb.as<uint64_t>(),
+                                               va.as<uint32_t>(), vb.as<uint32_t>(), (int)n, 0, 64, s));
+    BKD_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, leaf_bytes, reinterpret_cast<uint32_t *>(ka.p),
+                                               reinterpret_cast<uint32_t *>(kb.p), va.as<uint32_t>(),
+                                               vb.as<uint32_t>(), (int)n, 0, 32, s));
+    temp_bytes = std::max(temp_bytes, leaf_bytes);
+    Mem temp(temp_bytes);
+    for (int l = 0; l < h; l++) {
+        const int count = 1 << l, dim = l % d;
+        const float *col = dX.as<float>() + (int64_t)dim * n;
+        BKD_HIP(hipMemcpyAsync(doff.p, off[(size_t)l].data(), sizeof(int32_t) * (count + 1), hipMemcpyHostToDevice, s));
+        k_node_keys<<<blocks(n, T), T, 0, s>>>(col, l ? node.as<uint32_t>() : nullptr, n, ka.as<uint64_t>(),
+                                              va.as<uint32_t>());
+        BKD_HIP(hipGetLastError());
+        size_t b = temp_bytes;
+        BKD_HIP(hipcub::DeviceRadixSort::SortPairs(temp.p, b, ka.as<uint64_t>(), kb.as<uint64_t>(), va.as<uint32_t>(),
+                                                   vb.as<uint32_t>(), (int)n, 0, 32 + l, s));
+        k_split_children<<<blocks(n, T), T, 0, s>>>(kb.as<uint64_t>(), vb.as<uint32_t>(), n, doff.as<int32_t>(), col,
+                                                     dsplit.as<float>() + (count - 1), node.as<uint32_t>());
+        BKD_HIP(hipGetLastError());
+        // the host range array of this level is read by the copy above until the stream gets here
+        BKD_HIP(hipStreamSynchronize(s));
+    }
+    // leaves in ascending index: a stable sort by leaf of the points in index order
+    {
+        uint32_t *keys = reinterpret_cast<uint32_t *>(ka.p), *keys_out = reinterpret_cast<uint32_t *>(kb.p);
+        k_leaf_keys<<<blocks(n, T), T, 0, s>>>(node.as<uint32_t>(), n, keys, va.as<uint32_t>());
+        BKD_HIP(hipGetLastError());
+        size_t b = temp_bytes;
+        BKD_HIP(hipcub::DeviceRadixSort::SortPairs(temp.p, b, keys, keys_out, va.as<uint32_t>(), vb.as<uint32_t>(),
+                                                   (int)n, 0, std::max(1, h), s));
+    }
+    BKD_HIP(hipMemcpyAsync(t.perm.data(), vb.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
     BKD_HIP(hipMemcpyAsync(t.split.data(), dsplit.p, sizeof(float) * (nleaf - 1), hipMemcpyDeviceToHost, s));
     BKD_HIP(hipStreamSynchronize(s));
 }
