@@ -134,7 +134,7 @@ typedef struct bkd_stats {
     int64_t chunk_copies;   /* host-to-device chunk copies                        */
     int64_t bytes_h2d;      /* bytes of those copies                              */
     double dense_ms;        /* sum of dense-scan launch durations (BKD_FLAG_TIMING)  */
-    double sparse_ms;       /* sum of sparse-scan launch durations (BKD_FLAG_TIMING) */
+    double sparse_ms;       /* sum of sparse-scan and tail launch durations (BKD_FLAG_TIMING) */
     double total_ms;        /* wall time of the query call on the host            */
 } bkd_stats;
 
