@@ -341,6 +341,10 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
         }
         pre_o = *reinterpret_cast<const int32_t *>(at(orig, (uint32_t)i * 4u));
     };
+    // Every load issued so far (the query, its list) is complete here: without this
+    // the compiler keeps a wait for them inside the re-check path, which then also
+    // waits for the next tile's loads.
+    __builtin_amdgcn_s_waitcnt(0);
     load_tile(p0);
     for (int64_t pt = p0; pt < p1; pt += PT) {
         const int np = (int)min((int64_t)PT, p1 - pt);
