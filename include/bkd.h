@@ -59,8 +59,9 @@ extern "C" {
 #define BKD_FLAG_SQUARED 4 /* out_dist receives the float32 squared distance, not its root      */
 #define BKD_FLAG_NO_TAIL 8 /* lock-step rounds to the end: no hand-over of the last few pending  */
                            /* queries to one-workgroup-per-query traversals (results identical)  */
-#define BKD_FLAG_DEVICE_BUILD 16 /* build the top tree on the device: one segmented sort per level    */
-                                 /* (the same canonical tree as the host build, Section 2.3)       */
+#define BKD_FLAG_DEVICE_BUILD 16 /* build the top tree on the device: one stable radix sort per     */
+                                 /* level (the same canonical tree as the host build, Section 2.3); */
+                                 /* needs about 8d + 32 bytes of device memory per point meanwhile  */
 
 typedef struct bkd_tree bkd_tree;
 
