@@ -35,6 +35,7 @@ def planted(n, d, seed):
     (1 << 14, 10, 6, 10, {}),
     (20000, 5, 7, 5, {"flags": bkd.FLAG_SQUARED}),
     (1 << 14, 10, 6, 10, {"leaf_budget_bytes": 200_000}),
+    (3000, 3, 4, 63, {}),  # the largest k: 64 nearest per point
 ])
 def test_outlier_scores_match_oracle(n, d, h, k, opts):
     say(f"outliers n={n} d={d} h={h} k={k} opts={opts}")

@@ -364,6 +364,7 @@ def test_on_device_config_sampled_parity():
     (4096, 2, 12, "normal"),        # leaves of one point
     (20_000, 5, 7, "duplicates"),   # many equal coordinates: ties by index
     (6000, 3, 6, "signed_zeros"),   # -0 and +0 compare equal
+    (1 << 20, 10, 13, "normal"),    # node keys of 13 bits: more radix passes
 ])
 def test_device_build_matches_oracle(n, d, h, kind):
     say(f"case: device build n={n} d={d} h={h} {kind}")
