@@ -47,19 +47,31 @@ WORKLOADS = {
 }
 
 
-def dense_scan_traffic(kernel_src="paper_1512_02831_amd/csrc/leaf_scan.h",
-                       summary="profiles/k_leaf_scan_ondevice_n2p22.md"):
-    """HBM bytes per dense-scan launch from the committed FETCH_SIZE/WRITE_SIZE summary, or None
-    when the kernel source has changed since those counters were taken."""
+KERNEL_FILES = ("paper_1512_02831_amd/csrc/leaf_scan.h", "paper_1512_02831_amd/csrc/scan_inst.h",
+                "paper_1512_02831_amd/compile.py")
+
+
+def kernel_source_hash():
+    """sha256 over the dense scan's source, its instantiation macros and the compile flags."""
     import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_FILES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def dense_scan_traffic(summary="profiles/k_leaf_scan_ondevice_n2p22.md"):
+    """HBM bytes per dense-scan launch from the committed FETCH_SIZE/WRITE_SIZE summary, or None
+    when the kernel's source or build flags have changed since those counters were taken."""
     try:
         text = open(os.path.join(ROOT, summary)).read()
-        src = open(os.path.join(ROOT, kernel_src), "rb").read()
+        digest = kernel_source_hash()
     except OSError:
         return None
     fields = dict(line.split(":", 1) for line in text.splitlines()
                   if line.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
-    if "source_sha256" not in fields or fields["source_sha256"].split()[0] != hashlib.sha256(src).hexdigest():
+    if "source_sha256" not in fields or fields["source_sha256"].split()[0] != digest:
         return None
     return int(fields["traffic_bytes_per_launch"])
 

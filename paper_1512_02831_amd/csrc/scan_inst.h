@@ -2,6 +2,22 @@
 #pragma once
 #include "leaf_scan.h"
 
+// The dense scan's instantiations live in files of their own (scan_dense_*.hip),
+// compiled with the instruction-level-parallelism scheduler; the files that
+// launch them only declare them.
+#define BKD_SCAN_DENSE_EACH(D, X)                                                                   \
+    X template __global__ void k_leaf_scan<D, 1>(ScanArgs);                                         \
+    X template __global__ void k_leaf_scan<D, 2>(ScanArgs);                                         \
+    X template __global__ void k_leaf_scan<D, 4>(ScanArgs);                                         \
+    X template __global__ void k_leaf_scan<D, 5>(ScanArgs);                                         \
+    X template __global__ void k_leaf_scan<D, 8>(ScanArgs);                                         \
+    X template __global__ void k_leaf_scan<D, 10>(ScanArgs);                                        \
+    X template __global__ void k_leaf_scan<D, 16>(ScanArgs);                                        \
+    X template __global__ void k_leaf_scan<D, 32>(ScanArgs);                                        \
+    X template __global__ void k_leaf_scan<D, 64>(ScanArgs);
+#define BKD_SCAN_DENSE_EXTERN(D) BKD_SCAN_DENSE_EACH(D, extern)
+#define BKD_SCAN_DENSE_INSTANTIATE(D) BKD_SCAN_DENSE_EACH(D, )
+
 #define BKD_SCAN_CASE(D, KK)                                                                        \
     case KK:                                                                                        \
         if (!sparse && a.item_count > 0) k_leaf_scan<D, KK><<<grid, SCAN_THREADS, 0, s>>>(a);      \
