@@ -384,10 +384,14 @@ class Request:
 
 
 class Server:
-    """Handle of ``bkd_server_create``; keeps served trees and request arrays alive."""
+    """Handle of ``bkd_server_create``.  It keeps the served trees alive, and every
+    submitted request's arrays (queries, idx and dist outputs, which the library
+    writes when the request completes) until ``release`` or ``destroy``: a caller may
+    drop a request handle, or cancel a running request, without the library writing
+    into freed memory."""
 
     def __init__(self, handle):
-        self._h, self.trees = handle, []
+        self._h, self.trees, self.requests = handle, [], {}
 
     @property
     def handle(self):
@@ -395,10 +399,16 @@ class Server:
             raise ValueError("server has been destroyed")
         return self._h
 
+    def request(self, rid: int) -> Request:
+        """The live request with id ``rid`` (submitted and not yet released)."""
+        return self.requests[rid]
+
     def destroy(self):
         if self._h:
             _check(lib().bkd_server_destroy(self._h))
             self._h = None
+        # the library no longer writes to any request's arrays
+        self.requests.clear()
 
     def __del__(self):
         try:
@@ -434,22 +444,31 @@ def submit(srv: Server, tree_id: int, Q, k: int) -> Request:
     dist = np.zeros((m, k), dtype=np.float32)
     rid = ctypes.c_int64()
     _check(lib().bkd_submit(srv.handle, tree_id, _p(Q), m, k, _p(idx), _p(dist), ctypes.byref(rid)))
-    return Request(rid.value, Q, idx, dist)
+    req = Request(rid.value, Q, idx, dist)
+    srv.requests[req.id] = req
+    return req
 
 
-def wait(srv: Server, req: Request, timeout_us: int = -1):
-    _check(lib().bkd_wait(srv.handle, req.id, timeout_us))
-    return req.idx, req.dist
+def _rid(req) -> int:
+    return req.id if isinstance(req, Request) else int(req)
 
 
-def poll(srv: Server, req: Request) -> int:
+def wait(srv: Server, req, timeout_us: int = -1):
+    """Block until the request (a Request or its id) is done; returns its (idx, dist)."""
+    rid = _rid(req)
+    _check(lib().bkd_wait(srv.handle, rid, timeout_us))
+    r = srv.requests[rid]
+    return r.idx, r.dist
+
+
+def poll(srv: Server, req) -> int:
     st = ctypes.c_int32()
-    _check(lib().bkd_poll(srv.handle, req.id, ctypes.byref(st)))
+    _check(lib().bkd_poll(srv.handle, _rid(req), ctypes.byref(st)))
     return st.value
 
 
-def cancel(srv: Server, req: Request):
-    _check(lib().bkd_cancel(srv.handle, req.id))
+def cancel(srv: Server, req):
+    _check(lib().bkd_cancel(srv.handle, _rid(req)))
 
 
 class ServerStats(ctypes.Structure):
@@ -465,11 +484,14 @@ def server_stats(srv: Server) -> dict:
     return {f: getattr(st, f) for f, _ in ServerStats._fields_}
 
 
-def request_times(srv: Server, req: Request):
+def request_times(srv: Server, req):
     a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-    _check(lib().bkd_request_times(srv.handle, req.id, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    _check(lib().bkd_request_times(srv.handle, _rid(req), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
     return a.value, b.value, c.value
 
 
-def release(srv: Server, req: Request):
-    _check(lib().bkd_release(srv.handle, req.id))
+def release(srv: Server, req):
+    """Forget a finished request; its arrays are no longer kept by the server."""
+    rid = _rid(req)
+    _check(lib().bkd_release(srv.handle, rid))
+    srv.requests.pop(rid, None)

@@ -343,7 +343,7 @@ template <int D, int G> __device__ __forceinline__ void scan_leaves(const BatchA
                 const int p = gb + 64 * g + lane;
                 v[g] = p < len;
 #pragma unroll
-                for (int j = 0; j < D; j++) x[g][j] = (v[g] && j < d) ? X[j * len + p] : 0.0f;
+                for (int j = 0; j < D; j++) x[g][j] = (v[g] && j < d) ? X[(int64_t)j * len + p] : 0.0f;
                 o[g] = v[g] ? (uint32_t)orig[p] : 0u;
             }
             // The leaf's buffered queries, 64 ids at a time in the lanes.  Each query's
@@ -478,7 +478,7 @@ __device__ __forceinline__ void tail_queries(const BatchArgs &a, int i, int j0, 
                     float acc = 0.0f;
 #pragma unroll
                     for (int c = 0; c < D; c++) {
-                        const float x = X[(c < d ? c : 0) * len + pi];
+                        const float x = X[(int64_t)(c < d ? c : 0) * len + pi];
                         const float tt = qv[c] - (c < d ? x : 0.0f);
                         acc = fmaf(tt, tt, acc);
                     }

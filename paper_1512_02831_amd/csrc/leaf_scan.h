@@ -311,35 +311,35 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
 
     // Staging: thread t brings point t of a tile; the next tile's coordinates
     // are loaded into registers while the current tile is scanned.
-    const int first_pt = (int)(p0 - l0);  // a valid point of this item (clamped loads stay in the chunk)
     float pre[DS], cr[DS];
     int32_t pre_o = 0;
 #pragma unroll
     for (int j = 0; j < DS; j++) cr[j] = (j < a.d) ? cen[j] : 0.0f;
-    // A column base (uniform) plus one 32-bit byte offset per thread: the loads
-    // take the scalar-base form, so the scan below never has to wait for them
-    // before reusing an address register.
+    // A uniform base (the tile's first point in each row, 64-bit) plus one small
+    // 32-bit byte offset per thread: the loads take the scalar-base form, so the
+    // scan below never has to wait for them before reusing an address register,
+    // and no per-thread offset grows with the leaf.
     auto at = [](const void *base, uint32_t bo) {
         return reinterpret_cast<const char *>(base) + bo;
     };
     auto load_tile = [&](int64_t pt) {
         if (PT < SCAN_THREADS && tid >= PT) return;
         const int np = (int)min((int64_t)PT, p1 - pt);
-        // rows past the tile load a valid point of the item; they are never read as points
-        const int i = tid < np ? (int)(pt - l0) + tid : first_pt;
+        // rows past the tile load the tile's first point (valid in the chunk); they are never read as points
+        const uint32_t bo = (uint32_t)(tid < np ? tid : 0) * 4u;
+        const float *Xt = X + (pt - l0);
         if (a.d == D) {
-            const uint32_t bo = (uint32_t)i * 4u;
 #pragma unroll
             for (int j = 0; j < DS; j++)
-                pre[j] = (j < D) ? *reinterpret_cast<const float *>(at(X + (int64_t)(j < D ? j : 0) * len, bo)) : 0.0f;
+                pre[j] = (j < D) ? *reinterpret_cast<const float *>(at(Xt + (int64_t)(j < D ? j : 0) * len, bo)) : 0.0f;
         } else {
 #pragma unroll
             for (int j = 0; j < DS; j++) {
-                const float x = X[(j < a.d ? j : 0) * len + i];
+                const float x = *reinterpret_cast<const float *>(at(Xt + (int64_t)(j < a.d ? j : 0) * len, bo));
                 pre[j] = (j < a.d) ? x : 0.0f;
             }
         }
-        pre_o = *reinterpret_cast<const int32_t *>(at(orig, (uint32_t)i * 4u));
+        pre_o = *reinterpret_cast<const int32_t *>(at(orig + (pt - l0), bo));
     };
     // Every load issued so far (the query, its list) is complete here: without this
     // the compiler keeps a wait for them inside the re-check path, which then also
@@ -517,7 +517,7 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
             valid[u] = p < p1;
             const int i = valid[u] ? (int)(p - l0) : i_first;
 #pragma unroll
-            for (int j = 0; j < D; j++) x[u][j] = X[(j < a.d ? j : 0) * len + i];
+            for (int j = 0; j < D; j++) x[u][j] = X[(int64_t)(j < a.d ? j : 0) * len + i];
             o[u] = orig[i];
         }
         uint64_t key[U];
@@ -637,7 +637,7 @@ template <int D, int K, int TT> __global__ __launch_bounds__(TT) void k_tail(Sca
                 valid[u] = p < hi;
                 const int i = valid[u] ? p : lo;
 #pragma unroll
-                for (int j = 0; j < D; j++) x[u][j] = X[(j < a.d ? j : 0) * len + i];
+                for (int j = 0; j < D; j++) x[u][j] = X[(int64_t)(j < a.d ? j : 0) * len + i];
                 o[u] = orig[i];
             }
 #pragma unroll

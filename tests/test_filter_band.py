@@ -18,8 +18,10 @@ modelled at its worst (2^-21 relative low, zero below 2^-126).  The claim:
 every pair whose float32 distance (the oracle's arithmetic) is at most thr
 passes.  These tests emulate every rounding
 exactly with rationals, float16 rounding to nearest even, toward zero, or
-with subnormals flushed, at thresholds equal to the pair's own distance and
-one ulp either side, and check the claim; a negative control shows that the
+with subnormals flushed, float32 accumulation in random orders and in the
+matrix cores' steps of sixteen products (one step at d <= 14, two or three at
+d = 15..32), at thresholds equal to the pair's own distance and one ulp
+either side, and check the claim; a negative control shows that the
 widening delta is needed.  The GPU parity tests check that results stay
 bit-identical.
 """
@@ -28,6 +30,7 @@ from __future__ import annotations
 from fractions import Fraction as F
 
 import numpy as np
+import pytest
 
 from tests.exact_ref import round_f32
 
@@ -113,6 +116,22 @@ def filter_margin(q, x, c, e, thr: F, rng, mode: str, widen: bool = True):
                 acc = rnd(acc + prods[o])
             m = acc - aq
             worst = m if worst is None else min(worst, m)
+        # the matrix cores take the products in steps of sixteen (operand order); within a
+        # step the sum may be formed in any order or with a single rounding, and each
+        # step's result is added to the running float32 accumulator
+        steps = [prods[i:i + 16] for i in range(0, len(prods), 16)]
+        for single in (True, False):
+            acc = F(0)
+            for st in steps:
+                if single:
+                    acc = rnd(acc + sum(st, F(0)))
+                else:
+                    part = F(0)
+                    for o in rng.permutation(len(st)):
+                        part = rnd(part + st[o])
+                    acc = rnd(acc + part)
+            m = acc - aq
+            worst = min(worst, m)
     return worst, d2
 
 
@@ -125,11 +144,17 @@ def scale_exponent(ext: float) -> int:
     return int(np.ceil(np.log2(ext)))
 
 
-def test_scaled_f16_band_random():
-    rng = np.random.default_rng(1)
+# one matrix-core step of sixteen products (d <= 14), and two or three steps (d >= 15)
+ONE_STEP_DIMS = [3, 5, 10, 14]
+MULTI_STEP_DIMS = [15, 16, 20, 24, 32]
+
+
+@pytest.mark.parametrize("dims,seed", [(ONE_STEP_DIMS, 1), (MULTI_STEP_DIMS, 11)])
+def test_scaled_f16_band_random(dims, seed):
+    rng = np.random.default_rng(seed)
     cases = 0
     for _ in range(120):
-        d = int(rng.choice([3, 5, 10, 14]))
+        d = int(rng.choice(dims))
         cen = rng.uniform(-20, 20, d).astype(np.float32)
         ext = float(rng.choice([1e-3, 0.5, 3.0, 50.0]))
         e = scale_exponent(ext)
@@ -144,10 +169,11 @@ def test_scaled_f16_band_random():
     assert cases > 500
 
 
-def test_scaled_f16_band_adversarial():
-    rng = np.random.default_rng(2)
+@pytest.mark.parametrize("dims,seed", [([3, 10, 14], 2), (MULTI_STEP_DIMS, 12)])
+def test_scaled_f16_band_adversarial(dims, seed):
+    rng = np.random.default_rng(seed)
     for _ in range(60):
-        d = int(rng.choice([3, 10, 14]))
+        d = int(rng.choice(dims))
         cen = rng.uniform(-1e3, 1e3, d).astype(np.float32)
         ext = float(rng.choice([1e-30, 1e-6, 1.0, 1e4]))
         e = scale_exponent(ext)
@@ -164,12 +190,12 @@ def test_scaled_f16_band_adversarial():
                         assert m >= 0
 
 
-def test_scaled_f16_band_needs_the_widening():
+@pytest.mark.parametrize("d", [10, 20])
+def test_scaled_f16_band_needs_the_widening(d):
     """Negative control: with delta = 0 some pair at its own threshold is dropped."""
     rng = np.random.default_rng(3)
     broke = False
     for _ in range(60):
-        d = 10
         cen = rng.uniform(-5, 5, d).astype(np.float32)
         x = (cen + rng.uniform(-1, 1, d) * np.float32(0.999)).astype(np.float32)
         q = (cen + rng.normal(0, 1.0, d)).astype(np.float32)
