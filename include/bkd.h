@@ -137,6 +137,24 @@ typedef struct bkd_stats {
     double dense_ms;        /* sum of dense-scan launch durations (BKD_FLAG_TIMING)  */
     double sparse_ms;       /* sum of sparse-scan and tail launch durations (BKD_FLAG_TIMING) */
     double total_ms;        /* wall time of the query call on the host            */
+    /* Algorithmic work.  A ProcessAllBuffers call reads every buffered leaf once    */
+    /* (4d + 4 bytes per point: coordinates and index) and, per buffered query, its  */
+    /* coordinates, its key list (read and written, 8 bytes per key each way) and    */
+    /* its buffer entry: 4d + 16k + 4 bytes per visit.  A tail visit reads its leaf  */
+    /* for its one query.                                                            */
+    int64_t dense_visits;       /* visits scanned by the dense leaf scan              */
+    int64_t leaf_points_dense;  /* points of the leaves the dense scan read, per call */
+    int64_t leaf_points_other;  /* the same for the sparse scan and the tail          */
+    int64_t alg_bytes;          /* leaf points (4d + 4) + visits (4d + 16k + 4)       */
+    int64_t alg_bytes_dense;    /* the dense scan's part of alg_bytes                 */
+    /* Phases (device time from HIP events with BKD_FLAG_TIMING, else 0).           */
+    double find_ms;         /* FindLeafBatch launches (first round; routing inside   */
+                            /* the scans of later rounds is part of the scans' time) */
+    double group_ms;        /* buffer insertion: grouping by leaf, offsets, chunk      */
+                            /* sweep redistribution                                   */
+    double copy_ms;         /* host-to-device chunk copies (streamed structures)     */
+    double wait_ms;         /* host time spent waiting for the device (readbacks and */
+                            /* synchronisations inside the call), always measured     */
 } bkd_stats;
 
 /* Thread-local description of the last error on this thread ("" if none). */

@@ -72,18 +72,51 @@ typedef struct {
     int32_t i;
 } vi_t;
 
-static int cmp_vi(const void *a, const void *b)
-{
-    const vi_t *x = (const vi_t *)a, *y = (const vi_t *)b;
-    if (x->v < y->v) return -1;
-    if (x->v > y->v) return 1;
-    return (x->i > y->i) - (x->i < y->i);
-}
-
 static int cmp_i32(const void *a, const void *b)
 {
     int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
     return (x > y) - (x < y);
+}
+
+static int less_vi(const vi_t *x, const vi_t *y)
+{
+    return x->v < y->v || (x->v == y->v && x->i < y->i);
+}
+
+/*
+ * Selection of rank r under the total order (value, index) (Hoare's FIND):
+ * afterwards a[r] is the element of rank r, every element before it is
+ * smaller and every element after it larger.  Only which elements land on
+ * either side matters to the build, and that is fixed by the order alone, so
+ * any exact selection gives the same tree (the paper's host build uses
+ * linear-time median selection).  The pivot position is drawn from a
+ * fixed-seed generator, so the expected cost is linear for every input.
+ */
+static void select_vi(vi_t *a, int64_t c, int64_t r)
+{
+    int64_t lo = 0, hi = c - 1;
+    uint64_t state = 0x9E3779B97F4A7C15ull ^ (uint64_t)c;
+    while (lo < hi) {
+        state = state * 6364136223846793005ull + 1442695040888963407ull;
+        const int64_t pi = lo + (int64_t)((state >> 33) % (uint64_t)(hi - lo + 1));
+        const vi_t pv = a[pi];
+        a[pi] = a[hi];
+        a[hi] = pv;
+        int64_t store = lo;
+        for (int64_t i = lo; i < hi; i++) {
+            if (less_vi(&a[i], &pv)) {
+                const vi_t t = a[i];
+                a[i] = a[store];
+                a[store] = t;
+                store++;
+            }
+        }
+        a[hi] = a[store];
+        a[store] = pv;
+        if (store == r) return;
+        if (store < r) lo = store + 1;
+        else hi = store - 1;
+    }
 }
 
 static int level_of(int64_t v)
@@ -124,9 +157,11 @@ int orc_build(const float *P, int64_t n, int32_t d, int32_t h, float *split, int
                 tmp[i].i = perm[a + i];
                 tmp[i].v = P[(int64_t)tmp[i].i * d + dim];
             }
-            qsort(tmp, (size_t)c, sizeof(vi_t), cmp_vi);
-            for (int64_t i = 0; i < c; i++) perm[a + i] = tmp[i].i;
+            /* the left child takes the floor(c/2) smallest; the split value is the
+               smallest value on the right */
             int64_t nl = c / 2;
+            select_vi(tmp, c, nl);
+            for (int64_t i = 0; i < c; i++) perm[a + i] = tmp[i].i;
             split[v] = tmp[nl].v;
             lo[2 * v + 1] = a;
             hi[2 * v + 1] = a + nl;

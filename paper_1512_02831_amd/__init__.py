@@ -50,7 +50,11 @@ class Stats(ctypes.Structure):
                 ("pairs", ctypes.c_int64), ("visits", ctypes.c_int64), ("dense_launches", ctypes.c_int64),
                 ("dense_pairs", ctypes.c_int64), ("sparse_launches", ctypes.c_int64),
                 ("sparse_pairs", ctypes.c_int64), ("chunk_copies", ctypes.c_int64), ("bytes_h2d", ctypes.c_int64),
-                ("dense_ms", ctypes.c_double), ("sparse_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+                ("dense_ms", ctypes.c_double), ("sparse_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("dense_visits", ctypes.c_int64), ("leaf_points_dense", ctypes.c_int64),
+                ("leaf_points_other", ctypes.c_int64), ("alg_bytes", ctypes.c_int64),
+                ("alg_bytes_dense", ctypes.c_int64), ("find_ms", ctypes.c_double), ("group_ms", ctypes.c_double),
+                ("copy_ms", ctypes.c_double), ("wait_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -100,7 +100,10 @@ enum Ctl : int {
     CTL_VISITS_LO = 6, // 64-bit counters (two words each)
     CTL_DPAIRS_LO = 8,
     CTL_SPAIRS_LO = 10,
-    CTL_WORDS = 16
+    CTL_LPD_LO = 12,     // points of the leaves scanned densely, each leaf once per call
+    CTL_LPS_LO = 14,     // points of the leaves scanned sparsely, and the tail's leaf reads
+    CTL_DVISITS_LO = 16, // visits scanned densely
+    CTL_WORDS = 24
 };
 
 // Query-tile width of the dense leaf scan (queries per work item), and the
@@ -275,7 +278,33 @@ int key_capacity(int k);
 
 void tree_build(Tree &t, const float *P, int64_t n, int d, int h, const bkd_options &opt);
 int guarded_call(const std::function<void()> &f);
-void tree_query_device(Tree &t, const float *dQ, int64_t m, int k, int64_t *d_idx, float *d_dist, hipStream_t s);
+
+// Device workspace of one query call on a resident structure: key lists,
+// traversal state, the reinsert ring, the two pending-pair buffers, grouping
+// scratch, per-leaf counts and offsets, and the renumbered query copy.
+struct Workspace {
+    uint64_t *keys;
+    uint32_t *kth;
+    int32_t *node, *ring;
+    uint32_t *pleaf, *tleaf;
+    int32_t *pq, *tq;
+    uint32_t *hist;
+    int32_t *cnt, *cnt0, *off, *tiles;
+    float *Qp;
+    int32_t *perm;
+};
+
+// Bytes of that workspace for m queries with k neighbours on tree t (each array
+// 256-byte aligned), and its layout inside a caller-provided region.
+size_t workspace_bytes(const Tree &t, int64_t m, int k);
+Workspace workspace_in(const Tree &t, int64_t m, int k, void *region);
+
+// One query call.  region == nullptr: the tree's own workspace, grown on demand.
+// Otherwise the call uses `region` (workspace_bytes(t, m, k) bytes of device
+// memory) and allocates nothing: the structure must be resident, and neither
+// the trace nor per-launch timing is recorded.
+void tree_query_device(Tree &t, const float *dQ, int64_t m, int k, int64_t *d_idx, float *d_dist, hipStream_t s,
+                       void *region = nullptr);
 
 }  // namespace bkd
 

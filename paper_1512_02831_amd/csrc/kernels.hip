@@ -345,22 +345,31 @@ __global__ __launch_bounds__(1024) void k_leaf_offsets(const int32_t *__restrict
                                                        int32_t *__restrict__ tiles, int32_t *__restrict__ sparse,
                                                        int32_t *__restrict__ ctl, int count_work)
 {
-    __shared__ long long wsum[16][5], wpre[16][3], wtot[5];
+    // columns: buffered entries, dense items, sparse items (prefix sums); then the work of a
+    // full scan: dense pairs, sparse pairs, points of the dense leaves, points of the sparse
+    // leaves, dense visits (totals)
+    constexpr int NC = 8;
+    __shared__ long long wsum[16][NC], wpre[16][3], wtot[NC];
     const int tid = threadIdx.x;
     const int seg = (nleaf + 1023) / 1024;
     const int lo = min(nleaf, tid * seg), hi = min(nleaf, lo + seg);
-    long long sc = 0, st = 0, ss = 0, pd = 0, ps = 0;
+    long long sc = 0, st = 0, ss = 0;
+    long long red[5] = {0, 0, 0, 0, 0};
     // count of leaf l: cnt[l], or end - start of its run when start is given
     for (int l = lo; l < hi; l++) {
         int c = cnt[l] - (start ? start[l] : 0);
-        const long long pr = (long long)c * (leaf_off[l + 1] - leaf_off[l]);
+        const int len = leaf_off[l + 1] - leaf_off[l];
+        const long long pr = (long long)c * len;
         sc += c;
         if (c >= dense_min) {
             st += (c + qt - 1) / qt;
-            pd += pr;
+            red[0] += pr;
+            red[2] += len;
+            red[4] += c;
         } else {
             ss += c;
-            ps += pr;
+            red[1] += pr;
+            if (c > 0) red[3] += len;
         }
     }
     // one pass: inclusive sums of the three running counts within each wave
@@ -368,7 +377,6 @@ __global__ __launch_bounds__(1024) void k_leaf_offsets(const int32_t *__restrict
     // into per-wave prefixes and the block totals
     const int lane = tid & 63, wave = tid >> 6;
     int32_t inc[3] = {(int32_t)sc, (int32_t)st, (int32_t)ss};
-    long long red[2] = {pd, ps};
     for (int o = 1; o < 64; o <<= 1) {
 #pragma unroll
         for (int i = 0; i < 3; i++) {
@@ -378,8 +386,8 @@ __global__ __launch_bounds__(1024) void k_leaf_offsets(const int32_t *__restrict
     }
     if (count_work) {
         for (int o = 32; o > 0; o >>= 1) {
-            red[0] += __shfl_xor(red[0], o);
-            red[1] += __shfl_xor(red[1], o);
+#pragma unroll
+            for (int i = 0; i < 5; i++) red[i] += __shfl_xor(red[i], o);
         }
     }
     if (lane == 63) {
@@ -388,12 +396,12 @@ __global__ __launch_bounds__(1024) void k_leaf_offsets(const int32_t *__restrict
         wsum[wave][2] = inc[2];
     }
     if (lane == 0) {
-        wsum[wave][3] = red[0];
-        wsum[wave][4] = red[1];
+#pragma unroll
+        for (int i = 0; i < 5; i++) wsum[wave][3 + i] = red[i];
     }
     __syncthreads();
-    if (tid < 5) {
-        // column tid: exclusive prefix over the waves (counts) or the total (pairs)
+    if (tid < NC) {
+        // column tid: exclusive prefix over the waves (counts) or the total (work)
         long long run = 0;
         for (int w = 0; w < 16; w++) {
             const long long v = wsum[w][tid];
@@ -406,10 +414,16 @@ __global__ __launch_bounds__(1024) void k_leaf_offsets(const int32_t *__restrict
     long long rc = wpre[wave][0] + inc[0] - sc, rt = wpre[wave][1] + inc[1] - st, rs = wpre[wave][2] + inc[2] - ss;
     const long long tc = wtot[0], tt = wtot[1], ts = wtot[2];
     if (count_work && tid == 0) {
-        // visits and pairs of a full scan of these buffers (as k_count_work does)
-        if (tc) atomicAdd((unsigned long long *)(ctl + CTL_VISITS_LO), (unsigned long long)tc);
-        if (wtot[3]) atomicAdd((unsigned long long *)(ctl + CTL_DPAIRS_LO), (unsigned long long)wtot[3]);
-        if (wtot[4]) atomicAdd((unsigned long long *)(ctl + CTL_SPAIRS_LO), (unsigned long long)wtot[4]);
+        // visits, pairs and leaf points of a full scan of these buffers (as k_count_work does)
+        auto add = [&](int w, long long v) {
+            if (v) atomicAdd((unsigned long long *)(ctl + w), (unsigned long long)v);
+        };
+        add(CTL_VISITS_LO, tc);
+        add(CTL_DPAIRS_LO, wtot[3]);
+        add(CTL_SPAIRS_LO, wtot[4]);
+        add(CTL_LPD_LO, wtot[5]);
+        add(CTL_LPS_LO, wtot[6]);
+        add(CTL_DVISITS_LO, wtot[7]);
     }
     for (int l = lo; l < hi; l++) {
         int c = cnt[l] - (start ? start[l] : 0);
@@ -435,23 +449,30 @@ __global__ __launch_bounds__(256) void k_count_work(const int32_t *__restrict__ 
                                                     const int32_t *__restrict__ leaf_off, int lf, int ll,
                                                     int dense_min, int32_t *__restrict__ ctl)
 {
-    long long v = 0, pd = 0, ps = 0;
+    long long w[6] = {0, 0, 0, 0, 0, 0};  // visits, dense pairs, sparse pairs, dense / sparse leaf points, dense visits
     for (int l = lf + threadIdx.x; l <= ll; l += blockDim.x) {
         const int c = off[l + 1] - off[l];
-        const long long pr = (long long)c * (leaf_off[l + 1] - leaf_off[l]);
-        v += c;
-        if (c >= dense_min) pd += pr;
-        else ps += pr;
+        const int len = leaf_off[l + 1] - leaf_off[l];
+        const long long pr = (long long)c * len;
+        w[0] += c;
+        if (c >= dense_min) {
+            w[1] += pr;
+            w[3] += len;
+            w[5] += c;
+        } else {
+            w[2] += pr;
+            if (c > 0) w[4] += len;
+        }
     }
     for (int o = 32; o > 0; o >>= 1) {
-        v += __shfl_xor(v, o);
-        pd += __shfl_xor(pd, o);
-        ps += __shfl_xor(ps, o);
+#pragma unroll
+        for (int i = 0; i < 6; i++) w[i] += __shfl_xor(w[i], o);
     }
     if (__lane_id() == 0) {
-        if (v) atomicAdd((unsigned long long *)(ctl + CTL_VISITS_LO), (unsigned long long)v);
-        if (pd) atomicAdd((unsigned long long *)(ctl + CTL_DPAIRS_LO), (unsigned long long)pd);
-        if (ps) atomicAdd((unsigned long long *)(ctl + CTL_SPAIRS_LO), (unsigned long long)ps);
+        const int word[6] = {CTL_VISITS_LO, CTL_DPAIRS_LO, CTL_SPAIRS_LO, CTL_LPD_LO, CTL_LPS_LO, CTL_DVISITS_LO};
+#pragma unroll
+        for (int i = 0; i < 6; i++)
+            if (w[i]) atomicAdd((unsigned long long *)(ctl + word[i]), (unsigned long long)w[i]);
     }
 }
 

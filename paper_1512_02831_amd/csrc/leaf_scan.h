@@ -703,6 +703,8 @@ template <int D, int K, int TT> __global__ __launch_bounds__(TT) void k_tail(Sca
         }
         atomicAdd((unsigned long long *)(a.ctl + CTL_VISITS_LO), (unsigned long long)visits);
         atomicAdd((unsigned long long *)(a.ctl + CTL_SPAIRS_LO), (unsigned long long)pairs);
+        // each tail visit reads its leaf for one query: its points count as leaf reads
+        atomicAdd((unsigned long long *)(a.ctl + CTL_LPS_LO), (unsigned long long)pairs);
     }
 }
 

@@ -296,35 +296,24 @@ struct Run {
     int32_t *qbuf[2];
     int cur = 0;  // pair holding the pending list
     const int32_t *bufq_override = nullptr;  // scan input other than the pending pair (chunk sweep)
-    Timer tdense, tsparse;
+    Timer tdense, tsparse, tfind, tgroup, tcopy;
+    double wait_ms = 0;  // host time spent waiting for the device
     std::vector<int32_t> tr_q, tr_l;
+    Workspace ws;
 
-    Run(Tree &t_, hipStream_t s_, const float *dQ_, int64_t m_, int k_)
+    Run(Tree &t_, hipStream_t s_, const float *dQ_, int64_t m_, int k_, const Workspace &ws_, bool timing)
         : t(t_), s(s_), dQ(dQ_), m(m_), k(k_), K(key_capacity(k_)), d(t_.host.d), h(t_.host.h), nleaf(t_.nleaf),
-          kbits(key_bits_for(t_.nleaf)), tracing((t_.opt.flags & BKD_FLAG_TRACE) != 0)
+          kbits(key_bits_for(t_.nleaf)), tracing((t_.opt.flags & BKD_FLAG_TRACE) != 0), ws(ws_)
     {
-        t.d_keys.ensure(sizeof(uint64_t) * (size_t)m * K);
-        t.d_kth.ensure(sizeof(uint32_t) * (size_t)m);
-        t.d_node.ensure(sizeof(int32_t) * (size_t)m);
-        t.d_ring.ensure(sizeof(int32_t) * (size_t)m);
-        t.d_pleaf.ensure(sizeof(uint32_t) * (size_t)m);
-        t.d_pq.ensure(sizeof(int32_t) * (size_t)m);
-        t.d_tleaf.ensure(sizeof(uint32_t) * (size_t)m);
-        t.d_tq.ensure(sizeof(int32_t) * (size_t)m);
-        t.d_hist.ensure(sizeof(uint32_t) * sort_hist_words(m));
-        t.d_cnt.ensure(sizeof(int32_t) * (size_t)nleaf);
-        t.d_cnt0.ensure(sizeof(int32_t) * (size_t)nleaf);
-        t.d_off.ensure(sizeof(int32_t) * (size_t)(nleaf + 1));
-        t.d_tiles.ensure(sizeof(int32_t) * 2 * (size_t)(nleaf + 1));
         if (!t.resident) t.h_tiles.ensure(sizeof(int32_t) * 3 * (size_t)(nleaf + 1));
         ctl = t.d_ctl.as<int32_t>();
         hctl = t.h_ctl.as<int32_t>();
-        cnt = t.d_cnt.as<int32_t>();
-        leafbuf[0] = t.d_pleaf.as<uint32_t>();
-        leafbuf[1] = t.d_tleaf.as<uint32_t>();
-        qbuf[0] = t.d_pq.as<int32_t>();
-        qbuf[1] = t.d_tq.as<int32_t>();
-        tdense.on = tsparse.on = (t.opt.flags & BKD_FLAG_TIMING) != 0;
+        cnt = ws.cnt;
+        leafbuf[0] = ws.pleaf;
+        leafbuf[1] = ws.tleaf;
+        qbuf[0] = ws.pq;
+        qbuf[1] = ws.tq;
+        tdense.on = tsparse.on = tfind.on = tgroup.on = tcopy.on = timing;
     }
 
     const int32_t *htiles() const { return t.h_tiles.as<int32_t>(); }
@@ -343,13 +332,23 @@ struct Run {
         BKD_HIP(hipEventRecord(t.ev_rb, s));
     }
 
+    // Host-side wait for the device, counted in wait_ms.
+    template <class F> void waiting(F &&f)
+    {
+        const auto w0 = std::chrono::steady_clock::now();
+        f();
+        wait_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
+    }
+
     void readback_wait()
     {
-        for (;;) {
-            const hipError_t e = hipEventQuery(t.ev_rb);
-            if (e == hipSuccess) break;
-            if (e != hipErrorNotReady) BKD_HIP(e);
-        }
+        waiting([&] {
+            for (;;) {
+                const hipError_t e = hipEventQuery(t.ev_rb);
+                if (e == hipSuccess) break;
+                if (e != hipErrorNotReady) BKD_HIP(e);
+            }
+        });
         if (hctl[CTL_BAD]) fail(BKD_EINVAL, "query coordinates must be finite");
     }
 
@@ -357,8 +356,10 @@ struct Run {
 
     void find_leaf_into(const FetchSpec &f, uint32_t *out_leaf, int32_t *out_q, int64_t base)
     {
-        launch_find_leaf(f, dQ, d, t.d_node.as<int32_t>(), t.d_kth.as<uint32_t>(), t.d_split.as<float>(), h,
+        tfind.begin(s);
+        launch_find_leaf(f, dQ, d, ws.node, ws.kth, t.d_split.as<float>(), h,
                          out_leaf, out_q, base, cnt, ctl, s);
+        tfind.end(s);
         t.stats.fetches++;
         const int64_t F = f.ring_count + f.in_count;
         if (tracing && F > 0) {
@@ -366,7 +367,7 @@ struct Run {
             tr_l.resize((size_t)F);
             BKD_HIP(hipMemcpyAsync(tr_q.data(), out_q + base, sizeof(int32_t) * F, hipMemcpyDeviceToHost, s));
             BKD_HIP(hipMemcpyAsync(tr_l.data(), out_leaf + base, sizeof(int32_t) * F, hipMemcpyDeviceToHost, s));
-            BKD_HIP(hipStreamSynchronize(s));
+            waiting([&] { BKD_HIP(hipStreamSynchronize(s)); });
             for (int64_t j = 0; j < F; j++) {
                 t.trace_q.push_back(tr_q[(size_t)j]);
                 t.trace_leaf.push_back(tr_l[(size_t)j] == (uint32_t)nleaf ? -1 : (int32_t)tr_l[(size_t)j]);
@@ -380,24 +381,25 @@ struct Run {
     // wait: read the control words back before returning (else the copy is only issued)
     void sort_and_offsets(int64_t count, bool runs = false, bool wait = true)
     {
+        tgroup.begin(s);
         if (runs && !tracing && nleaf + 1 <= bucket_max_keys()) {
             // lock-step rounds: group by leaf in one pass (order within a buffer is free)
             const int nb = nleaf + 1;
-            uint32_t *hist = t.d_hist.as<uint32_t>();
+            uint32_t *hist = ws.hist;
             const int32_t *counts = launch_bucket_count(leafbuf[cur], count, nb, hist, s);
             // a resident round scans every buffer (or hands them to the tail): its work is counted here
             counted = t.resident;
             offsets(counts, nullptr, counted);
             launch_bucket_scatter(leafbuf[cur], qbuf[cur], leafbuf[1 - cur], qbuf[1 - cur], count, nb, hist,
-                                  t.d_off.as<int32_t>(), s);
+                                  ws.off, s);
             cur = 1 - cur;
         } else {
             int which = launch_sort_pairs(leafbuf[cur], qbuf[cur], leafbuf[1 - cur], qbuf[1 - cur], count, kbits,
-                                          t.d_hist.as<uint32_t>(), s);
+                                          ws.hist, s);
             if (which) cur = 1 - cur;
             int32_t *start = nullptr;
             if (runs) {
-                start = t.d_cnt0.as<int32_t>();
+                start = ws.cnt0;
                 launch_fill_i32(cnt, 0, nleaf, s);
                 launch_fill_i32(start, 0, nleaf, s);
                 launch_run_bounds(leafbuf[cur], count, nleaf, start, cnt, s);
@@ -405,10 +407,11 @@ struct Run {
             counted = false;
             offsets(cnt, start, false);
         }
+        tgroup.end(s);
         if (!t.resident) {
-            BKD_HIP(hipMemcpyAsync(t.h_tiles.p, t.d_tiles.p, sizeof(int32_t) * 2 * (size_t)(nleaf + 1),
+            BKD_HIP(hipMemcpyAsync(t.h_tiles.p, ws.tiles, sizeof(int32_t) * 2 * (size_t)(nleaf + 1),
                                    hipMemcpyDeviceToHost, s));
-            BKD_HIP(hipMemcpyAsync(t.h_tiles.as<int32_t>() + 2 * (nleaf + 1), t.d_off.p,
+            BKD_HIP(hipMemcpyAsync(t.h_tiles.as<int32_t>() + 2 * (nleaf + 1), ws.off,
                                    sizeof(int32_t) * (size_t)(nleaf + 1), hipMemcpyDeviceToHost, s));
         }
         if (wait) readback();
@@ -420,16 +423,16 @@ struct Run {
     void offsets(const int32_t *counts, const int32_t *start, bool count_work)
     {
         launch_leaf_offsets(counts, start, t.d_leaf_off.as<int32_t>(), nleaf, SCAN_QT, SCAN_DENSE_MIN,
-                            t.d_off.as<int32_t>(), t.d_tiles.as<int32_t>(), t.d_tiles.as<int32_t>() + nleaf + 1, ctl,
+                            ws.off, ws.tiles, ws.tiles + nleaf + 1, ctl,
                             s, count_work);
     }
 
     ScanArgs scan_args(const float *base, int64_t shift) const
     {
         ScanArgs a{};
-        a.tiles = t.d_tiles.as<int32_t>();
+        a.tiles = ws.tiles;
         a.sparse = a.tiles + nleaf + 1;
-        a.off = t.d_off.as<int32_t>();
+        a.off = ws.off;
         a.bufq = bufq_override ? bufq_override : qbuf[cur];
         a.leaf_off = t.d_leaf_off.as<int32_t>();
         a.base = base;
@@ -437,8 +440,8 @@ struct Run {
         a.blk_shift = shift;
         a.Q = dQ;
         a.d = d;
-        a.keys = t.d_keys.as<uint64_t>();
-        a.kth = t.d_kth.as<uint32_t>();
+        a.keys = ws.keys;
+        a.kth = ws.kth;
         a.k = k;
         a.centers = t.d_centers.as<float>();
         a.scales = a.centers + (size_t)nleaf * d;
@@ -465,7 +468,7 @@ struct Run {
 
     void count_work(int lf, int ll)
     {
-        launch_count_work(t.d_off.as<int32_t>(), t.d_leaf_off.as<int32_t>(), lf, ll, SCAN_DENSE_MIN, ctl, s);
+        launch_count_work(ws.off, t.d_leaf_off.as<int32_t>(), lf, ll, SCAN_DENSE_MIN, ctl, s);
     }
 
     // Scan every buffered query of a resident structure.
@@ -489,7 +492,7 @@ struct Run {
     void route_args(ScanArgs &a) const
     {
         a.route_leaf = leafbuf[cur];
-        a.node = t.d_node.as<int32_t>();
+        a.node = ws.node;
         a.split = t.d_split.as<float>();
         a.h = h;
     }
@@ -542,8 +545,10 @@ struct Run {
         const Chunk &c = t.chunks[(size_t)j];
         const size_t bytes = (size_t)(c.word_hi - c.word_lo) * 4;
         BKD_HIP(hipStreamWaitEvent(t.copy_stream, t.ev_used[b], 0));
+        tcopy.begin(t.copy_stream);
         BKD_HIP(hipMemcpyAsync(t.d_chunk[b].p, t.h_leaf.as<float>() + c.word_lo, bytes, hipMemcpyHostToDevice,
                                t.copy_stream));
+        tcopy.end(t.copy_stream);
         BKD_HIP(hipEventRecord(t.ev_copied[b], t.copy_stream));
         t.chunk_in[b] = j;
         t.stats.chunk_copies++;
@@ -586,7 +591,7 @@ struct Run {
         a.tail_count = (int32_t)n;
         a.tail_wide = (t.host.n >> h) >= TAIL_WIDE_LEAF;
         a.route_leaf = Rl;
-        a.node = t.d_node.as<int32_t>();
+        a.node = ws.node;
         a.split = t.d_split.as<float>();
         a.h = h;
         a.ctl = ctl;
@@ -640,7 +645,7 @@ struct Run {
         while (in_head < m || re_len > 0) {
             const int64_t take_re = std::min(M, re_len);
             const int64_t take_in = std::min(M - take_re, m - in_head);
-            FetchSpec f{t.d_ring.as<int32_t>(), re_head, take_re, m, in_head, take_in};
+            FetchSpec f{ws.ring, re_head, take_re, m, in_head, take_in};
             f.track_fill = true;
             find_leaf(f, pend);
             pend += take_re + take_in;
@@ -661,7 +666,7 @@ struct Run {
                 if (t.resident) scan_resident();
                 else scan_all_chunks();
             }
-            launch_ring_append(t.d_ring.as<int32_t>(), m, (re_head + re_len) % m, qbuf[cur], V, s);
+            launch_ring_append(ws.ring, m, (re_head + re_len) % m, qbuf[cur], V, s);
             re_len += V;
             launch_fill_i32(cnt, 0, nleaf, s);
             launch_fill_i32(ctl + CTL_MAXCNT, 0, 2, s);
@@ -746,7 +751,7 @@ struct Run {
         a.tail_count = (int32_t)P;
         a.tail_wide = (t.host.n >> h) >= TAIL_WIDE_LEAF;
         a.tail_counted = counted ? 1 : 0;
-        a.node = t.d_node.as<int32_t>();
+        a.node = ws.node;
         a.split = t.d_split.as<float>();
         a.h = h;
         a.k = k;
@@ -762,12 +767,10 @@ struct Run {
     // Results are independent of numbering; traces keep the caller's numbers.
     void localize()
     {
-        t.d_Qp.ensure(sizeof(float) * (size_t)m * d);
-        t.d_perm.ensure(sizeof(int32_t) * (size_t)m);
-        launch_localize(qbuf[cur], leafbuf[cur], m, d, dQ, t.d_Qp.as<float>(), t.d_perm.as<int32_t>(),
-                        t.d_node.as<int32_t>(), h, s);
-        dQ = t.d_Qp.as<float>();
-        perm = t.d_perm.as<int32_t>();
+        launch_localize(qbuf[cur], leafbuf[cur], m, d, dQ, ws.Qp, ws.perm,
+                        ws.node, h, s);
+        dQ = ws.Qp;
+        perm = ws.perm;
     }
 
     // Chunk sweep over a streamed, leaf-aligned structure.  Pending entries live in one
@@ -796,10 +799,12 @@ struct Run {
         int32_t *sq = qbuf[1 - cur];
         auto read_counts = [&]() {
             BKD_HIP(hipMemcpyAsync(hr, rcnt, sizeof(int32_t) * (N + 1), hipMemcpyDeviceToHost, s));
-            BKD_HIP(hipStreamSynchronize(s));
+            waiting([&] { BKD_HIP(hipStreamSynchronize(s)); });
         };
+        tgroup.begin(s);
         launch_fill_i32(rcnt, 0, N + 1, s);
         launch_distribute(leafbuf[cur], qbuf[cur], m, nleaf, chunk_of, -1, rleaf, rq, m, rcnt, sleaf, sq, N, s);
+        tgroup.end(s);
         read_counts();
         int c = -1;
         for (;;) {
@@ -834,24 +839,28 @@ struct Run {
                 // few queries left in c: the tail kernel drains the chunk in one launch
                 tail_chunk(c, nc, Rl, Rq, n);
                 end_call();
+                tgroup.begin(s);
                 launch_distribute(Rl, Rq, n, nleaf, chunk_of, c, rleaf, rq, m, rcnt, sleaf, sq, N, s);
                 launch_restore(sleaf, sq, n, Rl, Rq, rcnt, c, N, s);
                 launch_fill_i32(rcnt + N, 0, 1, s);
+                tgroup.end(s);
                 read_counts();
                 continue;
             }
             // sort the region by leaf, then offsets and work items of chunk c's leaves
-            if (launch_sort_pairs(Rl, Rq, sleaf, sq, n, kbits, t.d_hist.as<uint32_t>(), s)) {
+            tgroup.begin(s);
+            if (launch_sort_pairs(Rl, Rq, sleaf, sq, n, kbits, ws.hist, s)) {
                 BKD_HIP(hipMemcpyAsync(Rl, sleaf, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
                 BKD_HIP(hipMemcpyAsync(Rq, sq, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
             }
-            int32_t *dtiles = t.d_tiles.as<int32_t>();
-            int32_t *start = t.d_cnt0.as<int32_t>();
+            int32_t *dtiles = ws.tiles;
+            int32_t *start = ws.cnt0;
             launch_fill_i32(cnt + lf, 0, nl, s);
             launch_fill_i32(start + lf, 0, nl, s);
             launch_run_bounds(Rl, n, nleaf, start, cnt, s);
             launch_leaf_offsets(cnt + lf, start + lf, t.d_leaf_off.as<int32_t>() + lf, nl, SCAN_QT, SCAN_DENSE_MIN,
-                                t.d_off.as<int32_t>() + lf, dtiles + lf, dtiles + nleaf + 1 + lf, ctl, s);
+                                ws.off + lf, dtiles + lf, dtiles + nleaf + 1 + lf, ctl, s);
+            tgroup.end(s);
             BKD_HIP(hipMemcpyAsync(t.h_tiles.as<int32_t>() + lf, dtiles + lf, sizeof(int32_t) * (nl + 1),
                                    hipMemcpyDeviceToHost, s));
             BKD_HIP(hipMemcpyAsync(t.h_tiles.as<int32_t>() + nleaf + 1 + lf, dtiles + nleaf + 1 + lf,
@@ -866,9 +875,11 @@ struct Run {
             FetchSpec f{Rq, 0, n, std::max<int64_t>(n, 1), 0, 0};
             f.count_leaves = false;
             find_leaf_into(f, Rl, Rq, 0);
+            tgroup.begin(s);
             launch_distribute(Rl, Rq, n, nleaf, chunk_of, c, rleaf, rq, m, rcnt, sleaf, sq, N, s);
             launch_restore(sleaf, sq, n, Rl, Rq, rcnt, c, N, s);
             launch_fill_i32(rcnt + N, 0, 1, s);
+            tgroup.end(s);
             read_counts();
         }
     }
@@ -876,7 +887,84 @@ struct Run {
 
 }  // namespace
 
-void tree_query_device(Tree &t, const float *dQ, int64_t m, int k, int64_t *d_idx, float *d_dist, hipStream_t s)
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// The workspace's arrays in order, with their sizes for m queries of key capacity K.
+template <class F> static void workspace_layout(const Tree &t, int64_t m, int k, F &&place)
+{
+    const size_t M = (size_t)m, L = (size_t)t.nleaf;
+    const size_t K = (size_t)key_capacity(k), d = (size_t)t.host.d;
+    place(0, sizeof(uint64_t) * M * K);                  // keys
+    place(1, sizeof(uint32_t) * M);                      // kth
+    place(2, sizeof(int32_t) * M);                       // node
+    place(3, sizeof(int32_t) * M);                       // ring
+    place(4, sizeof(uint32_t) * M);                      // pleaf
+    place(5, sizeof(uint32_t) * M);                      // tleaf
+    place(6, sizeof(int32_t) * M);                       // pq
+    place(7, sizeof(int32_t) * M);                       // tq
+    place(8, sizeof(uint32_t) * sort_hist_words(m));     // hist
+    place(9, sizeof(int32_t) * L);                       // cnt
+    place(10, sizeof(int32_t) * L);                      // cnt0
+    place(11, sizeof(int32_t) * (L + 1));                // off
+    place(12, sizeof(int32_t) * 2 * (L + 1));            // tiles
+    place(13, sizeof(float) * M * d);                    // Qp
+    place(14, sizeof(int32_t) * M);                      // perm
+}
+
+static Workspace workspace_from(void *const (&p)[15])
+{
+    Workspace w;
+    w.keys = static_cast<uint64_t *>(p[0]);
+    w.kth = static_cast<uint32_t *>(p[1]);
+    w.node = static_cast<int32_t *>(p[2]);
+    w.ring = static_cast<int32_t *>(p[3]);
+    w.pleaf = static_cast<uint32_t *>(p[4]);
+    w.tleaf = static_cast<uint32_t *>(p[5]);
+    w.pq = static_cast<int32_t *>(p[6]);
+    w.tq = static_cast<int32_t *>(p[7]);
+    w.hist = static_cast<uint32_t *>(p[8]);
+    w.cnt = static_cast<int32_t *>(p[9]);
+    w.cnt0 = static_cast<int32_t *>(p[10]);
+    w.off = static_cast<int32_t *>(p[11]);
+    w.tiles = static_cast<int32_t *>(p[12]);
+    w.Qp = static_cast<float *>(p[13]);
+    w.perm = static_cast<int32_t *>(p[14]);
+    return w;
+}
+
+size_t workspace_bytes(const Tree &t, int64_t m, int k)
+{
+    size_t total = 0;
+    workspace_layout(t, m, k, [&](int, size_t b) { total += align256(b); });
+    return total;
+}
+
+Workspace workspace_in(const Tree &t, int64_t m, int k, void *region)
+{
+    void *p[15];
+    size_t off = 0;
+    workspace_layout(t, m, k, [&](int i, size_t b) {
+        p[i] = static_cast<char *>(region) + off;
+        off += align256(b);
+    });
+    return workspace_from(p);
+}
+
+// The tree's own workspace: one device buffer per array, grown on demand.
+static Workspace tree_workspace(Tree &t, int64_t m, int k)
+{
+    DevBuf *bufs[15] = {&t.d_keys, &t.d_kth, &t.d_node, &t.d_ring, &t.d_pleaf, &t.d_tleaf, &t.d_pq, &t.d_tq,
+                        &t.d_hist, &t.d_cnt, &t.d_cnt0, &t.d_off, &t.d_tiles, &t.d_Qp, &t.d_perm};
+    void *p[15];
+    workspace_layout(t, m, k, [&](int i, size_t b) {
+        bufs[i]->ensure(b);
+        p[i] = bufs[i]->p;
+    });
+    return workspace_from(p);
+}
+
+void tree_query_device(Tree &t, const float *dQ, int64_t m, int k, int64_t *d_idx, float *d_dist, hipStream_t s,
+                       void *region)
 {
     auto t0 = std::chrono::steady_clock::now();
     BKD_HIP(hipSetDevice(t.device));
@@ -886,25 +974,42 @@ void tree_query_device(Tree &t, const float *dQ, int64_t m, int k, int64_t *d_id
     t.trace_q.clear();
     t.trace_leaf.clear();
     if (m == 0) return;
+    if (region && (!t.resident || (t.opt.flags & BKD_FLAG_TRACE)))
+        fail(BKD_EINVAL, "a query in a caller-provided workspace needs a resident structure and no trace");
 
-    Run r(t, s, dQ, m, k);
+    const Workspace ws = region ? workspace_in(t, m, k, region) : tree_workspace(t, m, k);
+    Run r(t, s, dQ, m, k, ws, !region && (t.opt.flags & BKD_FLAG_TIMING) != 0);
     launch_fill_i32(r.ctl, 0, CTL_WORDS, s);
     launch_fill_i32(r.cnt, 0, t.nleaf, s);
     launch_check_finite(dQ, m * t.host.d, r.ctl, s);
-    launch_init_state(t.d_node.as<int32_t>(), t.d_keys.as<uint64_t>(), t.d_kth.as<uint32_t>(), m, r.K, s);
+    launch_init_state(ws.node, ws.keys, ws.kth, m, r.K, s);
     if (t.M < 0) r.lockstep();
     else r.algorithm1();
-    launch_finalize(t.d_keys.as<uint64_t>(), r.K, k, m, r.perm, d_idx, d_dist, (t.opt.flags & BKD_FLAG_SQUARED) != 0,
-                    s);
+    launch_finalize(ws.keys, r.K, k, m, r.perm, d_idx, d_dist, (t.opt.flags & BKD_FLAG_SQUARED) != 0, s);
     r.readback();
     std::memcpy(&t.stats.visits, r.hctl + CTL_VISITS_LO, 8);
     std::memcpy(&t.stats.dense_pairs, r.hctl + CTL_DPAIRS_LO, 8);
     std::memcpy(&t.stats.sparse_pairs, r.hctl + CTL_SPAIRS_LO, 8);
     t.stats.pairs = t.stats.dense_pairs + t.stats.sparse_pairs;
+    std::memcpy(&t.stats.dense_visits, r.hctl + CTL_DVISITS_LO, 8);
+    std::memcpy(&t.stats.leaf_points_dense, r.hctl + CTL_LPD_LO, 8);
+    std::memcpy(&t.stats.leaf_points_other, r.hctl + CTL_LPS_LO, 8);
+    {
+        // algorithmic bytes: every buffered leaf once per call, and per visit the query, its
+        // key list (read and written) and its buffer entry
+        const int64_t per_point = 4 * (int64_t)t.host.d + 4, per_visit = 4 * (int64_t)t.host.d + 16 * (int64_t)k + 4;
+        t.stats.alg_bytes = (t.stats.leaf_points_dense + t.stats.leaf_points_other) * per_point +
+                            t.stats.visits * per_visit;
+        t.stats.alg_bytes_dense = t.stats.leaf_points_dense * per_point + t.stats.dense_visits * per_visit;
+    }
     if (r.tdense.on) {
         t.stats.dense_ms = r.tdense.total_ms();
         t.stats.sparse_ms = r.tsparse.total_ms();
+        t.stats.find_ms = r.tfind.total_ms();
+        t.stats.group_ms = r.tgroup.total_ms();
+        t.stats.copy_ms = r.tcopy.total_ms();
     }
+    t.stats.wait_ms = r.wait_ms;
     t.stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
