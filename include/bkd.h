@@ -212,6 +212,26 @@ int bkd_query_async(bkd_tree *tree, const float *dQ, int64_t m, int32_t k, int64
                     void *stream);
 
 /*
+ * bkd_query_async with no allocation, for callers that cannot allocate device
+ * memory during a call (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and ordering as
+ * bkd_query_async.  The call's workspace is a fixed 64 MiB device array of the
+ * library (one per device, held until the process ends) instead of the tree's
+ * own buffers, so the call makes no hipMalloc, hipFree or other allocating
+ * call.  The workspace a call needs is about m (8K + 4d + 33) + 20 * 2^h +
+ * 8 KiB bytes (fifteen arrays, each rounded up to 256 bytes), K = the key
+ * capacity >= k from {1, 2, 4, 5, 8, 10, 16, 32, 64}: about 440,000 queries
+ * at d = 10, k = 10, h = 10.  Calls on one device share
+ * the array: calls that overlap on one device (on different streams or host
+ * threads) race and must not be made.  The tree must be resident (no leaf
+ * budget) and built without BKD_FLAG_TRACE; per-launch timing is not recorded.
+ * Errors: BKD_EINVAL (as bkd_query_async; a streamed or traced tree; a query
+ * whose workspace exceeds 64 MiB, with both sizes in the message), BKD_EDEVICE.
+ */
+int bkd_query_async_noalloc(bkd_tree *tree, const float *dQ, int64_t m, int32_t k, int64_t *d_idx, float *d_dist,
+                            void *stream);
+
+/*
  * Proximity-based outlier scores (Section 4, large-scale outlier detection):
  * the all-nearest-neighbours problem over the tree's own reference set.  The
  * score of reference point i is the mean of the float32 distances (as

@@ -70,6 +70,7 @@ _PROTOS = {
     "bkd_free": (ctypes.c_int, [_V]),
     "bkd_query": (ctypes.c_int, [_V, _V, _I64, _I32, _V, _V]),
     "bkd_query_async": (ctypes.c_int, [_V, _V, _I64, _I32, _V, _V, _V]),
+    "bkd_query_async_noalloc": (ctypes.c_int, [_V, _V, _I64, _I32, _V, _V, _V]),
     "bkd_outlier_scores": (ctypes.c_int, [_V, _V, _I64, _I32, _V, _V]),
     "bkd_tree_info_get": (ctypes.c_int, [_V, _V]),
     "bkd_tree_export": (ctypes.c_int, [_V, _V, _V, _V]),
@@ -231,6 +232,22 @@ def query_async(tree: Tree, dQ, k: int, d_idx, d_dist, stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     _check(lib().bkd_query_async(tree.handle, dQ.data_ptr(), m, k, d_idx.data_ptr(), d_dist.data_ptr(),
                                  ctypes.c_void_p(s.cuda_stream)))
+
+
+def query_async_noalloc(tree: Tree, dQ, k: int, d_idx, d_dist, stream=None):
+    """``bkd_query_async_noalloc``: as ``query_async``, with the library's fixed 64 MiB
+    device workspace instead of buffers it allocates (resident trees; calls that overlap
+    on one device race)."""
+    import torch
+    for t, dt in ((dQ, torch.float32), (d_idx, torch.int64), (d_dist, torch.float32)):
+        if not (t.is_cuda and t.is_contiguous() and t.dtype == dt):
+            raise ValueError("device tensors must be contiguous HIP tensors of the documented dtypes")
+    m = dQ.shape[0]
+    if dQ.shape != (m, tree.d) or d_idx.shape != (m, k) or d_dist.shape != (m, k):
+        raise ValueError("shape mismatch")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().bkd_query_async_noalloc(tree.handle, dQ.data_ptr(), m, k, d_idx.data_ptr(), d_dist.data_ptr(),
+                                         ctypes.c_void_p(s.cuda_stream)))
 
 
 def tree_info(tree: Tree) -> TreeInfo:
