@@ -44,6 +44,14 @@ def _load():
     i64, i32 = ctypes.c_int64, ctypes.c_int32
     lib.orc_build.argtypes = [P, i64, i32, i32, P, P, P]
     lib.orc_build.restype = ctypes.c_int
+    lib.orc_build_rules.argtypes = [P, i64, i32, i32, i32, P, P, P, P]
+    lib.orc_build_rules.restype = ctypes.c_int
+    lib.orc_node_boxes.argtypes = [P, i32, i32, P, P, P]
+    lib.orc_node_boxes.restype = ctypes.c_int
+    lib.orc_traverse_f32_rules.argtypes = [P, i32, i32, P, P, P, P, P, P, i32, P, i64, P]
+    lib.orc_traverse_f32_rules.restype = i64
+    lib.orc_traverse_many_f32_rules.argtypes = [P, i32, i32, P, P, P, P, P, P, i64, i32, P, P, i32]
+    lib.orc_traverse_many_f32_rules.restype = ctypes.c_int
     lib.orc_brute_f64.argtypes = [P, i64, P, i64, i32, i32, P, P, i32]
     lib.orc_brute_f64.restype = ctypes.c_int
     lib.orc_brute_f32c.argtypes = [P, i64, P, i64, i32, i32, P, i32]
@@ -92,8 +100,10 @@ def max_threads() -> int:
 class Tree:
     """Canonical tree arrays: split (heap order), leaf_off, perm."""
 
-    def __init__(self, split, leaf_off, perm, height, d):
+    def __init__(self, split, leaf_off, perm, height, d, dims=None):
         self.split, self.leaf_off, self.perm, self.height, self.d = split, leaf_off, perm, height, d
+        # splitting dimension per internal node (None: level mod d, the original rule)
+        self.dims = dims
 
 
 def build_tree(P, height: int) -> Tree:
@@ -107,6 +117,67 @@ def build_tree(P, height: int) -> Tree:
     if rc != 0:
         raise ValueError("orc_build rejected its arguments")
     return Tree(split[: nleaf - 1], leaf_off, perm, height, d)
+
+
+SPLIT_CYCLIC, SPLIT_LONGEST = 0, 1
+
+
+def build_tree_rules(P, height: int, rule: int) -> Tree:
+    """The canonical tree under a splitting rule: SPLIT_CYCLIC (level mod d) or SPLIT_LONGEST
+    (longest side of the node's bounding box); dims holds each internal node's dimension."""
+    P = _f32(P)
+    n, d = P.shape
+    nleaf = 1 << height
+    split = np.zeros(max(nleaf - 1, 1), dtype=np.float32)
+    dims = np.zeros(max(nleaf - 1, 1), dtype=np.int32)
+    leaf_off = np.zeros(nleaf + 1, dtype=np.int64)
+    perm = np.zeros(n, dtype=np.int32)
+    rc = _load().orc_build_rules(_ptr(P), n, d, height, rule, _ptr(split), _ptr(dims), _ptr(leaf_off), _ptr(perm))
+    if rc != 0:
+        raise ValueError("orc_build_rules rejected its arguments")
+    return Tree(split[: nleaf - 1], leaf_off, perm, height, d, dims[: nleaf - 1])
+
+
+def node_boxes(P, tree: Tree) -> np.ndarray:
+    """Bounding box of every node's points, heap order over all 2^(h+1)-1 nodes: [nodes, 2, d]
+    (row 0 the minima, row 1 the maxima)."""
+    P = _f32(P)
+    nodes = (2 << tree.height) - 1
+    box = np.zeros((nodes, 2, tree.d), dtype=np.float32)
+    if _load().orc_node_boxes(_ptr(P), tree.d, tree.height, _ptr(tree.leaf_off), _ptr(tree.perm), _ptr(box)) != 0:
+        raise ValueError("orc_node_boxes rejected its arguments")
+    return box
+
+
+def traverse_f32_rules(P, tree: Tree, q, k: int, boxes=None, max_leaves: int = 1 << 16):
+    """Leaf sequence and final keys of one query, walking with the tree's per-node dimensions
+    and, if boxes is given, the far child's box term instead of the plane term."""
+    P = _f32(P)
+    q = _f32(q).reshape(-1)
+    leaves = np.zeros(max_leaves, dtype=np.int32)
+    keys = np.zeros(k, dtype=np.uint64)
+    dims = np.ascontiguousarray(tree.dims, dtype=np.int32) if tree.dims is not None else None
+    bx = np.ascontiguousarray(boxes, dtype=np.float32) if boxes is not None else None
+    cnt = _load().orc_traverse_f32_rules(_ptr(P), tree.d, tree.height, _ptr(tree.split),
+                                         _ptr(dims) if dims is not None else None,
+                                         _ptr(bx) if bx is not None else None, _ptr(tree.leaf_off),
+                                         _ptr(tree.perm), _ptr(q), k, _ptr(leaves), max_leaves, _ptr(keys))
+    return leaves[: min(cnt, max_leaves)].copy(), keys
+
+
+def traverse_many_f32_rules(P, tree: Tree, Q, k: int, boxes=None, threads: int = 0):
+    """Final keys and leaves visited per query under the tree's rules (see traverse_f32_rules)."""
+    P, Q = _f32(P), _f32(Q)
+    m = Q.shape[0]
+    keys = np.zeros((m, k), dtype=np.uint64)
+    visits = np.zeros(m, dtype=np.int64)
+    dims = np.ascontiguousarray(tree.dims, dtype=np.int32) if tree.dims is not None else None
+    bx = np.ascontiguousarray(boxes, dtype=np.float32) if boxes is not None else None
+    _load().orc_traverse_many_f32_rules(_ptr(P), tree.d, tree.height, _ptr(tree.split),
+                                        _ptr(dims) if dims is not None else None,
+                                        _ptr(bx) if bx is not None else None, _ptr(tree.leaf_off),
+                                        _ptr(tree.perm), _ptr(Q), m, k, _ptr(keys), _ptr(visits), threads)
+    return keys, visits
 
 
 def brute_f64(P, Q, k: int, threads: int = 0):

@@ -16,6 +16,9 @@
  *   orc_replay_*       LazySearch schedule replay       Algorithm 1 (Section 2.4), Section 3.2
  *   orc_traverse_f32   one query's leaf sequence        Section 2.3 search phases, stackless form
  *   orc_chunk_bounds   leaf-structure chunk bounds      Section 3.2 ("Processing the Leaf Structure")
+ *   orc_build_rules    variant tree: longest-side split Section 2.3 (footnote on splitting rules)
+ *   orc_node_boxes     node bounding boxes              Section 2.3 (search phase, pruning)
+ *   orc_traverse_*_rules  walk with per-node dimensions and bounding-box pruning
  *
  * Readings of the paper used here (the paper is silent or loose on them):
  *   - "height h" = h internal levels, 2^h leaves; h = 0 is a single leaf.
@@ -132,9 +135,47 @@ static int level_of(int64_t v)
  * perm[n]          original index of the point at each leaf-structure position
  * Returns 0, or -1 on invalid arguments / allocation failure.
  */
+/*
+ * Splitting dimension of a node (Section 2.3).  rule 0: level mod d (the
+ * original k-d tree).  rule 1: the longest side of the bounding box of the
+ * node's points (the footnote's alternative rule): the j with the largest
+ * float32 side fl32(max_j - min_j), the smaller j on ties.
+ */
+static int split_dim(const float *P, int d, const int32_t *perm, int64_t a, int64_t c, int level, int rule)
+{
+    if (rule == 0) return level % d;
+    int best = 0;
+    float best_side = -1.0f;
+    for (int j = 0; j < d; j++) {
+        float mn = INFINITY, mx = -INFINITY;
+        for (int64_t i = 0; i < c; i++) {
+            float v = P[(int64_t)perm[a + i] * d + j];
+            if (v < mn) mn = v;
+            if (v > mx) mx = v;
+        }
+        float side = mx - mn;
+        if (side > best_side) {
+            best_side = side;
+            best = j;
+        }
+    }
+    return best;
+}
+
+int orc_build_rules(const float *P, int64_t n, int32_t d, int32_t h, int32_t rule, float *split, int32_t *dims,
+                    int64_t *leaf_off, int32_t *perm);
+
 int orc_build(const float *P, int64_t n, int32_t d, int32_t h, float *split, int64_t *leaf_off, int32_t *perm)
 {
-    if (!P || n < 1 || d < 1 || h < 0 || h > 30 || ((int64_t)1 << h) > n) return -1;
+    return orc_build_rules(P, n, d, h, 0, split, NULL, leaf_off, perm);
+}
+
+/* The same construction with a choice of splitting rule; dims[v] (if not NULL) receives the
+   splitting dimension of internal node v. */
+int orc_build_rules(const float *P, int64_t n, int32_t d, int32_t h, int32_t rule, float *split, int32_t *dims,
+                    int64_t *leaf_off, int32_t *perm)
+{
+    if (!P || n < 1 || d < 1 || h < 0 || h > 30 || ((int64_t)1 << h) > n || rule < 0 || rule > 1) return -1;
     int64_t nleaf = (int64_t)1 << h;
     int64_t nnodes = 2 * nleaf - 1;
     int64_t *lo = (int64_t *)malloc(sizeof(int64_t) * nnodes);
@@ -145,12 +186,13 @@ int orc_build(const float *P, int64_t n, int32_t d, int32_t h, float *split, int
     hi[0] = n;
     for (int l = 0; l < h; l++) {
         int64_t first = ((int64_t)1 << l) - 1, count = (int64_t)1 << l;
-        int dim = l % d;
         int failed = 0;
 #pragma omp parallel for schedule(dynamic, 1)
         for (int64_t t = 0; t < count; t++) {
             int64_t v = first + t;
             int64_t a = lo[v], c = hi[v] - lo[v];
+            int dim = split_dim(P, d, perm, a, c, l, rule);
+            if (dims) dims[v] = dim;
             vi_t *tmp = (vi_t *)malloc(sizeof(vi_t) * (size_t)c);
             if (!tmp) { failed = 1; continue; }
             for (int64_t i = 0; i < c; i++) {
@@ -478,6 +520,138 @@ int orc_traverse_many_f32(const float *P, int32_t d, int32_t h, const float *spl
         }
         if (out_visits) out_visits[qi] = count;
         if (out_pairs) out_pairs[qi] = pairs;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Variant tree: a splitting dimension per node and bounding-box pruning     */
+/* (Section 2.3: the footnote's other splitting rules; the search phase     */
+/* prunes a subtree whose points are all farther than the current k-th      */
+/* candidate -- the box of its points gives a tighter such bound than the   */
+/* splitting hyperplane).                                                   */
+
+/*
+ * Bounding box of every node's points, heap order over all 2^(h+1) - 1
+ * nodes (internal nodes, then leaves): box[v * 2d + j] = min of coordinate j,
+ * box[v * 2d + d + j] = max.  A node's points are the leaf-structure
+ * positions of the leaves below it.
+ */
+int orc_node_boxes(const float *P, int32_t d, int32_t h, const int64_t *leaf_off, const int32_t *perm, float *box)
+{
+    if (!P || d < 1 || h < 0 || h > 30) return -1;
+    int64_t nleaf = (int64_t)1 << h, first_leaf = nleaf - 1;
+    for (int64_t l = 0; l < nleaf; l++) {
+        float *b = box + (first_leaf + l) * 2 * d;
+        for (int j = 0; j < d; j++) {
+            b[j] = INFINITY;
+            b[d + j] = -INFINITY;
+        }
+        for (int64_t p = leaf_off[l]; p < leaf_off[l + 1]; p++) {
+            const float *x = P + (int64_t)perm[p] * d;
+            for (int j = 0; j < d; j++) {
+                if (x[j] < b[j]) b[j] = x[j];
+                if (x[j] > b[d + j]) b[d + j] = x[j];
+            }
+        }
+    }
+    for (int64_t v = first_leaf - 1; v >= 0; v--) {
+        float *b = box + v * 2 * d;
+        const float *l = box + (2 * v + 1) * 2 * d, *r = box + (2 * v + 2) * 2 * d;
+        for (int j = 0; j < d; j++) {
+            b[j] = l[j] < r[j] ? l[j] : r[j];
+            b[d + j] = l[d + j] > r[d + j] ? l[d + j] : r[d + j];
+        }
+    }
+    return 0;
+}
+
+/*
+ * float32 box term of query q and box b: g_j = the distance of q_j to
+ * [min_j, max_j] (0 inside), rounded to float32, accumulated as the distance
+ * is: acc = fmaf(g_j, g_j, acc) for j = 0..d-1 from +0.  For every point x in
+ * the box, |fl32(q_j - x_j)| >= g_j and rounding is monotone, so the term
+ * never exceeds the float32 squared distance of x.
+ */
+static float box2_f32(const float *q, const float *b, int d)
+{
+    float acc = 0.0f;
+    for (int j = 0; j < d; j++) {
+        float g = 0.0f;
+        if (q[j] < b[j]) g = b[j] - q[j];
+        else if (q[j] > b[d + j]) g = q[j] - b[d + j];
+        acc = fmaf(g, g, acc);
+    }
+    return acc;
+}
+
+static int node_dim(const int32_t *dims, int64_t v, int d) { return dims ? dims[v] : level_of(v) % d; }
+
+static int64_t descend_r(const float *q, const float *split, const int32_t *dims, int64_t v, int64_t first_leaf, int d)
+{
+    while (v < first_leaf) v = (q[node_dim(dims, v, d)] < split[v]) ? 2 * v + 1 : 2 * v + 2;
+    return v;
+}
+
+/* The stackless walk of next_leaf with per-node dimensions (dims, NULL: level mod d) and the
+   far child's box term in place of the plane term (box, NULL: the plane). */
+static int64_t next_leaf_r(int64_t state, const float *q, float kth, const float *split, const int32_t *dims,
+                           const float *box, int64_t first_leaf, int d)
+{
+    if (state == ORC_DONE) return ORC_DONE;
+    if (state == ORC_FRESH) return descend_r(q, split, dims, 0, first_leaf, d);
+    int64_t u = state;
+    while (u != 0) {
+        int64_t p = (u - 1) / 2;
+        int dim = node_dim(dims, p, d);
+        int64_t nearc = (q[dim] < split[p]) ? 2 * p + 1 : 2 * p + 2;
+        int64_t sib = (nearc == 2 * p + 1) ? 2 * p + 2 : 2 * p + 1;
+        if (u == nearc) {
+            float t = q[dim] - split[p];
+            float bound = box ? box2_f32(q, box + sib * 2 * d, d) : t * t;
+            if (bound <= kth) return descend_r(q, split, dims, sib, first_leaf, d);
+        }
+        u = p;
+    }
+    return ORC_DONE;
+}
+
+int64_t orc_traverse_f32_rules(const float *P, int32_t d, int32_t h, const float *split, const int32_t *dims,
+                               const float *box, const int64_t *leaf_off, const int32_t *perm, const float *q, int32_t k,
+                               int32_t *out_leaves, int64_t max_leaves, uint64_t *out_keys)
+{
+    int64_t first_leaf = ((int64_t)1 << h) - 1;
+    for (int i = 0; i < k; i++) out_keys[i] = ORC_EMPTY_KEY;
+    int64_t state = ORC_FRESH, count = 0;
+    for (;;) {
+        state = next_leaf_r(state, q, kth_of(out_keys, k), split, dims, box, first_leaf, d);
+        if (state == ORC_DONE) break;
+        if (count < max_leaves) out_leaves[count] = (int32_t)(state - first_leaf);
+        count++;
+        scan_leaf(P, d, leaf_off, perm, state - first_leaf, q, out_keys, k);
+    }
+    return count;
+}
+
+int orc_traverse_many_f32_rules(const float *P, int32_t d, int32_t h, const float *split, const int32_t *dims,
+                                const float *box, const int64_t *leaf_off, const int32_t *perm, const float *Q,
+                                int64_t m, int32_t k, uint64_t *out_keys, int64_t *out_visits, int32_t nthreads)
+{
+    set_threads(nthreads);
+    int64_t first_leaf = ((int64_t)1 << h) - 1;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t qi = 0; qi < m; qi++) {
+        uint64_t *kl = out_keys + qi * k;
+        const float *q = Q + qi * d;
+        for (int i = 0; i < k; i++) kl[i] = ORC_EMPTY_KEY;
+        int64_t state = ORC_FRESH, count = 0;
+        for (;;) {
+            state = next_leaf_r(state, q, kth_of(kl, k), split, dims, box, first_leaf, d);
+            if (state == ORC_DONE) break;
+            count++;
+            scan_leaf(P, d, leaf_off, perm, state - first_leaf, q, kl, k);
+        }
+        if (out_visits) out_visits[qi] = count;
     }
     return 0;
 }

@@ -116,3 +116,109 @@ def search_py(P, split, leaves, h, q, k):
 
     visit(0, 0)
     return order, best
+
+
+# --------------------------------------------------------------------------
+# Variant tree: longest-side splits and bounding-box pruning (Section 2.3)
+
+def side_f32(vals) -> float:
+    """Longest-side measure of one dimension: fl32(max - min) of its float32 values."""
+    return round_f32(Fraction(float(max(vals))) - Fraction(float(min(vals))))
+
+
+def build_rules_py(P, h, rule):
+    """Recursive median split with a splitting rule: 0 = level mod d, 1 = the dimension whose
+    bounding-box side fl32(max - min) over the node's points is largest (smallest d on ties).
+    Returns (split, dims, leaves)."""
+    n, d = P.shape
+    split = [0.0] * ((1 << h) - 1)
+    dims = [0] * ((1 << h) - 1)
+    leaves = [None] * (1 << h)
+
+    def rec(v, level, idx):
+        if level == h:
+            leaves[v - ((1 << h) - 1)] = sorted(idx)
+            return
+        if rule == 0:
+            dim = level % d
+        else:
+            sides = [side_f32([float(P[i, j]) for i in idx]) for j in range(d)]
+            dim = max(range(d), key=lambda j: (sides[j], -j))
+        dims[v] = dim
+        s = sorted(idx, key=lambda i: (float(P[i, dim]), i))
+        c = len(s)
+        split[v] = float(P[s[c // 2], dim])
+        rec(2 * v + 1, level + 1, s[: c // 2])
+        rec(2 * v + 2, level + 1, s[c // 2:])
+
+    rec(0, 0, list(range(n)))
+    return split, dims, leaves
+
+
+def boxes_py(P, h, leaves):
+    """(lo, hi) lists of every heap node: the bounding box of the points of the leaves below it."""
+    first = (1 << h) - 1
+    out = [None] * (2 * first + 1)
+
+    def rec(v):
+        if v >= first:
+            pts = P[leaves[v - first]]
+        else:
+            rec(2 * v + 1)
+            rec(2 * v + 2)
+            pts = None
+        if pts is not None:
+            out[v] = ([float(x) for x in pts.min(axis=0)], [float(x) for x in pts.max(axis=0)])
+        else:
+            a, b = out[2 * v + 1], out[2 * v + 2]
+            out[v] = ([min(x, y) for x, y in zip(a[0], b[0])], [max(x, y) for x, y in zip(a[1], b[1])])
+        return out[v]
+
+    rec(0)
+    return out
+
+
+def box2_f32_exact(q, lo, hi) -> float:
+    """float32 box term: g_j = fl32 distance of q_j to [lo_j, hi_j], acc = fl32(g*g + acc)."""
+    acc = Fraction(0)
+    for qj, a, b in zip(q, lo, hi):
+        qj = Fraction(float(qj))
+        if qj < Fraction(a):
+            g = Fraction(round_f32(Fraction(a) - qj))
+        elif qj > Fraction(b):
+            g = Fraction(round_f32(qj - Fraction(b)))
+        else:
+            g = Fraction(0)
+        acc = Fraction(round_f32(g * g + acc))
+    return float(acc)
+
+
+def search_rules_py(P, split, dims, leaves, h, q, k, boxes=None):
+    """Recursive depth-first search, near child first, per-node dimensions, and the far child
+    entered when its bound (the box term with boxes, else the plane term) does not exceed the
+    current k-th float32 squared distance.  Returns (leaf order, final list)."""
+    first = (1 << h) - 1
+    best = []
+    order = []
+
+    def kth():
+        return best[k - 1][0] if len(best) >= k else math.inf
+
+    def visit(v):
+        if v >= first:
+            leaf = v - first
+            order.append(leaf)
+            for i in leaves[leaf]:
+                best.append((dist2_f32_exact(q, P[i]), i))
+            best.sort()
+            del best[k:]
+            return
+        dim = dims[v]
+        near, far = (2 * v + 1, 2 * v + 2) if float(q[dim]) < split[v] else (2 * v + 2, 2 * v + 1)
+        visit(near)
+        bound = box2_f32_exact(q, *boxes[far]) if boxes is not None else plane2_f32_exact(q[dim], split[v])
+        if bound <= kth():
+            visit(far)
+
+    visit(0)
+    return order, best
