@@ -64,6 +64,8 @@ def _load():
     lib.orc_kdtree_f64_query.restype = ctypes.c_int
     lib.orc_kdtree_f64_free.argtypes = [P]
     lib.orc_kdtree_f64_free.restype = None
+    lib.orc_leaf_chunks.argtypes = [P, i32, i32, i64, i64, P]
+    lib.orc_leaf_chunks.restype = i64
     lib.orc_traverse_f32.argtypes = [P, i32, i32, P, P, P, P, i32, P, i64, P]
     lib.orc_traverse_f32.restype = i64
     lib.orc_traverse_many_f32.argtypes = [P, i32, i32, P, P, P, P, i64, i32, P, P, P, i32]
@@ -315,6 +317,17 @@ def chunk_bounds(n: int, N: int):
     if _load().orc_chunk_bounds(n, N, _ptr(lo), _ptr(hi)) != 0:
         raise ValueError("bad chunk arguments")
     return lo, hi
+
+
+def leaf_chunks(tree: Tree, N: int = 0, cap_bytes: int = 0):
+    """Leaf-aligned chunk plan: array of first leaves, chunk j holds leaves [first[j], first[j+1])."""
+    nleaf = 1 << tree.height
+    first = np.zeros(nleaf + 1, dtype=np.int64)
+    c = _load().orc_leaf_chunks(_ptr(np.ascontiguousarray(tree.leaf_off, dtype=np.int64)), tree.height, tree.d,
+                                N, cap_bytes, _ptr(first))
+    if c < 0:
+        raise ValueError("bad leaf chunk arguments")
+    return first[: c + 1].copy()
 
 
 def keys_split(keys: np.ndarray):

@@ -16,6 +16,7 @@
  *   orc_replay_*       LazySearch schedule replay       Algorithm 1 (Section 2.4), Section 3.2
  *   orc_traverse_f32   one query's leaf sequence        Section 2.3 search phases, stackless form
  *   orc_chunk_bounds   leaf-structure chunk bounds      Section 3.2 ("Processing the Leaf Structure")
+ *   orc_leaf_chunks    leaf-aligned chunk plan          Section 3.2 (chunks of whole leaves)
  *   orc_build_rules    variant tree: longest-side split Section 2.3 (footnote on splitting rules)
  *   orc_node_boxes     node bounding boxes              Section 2.3 (search phase, pruning)
  *   orc_traverse_*_rules  walk with per-node dimensions and bounding-box pruning
@@ -833,6 +834,36 @@ void orc_replay_get(const orc_replay_t *r, uint64_t *keys, int64_t *call_off, in
 /* ------------------------------------------------------------------------ */
 /* Chunk bounds of the leaf structure (Section 3.2): chunk j of N covers    */
 /* positions [ceil((j-1) n / N), ceil(j n / N)), read half-open.            */
+
+/*
+ * Leaf-aligned chunks (the reading of Section 3.2 in which a chunk holds whole
+ * leaves, so a leaf never straddles two chunks): chunk j holds leaves
+ * [first[j], first[j+1]).  With N > 0 the leaf range is cut by the same
+ * ceiling rule as positions: chunk j of N holds leaves [ceil((j-1) L / N),
+ * ceil(j L / N)) of the L = 2^h leaves.  With N = 0 the leaves are packed in
+ * order, as many whole leaves per chunk as fit cap_bytes at (4d + 4) bytes per
+ * point (a leaf larger than the capacity is a chunk of its own).  first gets
+ * up to L + 1 entries; returns the number of chunks, or -1.
+ */
+int64_t orc_leaf_chunks(const int64_t *leaf_off, int32_t h, int32_t d, int64_t N, int64_t cap_bytes, int64_t *first)
+{
+    int64_t L = (int64_t)1 << h;
+    if (!leaf_off || d < 1 || N < 0 || (N == 0 && cap_bytes < 1)) return -1;
+    if (N > 0) {
+        if (N > L) N = L;
+        for (int64_t j = 0; j <= N; j++) first[j] = (j * L + N - 1) / N;
+        return N;
+    }
+    int64_t count = 0, l = 0, bpp = 4 * (int64_t)d + 4;
+    while (l < L) {
+        int64_t e = l + 1;
+        while (e < L && (leaf_off[e + 1] - leaf_off[l]) * bpp <= cap_bytes) e++;
+        first[count++] = l;
+        l = e;
+    }
+    first[count] = L;
+    return count;
+}
 
 int orc_chunk_bounds(int64_t n, int64_t N, int64_t *lo, int64_t *hi)
 {

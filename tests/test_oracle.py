@@ -340,3 +340,23 @@ def test_chunk_bounds_golden_and_partition():
             lo, hi = oracle.chunk_bounds(n, N)
             assert lo[0] == 0 and hi[-1] == n
             assert np.all(lo[1:] == hi[:-1]) and np.all(hi > lo)
+
+
+def test_leaf_chunk_plan_golden_and_partition():
+    for c in _golden("leaf_chunks.json")["cases"]:
+        t = oracle.Tree(None, np.array(c["leaf_off"], dtype=np.int64), None, c["height"], c["d"])
+        assert oracle.leaf_chunks(t, c["N"], c["cap_bytes"]).tolist() == c["first"], c["note"]
+    P, _ = datagen.mixture_pq(seed=13, n=10_007, m=1, d=5, comps=4)
+    t = oracle.build_tree(P, 6)
+    bpp = 4 * 5 + 4
+    for cap in (bpp * 400, bpp * 1000, bpp * 5000):
+        first = oracle.leaf_chunks(t, 0, cap)
+        assert first[0] == 0 and first[-1] == 64 and np.all(np.diff(first) > 0)
+        sizes = (t.leaf_off[first[1:]] - t.leaf_off[first[:-1]]) * bpp
+        assert np.all(sizes <= cap)
+        # packing is greedy: no chunk could also hold the next chunk's first leaf
+        nxt = (t.leaf_off[np.minimum(first[1:-1] + 1, 64)] - t.leaf_off[first[:-2]]) * bpp
+        assert np.all(nxt > cap)
+    for N in (1, 3, 7, 64, 100):
+        first = oracle.leaf_chunks(t, N)
+        assert len(first) == min(N, 64) + 1 and first[0] == 0 and first[-1] == 64 and np.all(np.diff(first) > 0)
