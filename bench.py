@@ -34,6 +34,13 @@ sys.path.insert(0, ROOT)
 
 import datagen  # noqa: E402
 
+T_START = time.perf_counter()
+
+
+def note(msg):
+    """Progress of a long run, on stderr (the JSON line stays alone on stdout)."""
+    print(f"bench [{time.perf_counter() - T_START:6.1f} s]: {msg}", file=sys.stderr, flush=True)
+
 # Peaks of one MI355X (vendor figures).
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # vendor FP32 vector figure (counts packed dual-rate FP32)
@@ -93,7 +100,8 @@ def timed_steps(bkd, torch, tree, dQ, k, di, dd, stream, steps, warmup):
         bkd.query_async(tree, dQ, k, di, dd, stream=stream)
     torch.cuda.synchronize()
     keys = ("dense_ms", "dense_launches", "dense_pairs", "sparse_ms", "sparse_launches", "sparse_pairs", "pairs",
-            "calls", "chunk_copies", "bytes_h2d")
+            "calls", "chunk_copies", "bytes_h2d", "visits", "dense_visits", "alg_bytes", "alg_bytes_dense",
+            "find_ms", "group_ms", "copy_ms", "wait_ms")
     acc = {key: 0 for key in keys}
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -126,22 +134,26 @@ def cpu_model():
     return platform.processor()
 
 
-def cpu_baseline(P, Q, k, budget_s):
-    """The oracle's float64 k-d tree (leaf size 32), OpenMP over queries on every host core."""
+def cpu_baseline(P, Q, k, budget_s, fixed=None, m_total=None):
+    """The oracle's float64 k-d tree (leaf size 32), OpenMP over queries on every host core.
+    fixed: time exactly the first `fixed` queries; else a sample of about budget_s seconds."""
     import oracle
     threads = oracle.max_threads()
     tree = oracle.KdTree64(P, 32)
-    # calibrate on a small sample, then time a bounded sample of about budget_s seconds
-    cal = min(len(Q), 2048)
-    t0 = time.perf_counter()
-    tree.query(Q[:cal], k)
-    rate = cal / max(time.perf_counter() - t0, 1e-6)
-    ns = int(min(len(Q), max(cal, rate * budget_s)))
+    if fixed is not None:
+        ns = min(len(Q), fixed)
+    else:
+        # calibrate on a small sample, then time a bounded sample of about budget_s seconds
+        cal = min(len(Q), 2048)
+        t0 = time.perf_counter()
+        tree.query(Q[:cal], k)
+        rate = cal / max(time.perf_counter() - t0, 1e-6)
+        ns = int(min(len(Q), max(cal, rate * budget_s)))
     t0 = time.perf_counter()
     tree.query(Q[:ns], k)
     dt = time.perf_counter() - t0
     return {"value": ns / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {ns} of {len(Q)} queries against all {len(P)} points; float64 k-d tree, "
+            "sample": f"first {ns} of {m_total or len(Q)} queries against all {len(P)} points; float64 k-d tree, "
                       f"leaf size 32, OpenMP over queries ({threads} threads, {cpu_model()})"}
 
 
@@ -199,11 +211,12 @@ def run_batched(args, torch, bkd):
                    "rounds": st["rounds"], "tasks": st["tasks"], "pairs": st["pairs"],
                    "plain_loop_queries_per_s": round(total_m / loop_s, 1),
                    "speedup_vs_plain_loop": round((total_m / (wall / args.steps)) / (total_m / loop_s), 2)},
+        # device code is built without packed FP32, so the vector peak it can reach is the
+        # non-packed 78.6 TFLOP/s (the vendor's 157.3 counts dual-rate packed FP32)
         "roofline": {"kernel": "k_batch (persistent)", "bound": "alu", "achieved": round(achieved, 3),
-                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
-                     "peak_nonpacked": round(FP32_NONPACKED_TFLOPS, 1),
-                     "frac_nonpacked": round(achieved / FP32_NONPACKED_TFLOPS, 4),
+                     "peak": round(FP32_NONPACKED_TFLOPS, 1), "unit": "TFLOP/s",
+                     "frac": round(achieved / FP32_NONPACKED_TFLOPS, 4), "traffic": None,
+                     "peak_packed_vendor": FP32_VECTOR_PEAK_TFLOPS,
                      "avg_launch_ms": round(run_ms / args.steps, 4), "flops_per_launch": flops},
         **({} if args.no_cpu_baseline else {"cpu_baseline": cpu_baseline_batched(inst, args.cpu_seconds)}),
     }
@@ -230,19 +243,20 @@ def cpu_baseline_batched(inst, budget_s):
                       f"leaf size 32, OpenMP over queries ({threads} threads, {cpu_model()})"}
 
 
-def run_served(args, torch, bkd):
-    import threading
+def run_served(args, torch, bkd, plain_requests=600, cpu_queries=None):
 
     specs = [dict(n=1 << 27, d=10, h=14), dict(n=1 << 25, d=15, h=12)]
-    trees, params = [], []
+    trees, params, Ps = [], [], []
     for t, sp in enumerate(specs):
         seed = args.seed + 100 * (t + 1)
         pr = datagen.mixture_params(seed, sp["d"], 16)
         P = datagen.mixture(seed, datagen.STREAM_P, sp["n"], sp["d"], 16, pr)
-        trees.append(bkd.build(P, sp["h"], buffer_size=-1, fetch_size=-1))
+        trees.append(bkd.build(P, sp["h"], buffer_size=-1, fetch_size=-1, flags=bkd.FLAG_DEVICE_BUILD))
         params.append((seed, pr))
+        Ps.append(P if cpu_queries else None)
         del P
-    srv = bkd.server_create(slots_per_session=1 << 21)
+    note("served: trees built")
+    srv = bkd.server_create(slots_per_session=1 << 21, age_max=args.served_age_max, tail_max=args.served_tail_max)
     tids = [bkd.server_add_tree(srv, t) for t in trees]
 
     def request_queries(trace):
@@ -285,14 +299,17 @@ def run_served(args, torch, bkd):
     x_sat = qc / wall_c
     s1 = bkd.server_stats(srv)
     closed_server = {f: (round(s1[f] - s0[f], 3) if f != "sessions" else s1[f]) for f in s1}
-    # the plain per-batch loop: one query call per request, one after another
+    # the plain per-batch loop: one query call per request, one after another (the first
+    # plain_requests requests of the same trace)
     t1 = time.perf_counter()
-    for r, Q in zip(closed, Qc):
+    npl = min(len(closed), plain_requests)
+    for r, Q in zip(closed[:npl], Qc[:npl]):
         bkd.query(trees[r["tree"]], Q, r["k"])
-    loop_qps = qc / (time.perf_counter() - t1)
+    loop_qps = sum(r["m"] for r in closed[:npl]) / (time.perf_counter() - t1)
     mean_m = (2 ** 16 - 1) / (16 * np.log(2))
     levels = {}
     for frac in (0.5, 0.8):
+        note(f"served: open loop at {frac} of the saturated rate")
         rate = frac * x_sat / mean_m
         trace = datagen.request_trace(args.seed + int(frac * 10), args.served_requests, rate)
         Qs = request_queries(trace)
@@ -305,7 +322,12 @@ def run_served(args, torch, bkd):
     srv.destroy()
     for t in trees:
         t.free()
-    return {
+    cpu = None
+    if cpu_queries:
+        note("served: CPU oracle baseline")
+        cpu = cpu_baseline_served(Ps, closed, Qc, cpu_queries)
+    del Ps
+    out = {
         "metric": "kNN queries/s (served form) + p50/p99 latency at fixed offered load",
         "value": round(x_sat, 1), "unit": "queries/s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": round(wall_c * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -313,14 +335,52 @@ def run_served(args, torch, bkd):
         "config": {"workload": "served: trees n=2^27 d=10 h=14 and n=2^25 d=15 h=12 (16-component mixtures), "
                                "requests m=floor(2^U(0,16)), k in {1,10,32}, tree uniform; saturated throughput "
                                f"from {len(closed)} requests submitted at once, latency from Poisson arrivals",
+                   "age_max": args.served_age_max, "tail_max": args.served_tail_max,
                    "closed_loop_requests": len(closed), "closed_loop_queries": qc,
                    "closed_loop_server": closed_server,
                    "closed_loop_p50_ms": round(float(np.percentile(lat_c, 50)) * 1e3, 3),
                    "closed_loop_p99_ms": round(float(np.percentile(lat_c, 99)) * 1e3, 3),
                    "plain_loop_queries_per_s": round(loop_qps, 1),
+                   "plain_loop_requests": npl,
                    "speedup_vs_plain_loop": round(x_sat / loop_qps, 2),
                    "open_loop": levels},
     }
+    if cpu:
+        out["cpu_baseline"] = cpu
+    return out
+
+
+def cpu_baseline_served(Ps, trace, Qs, count):
+    """The oracle's float64 k-d tree on the served workload: the requests of the closed-loop
+    trace in order, each against its own tree with its own k, until `count` queries."""
+    import oracle
+    threads = oracle.max_threads()
+    kd = [oracle.KdTree64(P, 32) for P in Ps]
+    q = 0
+    used = 0
+    t = 0.0
+    for r, Q in zip(trace, Qs):
+        Q = Q[:count - q]
+        t0 = time.perf_counter()
+        kd[r["tree"]].query(Q, r["k"])
+        t += time.perf_counter() - t0
+        q += len(Q)
+        used += 1
+        if q >= count:
+            break
+    return {"value": q / t, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first {q} queries of the closed-loop trace ({used} requests), each against its tree "
+                      f"(2^27 points d=10 or 2^25 points d=15) with its k; float64 k-d tree, leaf size 32, "
+                      f"OpenMP over queries ({threads} threads, {cpu_model()})"}
+
+
+def served_summary(args, torch, bkd):
+    """The served workload as one object of the default line: saturated queries/s, p50/p99 at
+    0.5 and 0.8 of it, the plain per-request loop on the first 100 requests, a 2^16-query
+    CPU sample."""
+    r = run_served(args, torch, bkd, plain_requests=100, cpu_queries=None if args.no_cpu_baseline else 1 << 16)
+    keep = ("metric", "value", "unit", "ms_per_step", "higher_is_better", "dtype", "config", "cpu_baseline")
+    return {key: r[key] for key in keep if key in r}
 
 
 def key_capacity(k):
@@ -381,11 +441,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ondevice", choices=sorted(WORKLOADS) + ["batched", "served", "outliers"])
     ap.add_argument("--served-requests", type=int, default=2000, help="requests per open-loop level")
+    ap.add_argument("--served-age-max", type=int, default=0,
+                    help="served form: rounds after which a query leaves the rounds for a single walk (0: never)")
+    ap.add_argument("--served-tail-max", type=int, default=0,
+                    help="served form: queries in flight at or below which a round hands them to single walks "
+                         "(0: the library default)")
     ap.add_argument("--seed", type=int, default=datagen.DEFAULT_SEED)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU baseline sample size in seconds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device-to-device copy (counter calibration for profiles)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="default workload only: no streamed and served objects in the line")
+    ap.add_argument("--streamed-steps", type=int, default=2, help="timed calls of the streamed object (1 warm-up)")
+    ap.add_argument("--time-budget", type=float, default=480.0,
+                    help="seconds from start within which the streamed and served objects must fit; "
+                         "an object that would not fit is reported as skipped")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -407,18 +478,59 @@ def main():
         print(json.dumps(run_batched(args, torch, bkd)), flush=True)
         return
     if args.workload == "served":
-        print(json.dumps(run_served(args, torch, bkd)), flush=True)
+        print(json.dumps(run_served(args, torch, bkd, cpu_queries=None if args.no_cpu_baseline else 1 << 16)),
+              flush=True)
         return
     if args.workload == "outliers":
         print(json.dumps(run_outliers(args, torch, bkd)), flush=True)
         return
-    w = WORKLOADS[args.workload]
+    out = run_plain(args, torch, bkd, args.workload, args.steps, args.warmup)
+    if args.workload == "ondevice" and not args.headline_only:
+        # the other two configurations of the metric, each in an object of the same line:
+        # the bigger-than-budget (streamed) workload and the served form's latency
+        deadline = T_START + args.time_budget
+        out["streamed"] = section("streamed", deadline, 240, lambda: streamed_summary(args, torch, bkd))
+        out["served"] = section("served", deadline, 200, lambda: served_summary(args, torch, bkd))
+    print(json.dumps(out), flush=True)
+
+
+def section(name, deadline, need_s, fn):
+    """Run one extra workload of the default line if the time budget allows; a failure of
+    it is reported in its object and does not lose the headline."""
+    left = deadline - time.perf_counter()
+    if left < need_s:
+        return {"skipped": f"{left:.0f} s of the bench's time budget left, {name} needs about {need_s} s"}
+    print(f"bench: {name} workload ({left:.0f} s of the time budget left)", file=sys.stderr, flush=True)
+    try:
+        return fn()
+    except Exception as e:  # noqa: BLE001 - reported in the line, the headline stays valid
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
+def streamed_summary(args, torch, bkd):
+    """The bigger-than-budget workload (n = 2^28, m = 2^24, h = 14, 2 GB leaf budget, 12 chunks)
+    as one object: queries/s, its dense scan against the matrix peak, the host link, and the
+    streamed/resident ratio, with a 2^16-query CPU sample."""
+    r = run_plain(args, torch, bkd, "streamed", args.streamed_steps, 1, cpu_fixed=1 << 16)
+    keep = ("metric", "value", "unit", "steps", "warmup", "ms_per_step", "higher_is_better", "dtype", "config",
+            "roofline", "cpu_baseline", "stats_per_step")
+    return {key: r[key] for key in keep if key in r}
+
+
+def run_plain(args, torch, bkd, wname, steps, warmup, cpu_fixed=None):
+    """One workload of the plain query path: tree built, queries resident in HBM, `steps`
+    timed query calls after `warmup` untimed ones."""
+    w = WORKLOADS[wname]
     n, m, d, k, h = w["n"], w["m"], w["d"], w["k"], w["h"]
+    note(f"{wname}: generating inputs (n={n}, m={m}, d={d})")
     P, Q = make_inputs(w, args.seed)
+    note(f"{wname}: building the tree")
     # lock-step rounds: every active query is fetched each iteration (results do not depend on B, M)
     budget = w.get("budget", 0)
     t_build = time.perf_counter()
-    tree = bkd.build(P, h, buffer_size=-1, fetch_size=-1, flags=bkd.FLAG_TIMING, leaf_budget_bytes=budget)
+    # the streamed tree is built on the device (the same canonical tree, a third of the host's time)
+    tree = bkd.build(P, h, buffer_size=-1, fetch_size=-1, leaf_budget_bytes=budget,
+                     flags=bkd.FLAG_TIMING | (bkd.FLAG_DEVICE_BUILD if budget else 0))
     t_build = time.perf_counter() - t_build
     build = None
     if not budget:
@@ -435,22 +547,24 @@ def main():
     di = torch.empty((m, k), dtype=torch.int64, device="cuda")
     dd = torch.empty((m, k), dtype=torch.float32, device="cuda")
     stream = torch.cuda.Stream()
-    acc, wall, gpu_ms = timed_steps(bkd, torch, tree, dQ, k, di, dd, stream, args.steps, args.warmup)
+    note(f"{wname}: {warmup} warm-up and {steps} timed query calls")
+    acc, wall, gpu_ms = timed_steps(bkd, torch, tree, dQ, k, di, dd, stream, steps, warmup)
     streaming = None
     if budget:
         info = bkd.tree_info(tree)
         tree.free()
-        res = bkd.build(P, h, buffer_size=-1, fetch_size=-1)
-        racc, rwall, _ = timed_steps(bkd, torch, res, dQ, k, di, dd, stream, args.steps, args.warmup)
+        note(f"{wname}: the same tree resident")
+        res = bkd.build(P, h, buffer_size=-1, fetch_size=-1, flags=bkd.FLAG_DEVICE_BUILD)
+        racc, rwall, _ = timed_steps(bkd, torch, res, dQ, k, di, dd, stream, steps, warmup)
         res.free()
         streaming = {"leaf_budget_bytes": budget, "chunks": info.num_chunks,
                      "chunk_capacity_bytes": info.chunk_capacity_bytes, "leaf_structure_bytes": info.leaf_bytes,
-                     "bytes_h2d_per_step": acc["bytes_h2d"] // args.steps,
-                     "structure_copies_per_step": round(acc["bytes_h2d"] / args.steps / info.leaf_bytes, 3),
-                     "chunk_copies_per_step": acc["chunk_copies"] / args.steps,
+                     "bytes_h2d_per_step": acc["bytes_h2d"] // steps,
+                     "structure_copies_per_step": round(acc["bytes_h2d"] / steps / info.leaf_bytes, 3),
+                     "chunk_copies_per_step": acc["chunk_copies"] / steps,
                      "h2d_rate_gbs_achieved": round(acc["bytes_h2d"] / wall / 1e9, 2),
                      "h2d_rate_gbs_pinned_copy": round(h2d_rate_gbs(torch), 2),
-                     "resident_ms_per_step": round(rwall * 1e3 / args.steps, 3),
+                     "resident_ms_per_step": round(rwall * 1e3 / steps, 3),
                      "t_streamed_over_t_resident": round(wall / rwall, 4),
                      "schedule": "lock-step rounds, chunk sweep (each resident chunk drained before the next)"}
 
@@ -468,8 +582,8 @@ def main():
         end_to_end = {"queries_per_s": round(m / t_e2e, 1), "ms_per_call": round(t_e2e * 1e3, 3),
                       "what": "bkd_query on host arrays (Q in, idx and dist out), median of 3 calls"}
 
-    ms_per_step = wall * 1e3 / args.steps
-    value = m * args.steps / wall
+    ms_per_step = wall * 1e3 / steps
+    value = m * steps / wall
     # Dominant kernel: the dense leaf scan.  Algorithmic work per (query, leaf point) pair is
     # the float32 distance, 3d flops (d subtractions and d fused multiply-adds), counted for
     # every pair the kernel covers and set against the dense float16 matrix-core peak, the
@@ -490,17 +604,21 @@ def main():
         "peak": F16_MATRIX_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / F16_MATRIX_PEAK_TFLOPS, 4),
-        "traffic": dense_scan_traffic() if args.workload == "ondevice" else None,
+        "traffic": dense_scan_traffic() if wname == "ondevice" else None,
         "flops_per_pair": 3 * d,
         "mfma_issued_tflops": round(issued, 3),
         "mfma_flops_per_pair": mfma_flops_per_pair,
         "matrix_core_frac": round(issued / F16_MATRIX_PEAK_TFLOPS, 4),
         "avg_launch_ms": round(acc["dense_ms"] / max(acc["dense_launches"], 1), 4),
-        "launches_per_step": acc["dense_launches"] / args.steps,
+        "launches_per_step": acc["dense_launches"] / steps,
         "pairs_per_launch": acc["dense_pairs"] // max(acc["dense_launches"], 1),
+        # algorithmic bytes of the dense scan (every buffered leaf once per call, per visit the
+        # query, its key list read and written, its buffer entry) and their rate: the HBM side
+        "alg_bytes_per_launch": acc["alg_bytes_dense"] // max(acc["dense_launches"], 1),
+        "alg_gbs": round(acc["alg_bytes_dense"] / dense_s / 1e9, 1) if dense_s > 0 else 0.0,
         "share_of_step": round(acc["dense_ms"] / max(gpu_ms, 1e-9), 4),
         # the library's sparse timer also covers the tail hand-over launch
-        "sparse_and_tail": {"launches_per_step": acc["sparse_launches"] / args.steps,
+        "sparse_and_tail": {"launches_per_step": acc["sparse_launches"] / steps,
                         "avg_launch_ms": round(acc["sparse_ms"] / max(acc["sparse_launches"], 1), 4),
                         "tflops": round(3.0 * d * acc["sparse_pairs"] / max(acc["sparse_ms"] * 1e-3, 1e-12) / 1e12, 3),
                         "share_of_step": round(acc["sparse_ms"] / max(gpu_ms, 1e-9), 4)},
@@ -510,30 +628,36 @@ def main():
         "value": round(value, 1),
         "unit": "queries/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: n={n} m={m} d={d} k={k} height={h} "
+        "config": {"workload": f"{wname}: n={n} m={m} d={d} k={k} height={h} "
                                f"{'16-component Gaussian mixture' if w['kind'] == 'mixture' else 'uniform [0,1]^d'}, "
                                f"seed {args.seed}, lock-step rounds"
                                + (f", leaf structure streamed through a {budget / 1e9:g} GB budget" if budget else ""),
-                   "n": n, "m": m, "d": d, "k": k, "height": h, "rounds_per_step": acc["calls"] / args.steps,
+                   "n": n, "m": m, "d": d, "k": k, "height": h, "rounds_per_step": acc["calls"] / steps,
                    "streaming": streaming,
-                   "pairs_per_query": acc["pairs"] / (args.steps * m)},
+                   "pairs_per_query": acc["pairs"] / (steps * m)},
         "roofline": roofline,
         "end_to_end": end_to_end,
         "build": build,
+        "stats_per_step": {key: (round(acc[key] / steps, 3) if key.endswith("_ms") else acc[key] // steps)
+                           for key in ("calls", "visits", "pairs", "alg_bytes", "find_ms", "group_ms", "dense_ms",
+                                       "sparse_ms", "copy_ms", "wait_ms")},
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(P, Q, k, args.cpu_seconds)
     if not budget:
         tree.free()
-    print(json.dumps(out), flush=True)
+    del dQ, di, dd
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        note(f"{wname}: CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(P, Q, k, args.cpu_seconds, fixed=cpu_fixed)
+    return out
 
 
 if __name__ == "__main__":

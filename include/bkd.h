@@ -63,6 +63,21 @@ extern "C" {
                                  /* level (the same canonical tree as the host build, Section 2.3); */
                                  /* needs about 8d + 32 bytes of device memory per point meanwhile  */
 
+/* Splitting rule and pruning bound of the tree (Section 2.3).  The original k-d tree splits
+   dimension (level mod d) and prunes with the splitting hyperplane; the footnote on splitting
+   rules names the longest side as an alternative, and the bounding box of a subtree's points
+   bounds its distances more tightly than the hyperplane.  Results are the same for every rule
+   and bound (exact kNN); the leaves a query visits differ. */
+#define BKD_SPLIT_CYCLIC 0  /* dimension (level mod d)                                        */
+#define BKD_SPLIT_LONGEST 1 /* the longest side of the bounding box of the node's points:      */
+                            /* the j with the largest float32 fl32(max_j - min_j), smaller j    */
+                            /* on ties; median split as in the original rule                    */
+#define BKD_PRUNE_PLANE 0   /* enter the far child iff fl32(q[dim] - s)^2 <= current k-th d2     */
+#define BKD_PRUNE_BOX 1     /* enter it iff its box term <= current k-th d2: g_j = fl32 distance */
+                            /* of q_j to the far child's [min_j, max_j] (0 inside), accumulated */
+                            /* acc = fma(g_j, g_j, acc) from +0 as the distance is; never above */
+                            /* the float32 distance of a point in the box, never below the plane */
+
 typedef struct bkd_tree bkd_tree;
 
 /*
@@ -95,6 +110,24 @@ typedef struct bkd_tree bkd_tree;
  *                 (each query walks on while its next leaf is in the chunk).
  *                 0: the default (32768); < 0: rounds to the end (as
  *                 BKD_FLAG_NO_TAIL).
+ *   split_rule    BKD_SPLIT_CYCLIC (0) or BKD_SPLIT_LONGEST (host build only:
+ *                 BKD_FLAG_DEVICE_BUILD with BKD_SPLIT_LONGEST is BKD_EINVAL).
+ *   prune         BKD_PRUNE_PLANE (0) or BKD_PRUNE_BOX; the boxes take
+ *                 (2^(h+1) - 1) 8d bytes of device memory.
+ *   leaf_path     NULL: a streamed leaf structure is kept in pinned host
+ *                 memory.  Otherwise the path of a file the library creates
+ *                 (truncating any file there), writes the streamed structure
+ *                 to (leaf-block layout, (4d + 4) n bytes) and removes at
+ *                 bkd_free, for a reference set whose structure does not fit
+ *                 in host memory (Section 3.2, last paragraph of "Processing
+ *                 the Leaf Structure").  Chunks then travel disk -> pinned
+ *                 staging buffer -> device in three overlapped stages: a
+ *                 reader thread fills one of two staging buffers (direct I/O
+ *                 where the file system allows it) while the other's copy to
+ *                 the device and the scans of the resident chunk run.  Host
+ *                 memory: two staging buffers of the chunk capacity.  Only
+ *                 used when the structure is streamed (leaf_budget_bytes or
+ *                 num_chunks).  The path is copied.
  * Results are identical for every value of these options.
  */
 typedef struct bkd_options {
@@ -106,6 +139,9 @@ typedef struct bkd_options {
     int32_t device;
     int32_t flags;
     int64_t tail_max;
+    int32_t split_rule;
+    int32_t prune;
+    const char *leaf_path;
 } bkd_options;
 
 /* Static facts of a built tree. */
@@ -119,6 +155,8 @@ typedef struct bkd_tree_info {
     int32_t resident;     /* 1: leaf structure lives on the device             */
     int64_t leaf_bytes;   /* bytes of the leaf structure (points + indices)    */
     int64_t chunk_capacity_bytes; /* bytes of one device chunk buffer          */
+    int32_t on_disk;      /* 1: the streamed structure is read from leaf_path      */
+    int32_t direct_io;    /* 1: reads bypass the page cache (O_DIRECT)             */
 } bkd_tree_info;
 
 /* Counters of the last query on a tree. */
@@ -154,7 +192,10 @@ typedef struct bkd_stats {
                             /* sweep redistribution                                   */
     double copy_ms;         /* host-to-device chunk copies (streamed structures)     */
     double wait_ms;         /* host time spent waiting for the device (readbacks and */
-                            /* synchronisations inside the call), always measured     */
+                            /* synchronisations inside the call) or for chunk reads   */
+                            /* from a leaf file, always measured                     */
+    int64_t bytes_disk;     /* bytes read from the leaf file (leaf_path), aligned reads */
+    double disk_ms;         /* time the reader thread spent in those reads            */
 } bkd_stats;
 
 /* Thread-local description of the last error on this thread ("" if none). */
@@ -265,6 +306,16 @@ int bkd_tree_info_get(const bkd_tree *tree, bkd_tree_info *out);
  * Any pointer may be NULL to skip that array.
  */
 int bkd_tree_export(const bkd_tree *tree, float *split, int64_t *leaf_off, int32_t *perm);
+
+/*
+ * The tree's splitting dimensions and node boxes: dims [2^h - 1] receives the
+ * dimension of every internal node (heap order; level mod d under
+ * BKD_SPLIT_CYCLIC); box [(2^(h+1) - 1) * 2d], heap order over all nodes
+ * (internal, then leaves), node v's minima at box[v*2d .. v*2d + d) and maxima
+ * after them, is filled for a tree built with BKD_PRUNE_BOX (BKD_EINVAL
+ * otherwise).  Either pointer may be NULL.
+ */
+int bkd_tree_rules_export(const bkd_tree *tree, int32_t *dims, float *box);
 
 /* Chunk bounds (positions [lo[j], hi[j])) of the streaming plan; num_chunks entries. */
 int bkd_chunk_plan(const bkd_tree *tree, int64_t *lo, int64_t *hi);
@@ -384,6 +435,11 @@ typedef struct bkd_server_opts {
     int32_t max_requests;      /* requests in flight per session; 0: 4096                        */
     int32_t device;            /* HIP device of the server (trees must live there)               */
     int32_t flags;             /* BKD_FLAG_SQUARED or 0                                          */
+    int32_t age_max;           /* > 0: a query still travelling after this many rounds leaves     */
+                               /* the rounds and walks the rest of its traversal alone (one       */
+                               /* workgroup), so long walks do not hold a request; 0: never       */
+    int64_t tail_max;          /* a round with at most this many queries in flight hands them    */
+                               /* all to single walks; 0: 16384; < 0: never                       */
 } bkd_server_opts;
 
 typedef struct bkd_server bkd_server;
@@ -428,6 +484,10 @@ typedef struct bkd_server_stats {
     double busy_s;          /* host wall time inside rounds, summed over sessions             */
     double admit_s;         /* host wall time admitting requests (copies in), summed          */
     double complete_s;      /* host wall time delivering results (copies out), summed         */
+    int64_t direct_launches;/* launches of the direct path: requests of at most 2048 queries  */
+                            /* skip the rounds, each query walking its whole traversal in one */
+                            /* workgroup right after admission                                 */
+    int64_t aged_queries;   /* queries handed from the rounds to single walks (age_max)       */
 } bkd_server_stats;
 
 int bkd_server_stats_get(bkd_server *srv, bkd_server_stats *out);

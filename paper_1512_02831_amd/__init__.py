@@ -21,6 +21,8 @@ OK, EINVAL, ENOMEM, EBUDGET, EDEVICE, EBUSY, ETIMEOUT, ENOTFOUND = 0, -1, -2, -3
 CHUNK_LEAF, CHUNK_POSITION = 0, 1
 FLAG_TRACE, FLAG_TIMING, FLAG_SQUARED, FLAG_NO_TAIL, FLAG_DEVICE_BUILD = 1, 2, 4, 8, 16
 MAX_DIM, MAX_K, MAX_HEIGHT = 32, 64, 24
+SPLIT_CYCLIC, SPLIT_LONGEST = 0, 1
+PRUNE_PLANE, PRUNE_BOX = 0, 1
 
 _lib = None
 
@@ -35,14 +37,15 @@ class Options(ctypes.Structure):
     _fields_ = [("buffer_size", ctypes.c_int64), ("fetch_size", ctypes.c_int64),
                 ("leaf_budget_bytes", ctypes.c_int64), ("chunk_mode", ctypes.c_int32),
                 ("num_chunks", ctypes.c_int32), ("device", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("tail_max", ctypes.c_int64)]
+                ("tail_max", ctypes.c_int64), ("split_rule", ctypes.c_int32), ("prune", ctypes.c_int32),
+                ("leaf_path", ctypes.c_char_p)]
 
 
 class TreeInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("height", ctypes.c_int32),
                 ("buffer_size", ctypes.c_int64), ("fetch_size", ctypes.c_int64), ("num_chunks", ctypes.c_int32),
                 ("resident", ctypes.c_int32), ("leaf_bytes", ctypes.c_int64),
-                ("chunk_capacity_bytes", ctypes.c_int64)]
+                ("chunk_capacity_bytes", ctypes.c_int64), ("on_disk", ctypes.c_int32), ("direct_io", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -54,7 +57,8 @@ class Stats(ctypes.Structure):
                 ("dense_visits", ctypes.c_int64), ("leaf_points_dense", ctypes.c_int64),
                 ("leaf_points_other", ctypes.c_int64), ("alg_bytes", ctypes.c_int64),
                 ("alg_bytes_dense", ctypes.c_int64), ("find_ms", ctypes.c_double), ("group_ms", ctypes.c_double),
-                ("copy_ms", ctypes.c_double), ("wait_ms", ctypes.c_double)]
+                ("copy_ms", ctypes.c_double), ("wait_ms", ctypes.c_double), ("bytes_disk", ctypes.c_int64),
+                ("disk_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -75,6 +79,7 @@ _PROTOS = {
     "bkd_tree_info_get": (ctypes.c_int, [_V, _V]),
     "bkd_tree_export": (ctypes.c_int, [_V, _V, _V, _V]),
     "bkd_chunk_plan": (ctypes.c_int, [_V, _V, _V]),
+    "bkd_tree_rules_export": (ctypes.c_int, [_V, _V, _V]),
     "bkd_last_stats": (ctypes.c_int, [_V, _V]),
     "bkd_trace_size": (ctypes.c_int, [_V, _V, _V]),
     "bkd_trace_get": (ctypes.c_int, [_V, _V, _V, _V]),
@@ -141,11 +146,15 @@ def default_options(height: int) -> Options:
 
 
 def make_options(height: int, buffer_size=None, fetch_size=None, leaf_budget_bytes=None, chunk_mode=None,
-                 num_chunks=None, device=None, flags=None, tail_max=None) -> Options:
+                 num_chunks=None, device=None, flags=None, tail_max=None, split_rule=None, prune=None,
+                 leaf_path=None) -> Options:
     o = default_options(height)
+    if leaf_path is not None:
+        o.leaf_path = os.fsencode(leaf_path)
     for name, val in (("buffer_size", buffer_size), ("fetch_size", fetch_size),
                       ("leaf_budget_bytes", leaf_budget_bytes), ("chunk_mode", chunk_mode),
-                      ("num_chunks", num_chunks), ("device", device), ("flags", flags), ("tail_max", tail_max)):
+                      ("num_chunks", num_chunks), ("device", device), ("flags", flags), ("tail_max", tail_max),
+                      ("split_rule", split_rule), ("prune", prune)):
         if val is not None:
             setattr(o, name, val)
     return o
@@ -248,6 +257,16 @@ def query_async_noalloc(tree: Tree, dQ, k: int, d_idx, d_dist, stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     _check(lib().bkd_query_async_noalloc(tree.handle, dQ.data_ptr(), m, k, d_idx.data_ptr(), d_dist.data_ptr(),
                                          ctypes.c_void_p(s.cuda_stream)))
+
+
+def tree_rules_export(tree: Tree, boxes: bool = False):
+    """(dims [2^h-1] int32, boxes [2^(h+1)-1, 2, d] float32 or None) of a tree: every internal
+    node's splitting dimension and, for a tree built with PRUNE_BOX, every node's box."""
+    nleaf = 1 << tree.height
+    dims = np.zeros(max(nleaf - 1, 1), dtype=np.int32)
+    box = np.zeros((2 * nleaf - 1, 2, tree.d), dtype=np.float32) if boxes else None
+    _check(lib().bkd_tree_rules_export(tree.handle, _p(dims), _p(box) if boxes else None))
+    return dims[: nleaf - 1], box
 
 
 def tree_info(tree: Tree) -> TreeInfo:
@@ -396,7 +415,7 @@ REQ_WAITING, REQ_RUNNING, REQ_DONE, REQ_CANCELLED = 0, 1, 2, 3
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("slots_per_session", ctypes.c_int64), ("max_requests", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("age_max", ctypes.c_int32), ("tail_max", ctypes.c_int64)]
 
 
 class Request:
@@ -444,8 +463,9 @@ class Server:
         self.destroy()
 
 
-def server_create(slots_per_session: int = 0, max_requests: int = 0, device: int = 0, flags: int = 0) -> Server:
-    o = ServerOpts(slots_per_session, max_requests, device, flags)
+def server_create(slots_per_session: int = 0, max_requests: int = 0, device: int = 0, flags: int = 0,
+                  age_max: int = 0, tail_max: int = 0) -> Server:
+    o = ServerOpts(slots_per_session, max_requests, device, flags, age_max, tail_max)
     h = ctypes.c_void_p()
     _check(lib().bkd_server_create(ctypes.byref(o), ctypes.byref(h)))
     return Server(h.value)
@@ -495,7 +515,8 @@ def cancel(srv: Server, req):
 class ServerStats(ctypes.Structure):
     _fields_ = [("sessions", ctypes.c_int32), ("rounds", ctypes.c_int64), ("scan_rounds", ctypes.c_int64),
                 ("tail_rounds", ctypes.c_int64), ("queries", ctypes.c_int64), ("busy_s", ctypes.c_double),
-                ("admit_s", ctypes.c_double), ("complete_s", ctypes.c_double)]
+                ("admit_s", ctypes.c_double), ("complete_s", ctypes.c_double), ("direct_launches", ctypes.c_int64),
+                ("aged_queries", ctypes.c_int64)]
 
 
 def server_stats(srv: Server) -> dict:

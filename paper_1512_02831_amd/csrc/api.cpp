@@ -111,6 +111,7 @@ int bkd_build(const float *P, int64_t n, int32_t d, int32_t height, const bkd_op
     });
     if (rc != BKD_OK) {
         if (tree) {
+            bkd::leaffile_destroy(tree->t);
             if (tree->stream) (void)hipStreamDestroy(tree->stream);
             if (tree->t.copy_stream) (void)hipStreamDestroy(tree->t.copy_stream);
             delete tree;
@@ -125,6 +126,7 @@ int bkd_free(bkd_tree *tree)
         if (!tree) return;
         (void)hipSetDevice(tree->t.device);
         (void)hipDeviceSynchronize();
+        bkd::leaffile_destroy(tree->t);
         if (tree->stream) (void)hipStreamDestroy(tree->stream);
         if (tree->t.copy_stream) (void)hipStreamDestroy(tree->t.copy_stream);
         for (int b = 0; b < 2; b++) {
@@ -185,6 +187,8 @@ int bkd_tree_info_get(const bkd_tree *tree, bkd_tree_info *out)
         out->resident = t.resident ? 1 : 0;
         out->leaf_bytes = t.host.n * (int64_t)(4 * t.host.d + 4);
         out->chunk_capacity_bytes = (int64_t)t.chunk_cap_bytes;
+        out->on_disk = t.leaf_file ? 1 : 0;
+        out->direct_io = bkd::leaffile_direct(t) ? 1 : 0;
     });
 }
 
@@ -196,6 +200,25 @@ int bkd_tree_export(const bkd_tree *tree, float *split, int64_t *leaf_off, int32
         if (split && !H.split.empty()) std::memcpy(split, H.split.data(), sizeof(float) * H.split.size());
         if (leaf_off) std::memcpy(leaf_off, H.leaf_off.data(), sizeof(int64_t) * H.leaf_off.size());
         if (perm) std::memcpy(perm, H.perm.data(), sizeof(int32_t) * H.perm.size());
+    });
+}
+
+int bkd_tree_rules_export(const bkd_tree *tree, int32_t *dims, float *box)
+{
+    return guarded([&] {
+        require(tree != nullptr, "tree is NULL");
+        const bkd::HostTree &H = tree->t.host;
+        if (dims) {
+            for (size_t v = 0; v < H.split.size(); v++) {
+                int level = 0;
+                while ((size_t(2) << level) <= v + 1) level++;
+                dims[v] = H.dims.empty() ? level % H.d : (int32_t)H.dims[v];
+            }
+        }
+        if (box) {
+            require(!H.box.empty(), "the tree was built without BKD_PRUNE_BOX (no node boxes)");
+            std::memcpy(box, H.box.data(), sizeof(float) * H.box.size());
+        }
     });
 }
 

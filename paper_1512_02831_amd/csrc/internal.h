@@ -69,10 +69,16 @@ struct HostTree {
     std::vector<float> split;      // 2^h - 1
     std::vector<int64_t> leaf_off; // 2^h + 1
     std::vector<int32_t> perm;     // n
+    std::vector<uint8_t> dims;     // 2^h - 1 splitting dimensions (BKD_SPLIT_LONGEST); empty: level mod d
+    std::vector<float> box;        // (2^(h+1) - 1) x 2d node boxes (BKD_PRUNE_BOX); empty: plane pruning
 };
 
-// Build the canonical tree of P (row-major n x d); parallel = use the host thread pool.
-void build_canonical(const float *P, int64_t n, int d, int h, HostTree &t, bool parallel = true);
+// Build the canonical tree of P (row-major n x d) under a splitting rule (BKD_SPLIT_*);
+// parallel = use the host thread pool.
+void build_canonical(const float *P, int64_t n, int d, int h, HostTree &t, bool parallel = true,
+                     int rule = BKD_SPLIT_CYCLIC);
+// Bounding boxes of every node's points (HostTree::box) from the built tree.
+void build_boxes(const float *P, HostTree &t);
 // The same tree built on the current device (one segmented sort per level); blocking on s.
 void build_canonical_device(const float *P, int64_t n, int d, int h, HostTree &t, hipStream_t s);
 
@@ -103,6 +109,7 @@ enum Ctl : int {
     CTL_LPD_LO = 12,     // points of the leaves scanned densely, each leaf once per call
     CTL_LPS_LO = 14,     // points of the leaves scanned sparsely, and the tail's leaf reads
     CTL_DVISITS_LO = 16, // visits scanned densely
+    CTL_AGED = 18,       // served form: routed queries handed to the tail for their age
     CTL_WORDS = 24
 };
 
@@ -111,6 +118,25 @@ enum Ctl : int {
 constexpr int SCAN_QT = 256;
 constexpr int SCAN_DENSE_MIN = 32;
 
+// Disk-backed leaf structure (bkd_options.leaf_path): chunks are read from the
+// file into two pinned staging buffers by a reader thread, then copied to the
+// device chunk buffers (leaffile.cpp).
+struct LeafFile;
+void leaffile_create(struct Tree &t, const float *P, const char *path);
+void leaffile_destroy(struct Tree &t);
+// Ask for chunk j to be read ahead (no-op if it is already read, being read, or no
+// staging buffer is free).
+void leaffile_prefetch(struct Tree &t, int j);
+// Copy chunk j to device buffer dst on stream s (after the copy stream waits for
+// `after`): waits until the chunk is in a staging buffer, queues the copy, and
+// releases the staging buffer once the copy completes.  Returns the host wait in ms.
+double leaffile_copy(struct Tree &t, int j, void *dst, hipStream_t s);
+// Bytes read and milliseconds spent reading since the last call (per query statistics).
+void leaffile_take_stats(struct Tree &t, int64_t *bytes, double *ms);
+bool leaffile_direct(const struct Tree &t);
+// Write the blocks of leaves [lf, ll] of P's leaf structure to dst (word 0 = first word of leaf lf).
+void gather_leaves(const float *P, const struct Tree &t, int lf, int ll, void *dst);
+
 struct Tree {
     HostTree host;
     bkd_options opt{};
@@ -118,21 +144,26 @@ struct Tree {
     int device = 0;
     int nleaf = 1;
 
-    // device top tree and leaf bounds
-    DevBuf d_split, d_leaf_off;
+    // device top tree and leaf bounds; per-node dimensions and boxes of a variant tree
+    DevBuf d_split, d_leaf_off, d_dims, d_box;
 
     // leaf structure
     std::vector<int64_t> leaf_blk; // [nleaf+1] word offsets of the leaf blocks
     DevBuf d_leaf_blk;
     DevBuf d_centers;              // [nleaf][d] float32 bounding-box midpoints, then [nleaf] leaf scales
     bool resident = true;
+    // buffers of at least this many queries go to the dense scan: SCAN_DENSE_MIN, or never
+    // (INT32_MAX) when a leaf holds 2^30 points or more (the dense scan addresses a leaf's
+    // rows with 32-bit byte offsets)
+    int dense_min = SCAN_DENSE_MIN;
     bool wide = false;             // a reference coordinate beyond +-FILTER_RANGE
     bool sweep = false;            // streaming with the chunk-sweep schedule
     std::vector<Chunk> chunks;
     size_t chunk_cap_bytes = 0;
     DevBuf d_chunk[2];     // resident: d_chunk[0] holds everything
     int chunk_in[2] = {-1, -1};
-    PinnedBuf h_leaf;      // streaming: pinned host copy of the leaf structure
+    PinnedBuf h_leaf;      // streaming: pinned host copy of the leaf structure (no leaf file)
+    LeafFile *leaf_file = nullptr;  // streaming from a file (leaf_path), else null
     hipStream_t copy_stream = nullptr;
     hipEvent_t ev_copied[2] = {nullptr, nullptr};
     hipEvent_t ev_used[2] = {nullptr, nullptr};
@@ -146,6 +177,10 @@ struct Tree {
     DevBuf d_chunk_of, d_rleaf, d_rq, d_rcnt;  // chunk sweep: leaf -> chunk, per-chunk pending regions
     PinnedBuf h_rcnt;
     PinnedBuf h_ctl, h_tiles;  // h_tiles: dense tiles, sparse items, buffer offsets (3 x (nleaf+1))
+
+    // variant-tree arrays on the device, or null under the original rules
+    const uint8_t *dims_dev() const { return host.dims.empty() ? nullptr : d_dims.as<uint8_t>(); }
+    const float *boxes_dev() const { return host.box.empty() ? nullptr : d_box.as<float>(); }
 
     // results of the last query
     bkd_stats stats{};
@@ -170,6 +205,15 @@ struct FetchSpec {
     // those from the sorted list instead (count_leaves false: no atomics).
     bool track_fill = false;
     bool count_leaves = true;
+    // variant tree (Section 2.3): per-node splitting dimensions (null: level mod d) and node
+    // boxes for the pruning test (null: the splitting hyperplane)
+    const uint8_t *dims = nullptr;
+    const float *boxes = nullptr;
+    // served form: rounds each query has been routed (null: not tracked); a query routed more
+    // than age_max times leaves the rounds: its entry gets the key 2^h + 1 (sorted after the
+    // finished ones) and it is counted in ctl[CTL_AGED]
+    int32_t *age = nullptr;
+    int32_t age_max = 0;
 };
 
 void launch_init_state(int32_t *node, uint64_t *keys, uint32_t *kth, int64_t m, int K, hipStream_t s);
@@ -246,6 +290,7 @@ struct ScanArgs {
     int32_t tail_count;
     int tail_counted;         // the first visit of each tail entry is already in the work counters
     int tail_wide;            // tail workgroups of 512 lanes (leaves of TAIL_WIDE_LEAF points and more)
+    int tail_from_node;       // each tail entry starts at the leaf in node[q] (tail_leaf unused)
     int32_t *node;            // [m] traversal state, set to DONE at the end
     const float *split;       // [2^h - 1]
     int h, k;                 // tree height; k of the query (pruning uses the k-th key)
@@ -255,6 +300,9 @@ struct ScanArgs {
     const int32_t *req_of;
     int32_t *req_left;
     int32_t *done_list;
+    // variant tree: per-node splitting dimensions and node boxes (null: the original rules)
+    const uint8_t *dims;
+    const float *boxes;
 };
 
 // Default number of pending queries at or below which the lock-step rounds hand over to

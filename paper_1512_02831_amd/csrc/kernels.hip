@@ -89,7 +89,9 @@ __global__ __launch_bounds__(256) void k_find_leaf(FetchSpec f, const float *__r
         const float *qp = Q + (int64_t)q * d;
         const int32_t st = node[q];
         int32_t v;
-        if (d <= FIND_LDS_DIMS) {
+        if (f.dims || f.boxes) {
+            v = next_leaf_rules(st, qp, kth + q, split, f.dims, f.boxes, h, d);
+        } else if (d <= FIND_LDS_DIMS) {
             float *ql = q_lds + threadIdx.x;
             for (int c = 0; c < d; c++) ql[c * 256] = qp[c];
             v = next_leaf(st, ql, kth + q, split, split_lds, lds_nodes, h, d, 256);
@@ -103,9 +105,14 @@ __global__ __launch_bounds__(256) void k_find_leaf(FetchSpec f, const float *__r
             if (atomicSub(&f.req_left[r], 1) == 1) f.done_list[1 + atomicAdd(&f.done_list[0], 1)] = r;
         }
         leaf = (v >= 0) ? (uint32_t)(v - first) : nleaf;
+        if (f.age && v >= 0 && ++f.age[q] > f.age_max) {
+            // a long traversal leaves the rounds: the tail walks it to its end from node[q]
+            leaf = nleaf + 1;
+            atomicAdd(&ctl[CTL_AGED], 1);
+        }
         pend_leaf[pend_base + j] = leaf;
         pend_q[pend_base + j] = q;
-        valid = v >= 0;
+        valid = leaf < nleaf;
     }
     // Buffer fills: lanes bound for the same leaf are counted with one atomic
     // (fetched queries arrive grouped by their previous leaf, so a wave holds

@@ -311,35 +311,39 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
 
     // Staging: thread t brings point t of a tile; the next tile's coordinates
     // are loaded into registers while the current tile is scanned.
+    const int first_pt = (int)(p0 - l0);  // a valid point of this item (clamped loads stay in the chunk)
     float pre[DS], cr[DS];
     int32_t pre_o = 0;
 #pragma unroll
     for (int j = 0; j < DS; j++) cr[j] = (j < a.d) ? cen[j] : 0.0f;
-    // A uniform base (the tile's first point in each row, 64-bit) plus one small
-    // 32-bit byte offset per thread: the loads take the scalar-base form, so the
-    // scan below never has to wait for them before reusing an address register,
-    // and no per-thread offset grows with the leaf.
+    // A column base (uniform, 64-bit) plus one 32-bit byte offset per thread: the
+    // loads take the scalar-base form, so the scan below never has to wait for
+    // them before reusing an address register.  The offset 4 i stays below 2^32
+    // because leaves of 2^30 points and more never reach this kernel (the host
+    // scans them with the sparse and tail kernels).
     auto at = [](const void *base, uint32_t bo) {
         return reinterpret_cast<const char *>(base) + bo;
     };
     auto load_tile = [&](int64_t pt) {
         if (PT < SCAN_THREADS && tid >= PT) return;
         const int np = (int)min((int64_t)PT, p1 - pt);
-        // rows past the tile load the tile's first point (valid in the chunk); they are never read as points
-        const uint32_t bo = (uint32_t)(tid < np ? tid : 0) * 4u;
-        const float *Xt = X + (pt - l0);
+        // rows past the tile load a valid point of the item; they are never read as points
+        const int i = tid < np ? (int)(pt - l0) + tid : first_pt;
         if (a.d == D) {
+            const uint32_t bo = (uint32_t)i * 4u;
 #pragma unroll
             for (int j = 0; j < DS; j++)
-                pre[j] = (j < D) ? *reinterpret_cast<const float *>(at(Xt + (int64_t)(j < D ? j : 0) * len, bo)) : 0.0f;
+                pre[j] = (j < D) ? *reinterpret_cast<const float *>(at(X + (int64_t)(j < D ? j : 0) * len, bo)) : 0.0f;
         } else {
+            // a padded dimension: the plain indexed form (a common form for both branches
+            // made the compiler give up the scalar-base loads above, 7% slower)
 #pragma unroll
             for (int j = 0; j < DS; j++) {
-                const float x = *reinterpret_cast<const float *>(at(Xt + (int64_t)(j < a.d ? j : 0) * len, bo));
+                const float x = X[(int64_t)(j < a.d ? j : 0) * len + i];
                 pre[j] = (j < a.d) ? x : 0.0f;
             }
         }
-        pre_o = *reinterpret_cast<const int32_t *>(at(orig + (pt - l0), bo));
+        pre_o = *reinterpret_cast<const int32_t *>(at(orig, (uint32_t)i * 4u));
     };
     // Every load issued so far (the query, its list) is complete here: without this
     // the compiler keeps a wait for them inside the re-check path, which then also
@@ -454,6 +458,8 @@ __global__ __launch_bounds__(SCAN_THREADS, 4) void k_leaf_scan(ScanArgs a)
         __syncthreads();
         if (act) {
             const int32_t first = (1 << a.h) - 1;
+            // (only trees with the original rules route here: a variant tree's rounds route with
+            // FindLeafBatch, which keeps this kernel's code and registers as they are)
             const int32_t v = QL ? next_leaf(first + L, qlds + tid, &kb, a.split, route_splits, lds_nodes, a.h, a.d,
                                              SCAN_THREADS)
                                  : next_leaf(first + L, a.Q + (int64_t)q * a.d, &kb, a.split, route_splits,
@@ -556,7 +562,8 @@ template <int D, int K> __global__ __launch_bounds__(SCAN_THREADS) void k_leaf_s
         // next leaf of the query (the FindLeafBatch step of the next round), walked by every lane alike
         const uint32_t kb = (uint32_t)(readlane_u64(li, kk - 1) >> 32);
         const int32_t first = (1 << a.h) - 1;
-        const int32_t v = next_leaf(first + L, qp, &kb, a.split, a.split, 0, a.h, a.d);
+        const int32_t v = (a.dims || a.boxes) ? next_leaf_rules(first + L, qp, &kb, a.split, a.dims, a.boxes, a.h, a.d)
+                                              : next_leaf(first + L, qp, &kb, a.split, a.split, 0, a.h, a.d);
         if (lane == 0) {
             a.node[q] = v;
             a.route_leaf[a.off[L] + (s - a.sparse[L])] = v >= 0 ? (uint32_t)(v - first) : (uint32_t)(1 << a.h);
@@ -604,7 +611,7 @@ template <int D, int K, int TT> __global__ __launch_bounds__(TT) void k_tail(Sca
 
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int32_t q = a.tail_q[blockIdx.x];
-    int32_t leaf = (int32_t)a.tail_leaf[blockIdx.x];
+    int32_t leaf = a.tail_from_node ? a.node[q] - ((1 << a.h) - 1) : (int32_t)a.tail_leaf[blockIdx.x];
     const float *qp = a.Q + (int64_t)q * a.d;
     if (threadIdx.x < D) q_lds[threadIdx.x] = (threadIdx.x < a.d) ? qp[threadIdx.x] : 0.0f;
     __syncthreads();
@@ -683,7 +690,9 @@ template <int D, int K, int TT> __global__ __launch_bounds__(TT) void k_tail(Sca
         }
         visits_seen++;
         const uint64_t kth_key = readlane_u64(li, kk - 1);
-        const int32_t v = next_leaf(first + leaf, q_lds, &kth_key, a.split, split_lds, lds_nodes, h, a.d);
+        const int32_t v = (a.dims || a.boxes)
+                              ? next_leaf_rules(first + leaf, q_lds, &kth_key, a.split, a.dims, a.boxes, h, a.d)
+                              : next_leaf(first + leaf, q_lds, &kth_key, a.split, split_lds, lds_nodes, h, a.d);
         if (v == NODE_DONE) break;
         leaf = v - first;
         if (a.route_leaf && (leaf < a.leaf_first || leaf > a.leaf_last)) {

@@ -128,7 +128,7 @@ static void plan_chunks(Tree &t)
 }
 
 // Write the blocks of leaves [lf, ll] to dst (word 0 = first word of leaf lf).
-static void gather_leaves(const float *P, const Tree &t, int lf, int ll, void *dst)
+void gather_leaves(const float *P, const Tree &t, int lf, int ll, void *dst)
 {
     const HostTree &H = t.host;
     const int d = H.d;
@@ -159,10 +159,19 @@ void tree_build(Tree &t, const float *P, int64_t n, int d, int h, const bkd_opti
     if (opt.fetch_size == 0) t.M = t.B > 0 ? 10 * t.B : -1;
     else t.M = opt.fetch_size < 0 ? -1 : opt.fetch_size;
 
+    if (opt.split_rule != BKD_SPLIT_CYCLIC && opt.split_rule != BKD_SPLIT_LONGEST)
+        fail(BKD_EINVAL, "split_rule must be BKD_SPLIT_CYCLIC or BKD_SPLIT_LONGEST");
+    if (opt.prune != BKD_PRUNE_PLANE && opt.prune != BKD_PRUNE_BOX)
+        fail(BKD_EINVAL, "prune must be BKD_PRUNE_PLANE or BKD_PRUNE_BOX");
+    if ((opt.flags & BKD_FLAG_DEVICE_BUILD) && opt.split_rule != BKD_SPLIT_CYCLIC)
+        fail(BKD_EINVAL, "the device build supports the cyclic splitting rule only");
     if (opt.flags & BKD_FLAG_DEVICE_BUILD) build_canonical_device(P, n, d, h, t.host, nullptr);
-    else build_canonical(P, n, d, h, t.host);
+    else build_canonical(P, n, d, h, t.host, true, opt.split_rule);
+    if (opt.prune == BKD_PRUNE_BOX) build_boxes(P, t.host);
     plan_chunks(t);
     t.sweep = !t.resident && t.opt.chunk_mode == BKD_CHUNK_LEAF;
+    for (int l = 0; l < t.nleaf; l++)
+        if (t.host.leaf_off[(size_t)l + 1] - t.host.leaf_off[(size_t)l] >= (int64_t(1) << 30)) t.dense_min = INT32_MAX;
 
     const HostTree &H = t.host;
     t.d_split.ensure(sizeof(float) * std::max<size_t>(1, H.split.size()));
@@ -172,6 +181,14 @@ void tree_build(Tree &t, const float *P, int64_t n, int d, int h, const bkd_opti
     for (size_t i = 0; i < lo32.size(); i++) lo32[i] = (int32_t)H.leaf_off[i];
     t.d_leaf_off.ensure(sizeof(int32_t) * lo32.size());
     BKD_HIP(hipMemcpy(t.d_leaf_off.p, lo32.data(), sizeof(int32_t) * lo32.size(), hipMemcpyHostToDevice));
+    if (!H.dims.empty()) {
+        t.d_dims.ensure(H.dims.size());
+        BKD_HIP(hipMemcpy(t.d_dims.p, H.dims.data(), H.dims.size(), hipMemcpyHostToDevice));
+    }
+    if (!H.box.empty()) {
+        t.d_box.ensure(sizeof(float) * H.box.size());
+        BKD_HIP(hipMemcpy(t.d_box.p, H.box.data(), sizeof(float) * H.box.size(), hipMemcpyHostToDevice));
+    }
     t.d_leaf_blk.ensure(sizeof(int64_t) * t.leaf_blk.size());
     BKD_HIP(hipMemcpy(t.d_leaf_blk.p, t.leaf_blk.data(), sizeof(int64_t) * t.leaf_blk.size(), hipMemcpyHostToDevice));
     {
@@ -218,8 +235,12 @@ void tree_build(Tree &t, const float *P, int64_t n, int d, int h, const bkd_opti
         BKD_HIP(hipMemcpy(t.d_chunk[0].p, blk.data(), total_bytes, hipMemcpyHostToDevice));
         t.chunk_in[0] = 0;
     } else {
-        t.h_leaf.ensure(total_bytes);
-        gather_leaves(P, t, 0, t.nleaf - 1, t.h_leaf.p);
+        if (opt.leaf_path) {
+            leaffile_create(t, P, opt.leaf_path);
+        } else {
+            t.h_leaf.ensure(total_bytes);
+            gather_leaves(P, t, 0, t.nleaf - 1, t.h_leaf.p);
+        }
         t.d_chunk[0].ensure(t.chunk_cap_bytes);
         t.d_chunk[1].ensure(t.chunk_cap_bytes);
         BKD_HIP(hipStreamCreateWithFlags(&t.copy_stream, hipStreamNonBlocking));
@@ -354,8 +375,11 @@ struct Run {
 
     void find_leaf(const FetchSpec &f, int64_t base) { find_leaf_into(f, leafbuf[cur], qbuf[cur], base); }
 
-    void find_leaf_into(const FetchSpec &f, uint32_t *out_leaf, int32_t *out_q, int64_t base)
+    void find_leaf_into(const FetchSpec &f0, uint32_t *out_leaf, int32_t *out_q, int64_t base)
     {
+        FetchSpec f = f0;
+        f.dims = t.dims_dev();
+        f.boxes = t.boxes_dev();
         tfind.begin(s);
         launch_find_leaf(f, dQ, d, ws.node, ws.kth, t.d_split.as<float>(), h,
                          out_leaf, out_q, base, cnt, ctl, s);
@@ -379,7 +403,9 @@ struct Run {
     // With runs, the per-leaf counts come from the runs of the sorted list (the fetch
     // did not count); otherwise from the fetch's counters.
     // wait: read the control words back before returning (else the copy is only issued)
-    void sort_and_offsets(int64_t count, bool runs = false, bool wait = true)
+    // count_full: a resident round's grouping counts the work of scanning every buffer (false when
+    // the round goes to the tail, which counts its own visits)
+    void sort_and_offsets(int64_t count, bool runs = false, bool wait = true, bool count_full = true)
     {
         tgroup.begin(s);
         if (runs && !tracing && nleaf + 1 <= bucket_max_keys()) {
@@ -387,8 +413,8 @@ struct Run {
             const int nb = nleaf + 1;
             uint32_t *hist = ws.hist;
             const int32_t *counts = launch_bucket_count(leafbuf[cur], count, nb, hist, s);
-            // a resident round scans every buffer (or hands them to the tail): its work is counted here
-            counted = t.resident;
+            // a resident round scans every buffer: its work is counted here
+            counted = t.resident && count_full;
             offsets(counts, nullptr, counted);
             launch_bucket_scatter(leafbuf[cur], qbuf[cur], leafbuf[1 - cur], qbuf[1 - cur], count, nb, hist,
                                   ws.off, s);
@@ -422,7 +448,7 @@ struct Run {
     // (cnt, or end - start of each run when start is given).
     void offsets(const int32_t *counts, const int32_t *start, bool count_work)
     {
-        launch_leaf_offsets(counts, start, t.d_leaf_off.as<int32_t>(), nleaf, SCAN_QT, SCAN_DENSE_MIN,
+        launch_leaf_offsets(counts, start, t.d_leaf_off.as<int32_t>(), nleaf, SCAN_QT, t.dense_min,
                             ws.off, ws.tiles, ws.tiles + nleaf + 1, ctl,
                             s, count_work);
     }
@@ -447,6 +473,8 @@ struct Run {
         a.scales = a.centers + (size_t)nleaf * d;
         a.exact_only = t.wide ? 1 : 0;
         a.wide_flag = ctl + CTL_WIDE;
+        a.dims = t.dims_dev();
+        a.boxes = t.boxes_dev();
         return a;
     }
 
@@ -468,7 +496,7 @@ struct Run {
 
     void count_work(int lf, int ll)
     {
-        launch_count_work(ws.off, t.d_leaf_off.as<int32_t>(), lf, ll, SCAN_DENSE_MIN, ctl, s);
+        launch_count_work(ws.off, t.d_leaf_off.as<int32_t>(), lf, ll, t.dense_min, ctl, s);
     }
 
     // Scan every buffered query of a resident structure.
@@ -499,7 +527,7 @@ struct Run {
 
     // Dense scan of a resident round queued before its counts reach the host:
     // the item count is read on the device, the grid is bounded by the list
-    // length (a dense leaf holds at least SCAN_DENSE_MIN queries).
+    // length (a dense leaf holds at least dense_min queries).
     void scan_resident_dense_ahead(int64_t list)
     {
         if (!counted) count_work(0, nleaf - 1);
@@ -507,7 +535,7 @@ struct Run {
         a.chunk_lo = 0;
         a.chunk_hi = t.host.n;
         a.item_first = 0;
-        const int64_t bound = list / SCAN_QT + std::min<int64_t>(nleaf, list / SCAN_DENSE_MIN) + 1;
+        const int64_t bound = list / SCAN_QT + std::min<int64_t>(nleaf, list / std::max(1, t.dense_min)) + 1;
         a.item_count = (int32_t)std::min<int64_t>(bound, INT32_MAX);
         a.dev_counts = ctl;
         route_args(a);
@@ -540,14 +568,25 @@ struct Run {
         return (htiles()[c.leaf_last + 1] - htiles()[c.leaf_first]) + (hsparse()[c.leaf_last + 1] - hsparse()[c.leaf_first]);
     }
 
+    // Leaf file: start reading chunk j unless a device buffer already holds it.
+    void prefetch(int j)
+    {
+        if (t.leaf_file && j >= 0 && t.chunk_in[0] != j && t.chunk_in[1] != j) leaffile_prefetch(t, j);
+    }
+
     void issue_copy(int b, int j)
     {
         const Chunk &c = t.chunks[(size_t)j];
         const size_t bytes = (size_t)(c.word_hi - c.word_lo) * 4;
         BKD_HIP(hipStreamWaitEvent(t.copy_stream, t.ev_used[b], 0));
         tcopy.begin(t.copy_stream);
-        BKD_HIP(hipMemcpyAsync(t.d_chunk[b].p, t.h_leaf.as<float>() + c.word_lo, bytes, hipMemcpyHostToDevice,
-                               t.copy_stream));
+        if (t.leaf_file) {
+            // disk -> staging (reader thread, usually prefetched) -> device
+            wait_ms += leaffile_copy(t, j, t.d_chunk[b].p, t.copy_stream);
+        } else {
+            BKD_HIP(hipMemcpyAsync(t.d_chunk[b].p, t.h_leaf.as<float>() + c.word_lo, bytes, hipMemcpyHostToDevice,
+                                   t.copy_stream));
+        }
         tcopy.end(t.copy_stream);
         BKD_HIP(hipEventRecord(t.ev_copied[b], t.copy_stream));
         t.chunk_in[b] = j;
@@ -626,8 +665,11 @@ struct Run {
         std::vector<int> active;
         for (int j = 0; j < (int)t.chunks.size(); j++)
             if (chunk_items(j) > 0) active.push_back(j);
-        for (size_t ai = 0; ai < active.size(); ai++)
+        for (size_t ai = 0; ai < active.size(); ai++) {
+            // read ahead from the leaf file: the next chunks of the walk
+            for (size_t x = ai + 1; x < std::min(active.size(), ai + 3); x++) prefetch(active[x]);
             scan_chunk(active[ai], ai + 1 < active.size() ? active[ai + 1] : 0);
+        }
     }
 
     void end_call()
@@ -690,17 +732,17 @@ struct Run {
         bool first = true;
         const int64_t tail_max = t.opt.tail_max == 0 ? TAIL_MAX : t.opt.tail_max;
         const bool use_tail = !(t.opt.flags & BKD_FLAG_NO_TAIL);
-        if (t.resident && !tracing) {
+        if (t.resident && !tracing && !t.dims_dev() && !t.boxes_dev()) {
             // Resident rounds without a host wait before the scan: the dense scan of a round is
             // queued behind its sort and reads its item count on the device, and the host reads
             // the round's counts back meanwhile.  The tail takes over once a round's list (the
             // pending entries routed in the previous round) is at most tail_max long.
             for (;;) {
                 const int64_t list = P;
-                sort_and_offsets(list, true, false);
+                const bool tail_now = use_tail && list <= tail_max;
+                sort_and_offsets(list, true, false, !tail_now);
                 if (first) localize();
                 first = false;
-                const bool tail_now = use_tail && list <= tail_max;
                 if (!tail_now) scan_resident_dense_ahead(list);
                 readback_wait();
                 P = hctl[CTL_V];
@@ -830,6 +872,10 @@ struct Run {
             };
             if (c < 0 || hr[c] < mark) c = next_from(c, -1);
             const int nc = next_from(c, c);
+            // from a leaf file: read c (if not on the device) and the chunk after it while c is
+            // sorted, scanned and routed
+            prefetch(c);
+            prefetch(nc);
             const Chunk &C = t.chunks[(size_t)c];
             const int lf = C.leaf_first, ll = C.leaf_last, nl = ll - lf + 1;
             const int64_t n = hr[c];
@@ -858,7 +904,7 @@ struct Run {
             launch_fill_i32(cnt + lf, 0, nl, s);
             launch_fill_i32(start + lf, 0, nl, s);
             launch_run_bounds(Rl, n, nleaf, start, cnt, s);
-            launch_leaf_offsets(cnt + lf, start + lf, t.d_leaf_off.as<int32_t>() + lf, nl, SCAN_QT, SCAN_DENSE_MIN,
+            launch_leaf_offsets(cnt + lf, start + lf, t.d_leaf_off.as<int32_t>() + lf, nl, SCAN_QT, t.dense_min,
                                 ws.off + lf, dtiles + lf, dtiles + nleaf + 1 + lf, ctl, s);
             tgroup.end(s);
             BKD_HIP(hipMemcpyAsync(t.h_tiles.as<int32_t>() + lf, dtiles + lf, sizeof(int32_t) * (nl + 1),
@@ -1010,6 +1056,7 @@ void tree_query_device(Tree &t, const float *dQ, int64_t m, int k, int64_t *d_id
         t.stats.copy_ms = r.tcopy.total_ms();
     }
     t.stats.wait_ms = r.wait_ms;
+    if (t.leaf_file) leaffile_take_stats(t, &t.stats.bytes_disk, &t.stats.disk_ms);
     t.stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 

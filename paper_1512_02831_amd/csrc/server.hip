@@ -34,7 +34,7 @@ namespace {
 __global__ void k_admit(const float *__restrict__ stage, const int32_t *__restrict__ slots, int64_t m, int d, int K,
                         int k, int32_t table, float *__restrict__ Qpool, uint64_t *__restrict__ keys,
                         uint32_t *__restrict__ kth, int32_t *__restrict__ node, int32_t *__restrict__ kq,
-                        int32_t *__restrict__ req_of)
+                        int32_t *__restrict__ req_of, int32_t *__restrict__ age)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
@@ -45,6 +45,7 @@ __global__ void k_admit(const float *__restrict__ stage, const int32_t *__restri
     node[s] = NODE_FRESH;
     kq[s] = k;
     req_of[s] = table;
+    age[s] = 0;
 }
 
 __global__ void k_gather(const uint64_t *__restrict__ keys, const int32_t *__restrict__ slots, int64_t m, int K, int k,
@@ -69,6 +70,13 @@ double now_s()
 
 }  // namespace
 
+// Pending queries at or below which a session's round hands them all to the tail kernel
+// (bkd_server_opts.tail_max).  Lower than the single call's default: a session keeps
+// admitting work, and its rounds share leaf reads among the queries in flight.  Measured on
+// the two-tree workload: 2048 gave 0.79 M queries/s saturated and p99 8.0 s at half load,
+// 16384 gave 0.81 M and 4.7 s, 65536 gave 0.66 M and 10.6 s.
+constexpr int64_t SERVED_TAIL_MAX = 16384;
+
 struct Request {
     int64_t id = 0;
     int tree = 0, k = 0, K = 0;
@@ -92,10 +100,12 @@ struct Session {
     int tree_id = 0, K = 0;
     int64_t cap = 0;  // query slots
     int max_req = 0;
+    int age_max = 0;  // rounds after which a query leaves the rounds for the tail (0: never)
+    int64_t tail_max = 0;  // pending queries at or below which a round hands them all to the tail
     hipStream_t s = nullptr;
     // device state
     DevBuf Qpool, keys, kth, node, kq, req_of, req_left, done, pleaf, pq, tleaf, tq, hist, cnt, cnt0, off, tiles, ctl, newslots,
-        stage, oidx, odist, gslots;
+        stage, oidx, odist, gslots, fleaf, fq, age;
     PinnedBuf hctl, hdone, hstage, hout, hgslots;
     hipEvent_t ev_stage = nullptr;  // after the last admission's staging copies
     bool stage_pending = false;
@@ -105,9 +115,10 @@ struct Session {
     std::deque<Request *> waiting;
     std::map<int32_t, Request *> running;  // by table index
     int64_t P = 0;  // pending entries in flight (sorted list of the last round)
+    int64_t nfast = 0;  // admitted queries of small requests (at the front of newslots), this round
     int cur = 0;
     std::thread th;
-    int64_t rounds = 0, scans = 0, tails = 0, admitted = 0;
+    int64_t rounds = 0, scans = 0, tails = 0, directs = 0, admitted = 0, aged = 0;
     double busy_s = 0, admit_s = 0, complete_s = 0;
 };
 
@@ -116,6 +127,8 @@ struct Server {
     int64_t slots_per_session = 0;
     int32_t max_requests = 0;
     int32_t flags = 0;
+    int32_t age_max = 0;
+    int64_t tail_max = SERVED_TAIL_MAX;
     std::mutex mu;
     std::condition_variable cv;       // wakes sessions (new work, stop)
     std::condition_variable done_cv;  // wakes waiters
@@ -151,6 +164,9 @@ static void session_init(Session &S)
     S.tiles.ensure(sizeof(int32_t) * 2 * (nleaf + 1));
     S.ctl.ensure(sizeof(int32_t) * CTL_WORDS);
     S.newslots.ensure(sizeof(int32_t) * cap);
+    S.fleaf.ensure(sizeof(uint32_t) * cap);
+    S.fq.ensure(sizeof(int32_t) * cap);
+    S.age.ensure(sizeof(int32_t) * cap);
     S.hctl.ensure(sizeof(int32_t) * CTL_WORDS);
     S.hdone.ensure(sizeof(int32_t) * (S.max_req + 1));
     S.free_slots.resize((size_t)cap);
@@ -164,6 +180,12 @@ static void session_init(Session &S)
     launch_fill_i32(S.done.as<int32_t>(), 0, 1, S.s);
     BKD_HIP(hipStreamSynchronize(S.s));
 }
+
+// Requests of at most this many queries skip the rounds: each of their queries is routed to its
+// first leaf and finishes its whole traversal in one tail workgroup, right after admission, so
+// their latency is one launch instead of the session's round count (Section 2.3 search phases,
+// the same visits and results as the rounds).
+constexpr int64_t SERVED_DIRECT_MAX = 2048;
 
 // Admit waiting requests that fit (FIFO); called with the server lock held for the bookkeeping.
 static int64_t session_admit(Session &S, std::unique_lock<std::mutex> &lk)
@@ -191,6 +213,11 @@ static int64_t session_admit(Session &S, std::unique_lock<std::mutex> &lk)
         adm.push_back(r);
     }
     lk.unlock();
+    // small requests first: their queries take the direct path (one traversal per query, no rounds)
+    std::stable_partition(adm.begin(), adm.end(), [](const Request *r) { return r->m <= SERVED_DIRECT_MAX; });
+    S.nfast = 0;
+    for (Request *r : adm)
+        if (r->m <= SERVED_DIRECT_MAX) S.nfast += r->m;
     if (!adm.empty()) {
         // all admitted requests in one staging pass: host -> pinned stage -> device stage -> slots
         int64_t total = 0;
@@ -214,7 +241,7 @@ static int64_t session_admit(Session &S, std::unique_lock<std::mutex> &lk)
                 S.stage.as<float>() + nnew * d, S.newslots.as<int32_t>() + nnew, r->m, d, S.K, r->k, r->table,
                 S.Qpool.as<float>(), S.keys.as<uint64_t>(), S.kth.as<uint32_t>(), S.node.as<int32_t>(),
                 S.kq.as<int32_t>(),
-                S.req_of.as<int32_t>());
+                S.req_of.as<int32_t>(), S.age.as<int32_t>());
             k_set_i32<<<1, 1, 0, S.s>>>(S.req_left.as<int32_t>(), r->table, (int32_t)r->m);
             nnew += r->m;
         }
@@ -226,10 +253,12 @@ static int64_t session_admit(Session &S, std::unique_lock<std::mutex> &lk)
     return nnew;
 }
 
-// Pending queries at or below which a session's round hands them all to the tail kernel.
-// Lower than the single-call default: a session keeps admitting work, and its
-// rounds share leaf reads among the queries in flight.
-constexpr int64_t SERVED_TAIL_MAX = 2048;
+// Buffers of at least this many queries take the dense scan in a session round (8 against the
+// single call's 32: a session's rounds hold few queries per leaf, and reading a leaf once for
+// eight queries beats eight walks of it; saturated throughput 0.70 -> 0.77 M queries/s on the
+// two-tree workload).
+constexpr int SERVED_DENSE_MIN = 8;
+
 
 // One round: route the last round's queries and the new ones, buffer them, scan.
 static void session_round(Session &S, int64_t nnew)
@@ -241,30 +270,108 @@ static void session_round(Session &S, int64_t nnew)
     int32_t *qbuf[2] = {S.pq.as<int32_t>(), S.tq.as<int32_t>()};
     int32_t *ctl = S.ctl.as<int32_t>();
     int32_t *hctl = S.hctl.as<int32_t>();
-    // route in place: the previous sorted list, then the admitted slots appended
+    if (S.nfast > 0) {
+        // small requests: first leaf of each query, then its whole traversal in one workgroup
+        FetchSpec g{nullptr, 0, 0, 1, 0, S.nfast};
+        g.count_leaves = false;
+        g.in_list = S.newslots.as<int32_t>();
+        g.req_of = S.req_of.as<int32_t>();
+        g.req_left = S.req_left.as<int32_t>();
+        g.done_list = S.done.as<int32_t>();
+        g.dims = T.dims_dev();
+        g.boxes = T.boxes_dev();
+        launch_find_leaf(g, S.Qpool.as<float>(), H.d, S.node.as<int32_t>(), S.kth.as<uint32_t>(),
+                         T.d_split.as<float>(), H.h, S.fleaf.as<uint32_t>(), S.fq.as<int32_t>(), 0,
+                         S.cnt.as<int32_t>(), ctl, S.s);
+        ScanArgs a{};
+        a.leaf_off = T.d_leaf_off.as<int32_t>();
+        a.base = T.d_chunk[0].as<float>();
+        a.blk = T.d_leaf_blk.as<int64_t>();
+        a.Q = S.Qpool.as<float>();
+        a.d = H.d;
+        a.keys = S.keys.as<uint64_t>();
+        a.kth = S.kth.as<uint32_t>();
+        a.tail_leaf = S.fleaf.as<uint32_t>();
+        a.tail_q = S.fq.as<int32_t>();
+        a.tail_count = (int32_t)S.nfast;
+        a.tail_wide = (H.n >> H.h) >= TAIL_WIDE_LEAF;
+        a.node = S.node.as<int32_t>();
+        a.split = T.d_split.as<float>();
+        a.h = H.h;
+        a.k = S.K;
+        a.ctl = ctl;
+        a.kq = S.kq.as<int32_t>();
+        a.req_of = S.req_of.as<int32_t>();
+        a.req_left = S.req_left.as<int32_t>();
+        a.done_list = S.done.as<int32_t>();
+        a.dims = T.dims_dev();
+        a.boxes = T.boxes_dev();
+        launch_leaf_scan(a, S.K, 2, S.s);
+        S.directs++;
+    }
+    nnew -= S.nfast;
+    // route in place: the previous sorted list, then the other admitted slots appended
     FetchSpec f{qbuf[S.cur], 0, S.P, std::max<int64_t>(S.P, 1), 0, nnew};
     f.count_leaves = false;  // per-leaf counts come from the runs of the sorted list
-    f.in_list = S.newslots.as<int32_t>();
+    f.in_list = S.newslots.as<int32_t>() + S.nfast;
     f.req_of = S.req_of.as<int32_t>();
     f.req_left = S.req_left.as<int32_t>();
     f.done_list = S.done.as<int32_t>();
+    f.dims = T.dims_dev();
+    f.boxes = T.boxes_dev();
+    if (S.age_max > 0) {
+        f.age = S.age.as<int32_t>();
+        f.age_max = S.age_max;
+        launch_fill_i32(ctl + CTL_AGED, 0, 1, S.s);
+    }
     launch_find_leaf(f, S.Qpool.as<float>(), H.d, S.node.as<int32_t>(), S.kth.as<uint32_t>(),
                      T.d_split.as<float>(), H.h, leafbuf[S.cur], qbuf[S.cur], 0, S.cnt.as<int32_t>(), ctl, S.s);
     const int64_t total = S.P + nnew;
+    // keys: leaves 0 .. 2^h - 1, 2^h for a finished query, 2^h + 1 for one handed to the tail
     int which = launch_sort_pairs(leafbuf[S.cur], qbuf[S.cur], leafbuf[1 - S.cur], qbuf[1 - S.cur], total,
-                                  [&] { int b = 1; while ((1ll << b) <= nleaf) b++; return b; }(),
+                                  [&] { int b = 1; while ((1ll << b) <= nleaf + 1) b++; return b; }(),
                                   S.hist.as<uint32_t>(), S.s);
     if (which) S.cur = 1 - S.cur;
     launch_fill_i32(S.cnt.as<int32_t>(), 0, nleaf, S.s);
     launch_fill_i32(S.cnt0.as<int32_t>(), 0, nleaf, S.s);
     launch_run_bounds(leafbuf[S.cur], total, nleaf, S.cnt0.as<int32_t>(), S.cnt.as<int32_t>(), S.s);
     launch_leaf_offsets(S.cnt.as<int32_t>(), S.cnt0.as<int32_t>(), T.d_leaf_off.as<int32_t>(), nleaf, SCAN_QT,
-                        SCAN_DENSE_MIN,
+                        T.dense_min == INT32_MAX ? INT32_MAX : SERVED_DENSE_MIN,
                         S.off.as<int32_t>(), S.tiles.as<int32_t>(), S.tiles.as<int32_t>() + nleaf + 1, ctl, S.s);
     BKD_HIP(hipMemcpyAsync(hctl, ctl, sizeof(int32_t) * CTL_WORDS, hipMemcpyDeviceToHost, S.s));
     BKD_HIP(hipStreamSynchronize(S.s));
     S.P = hctl[CTL_V];
-    if (S.P > 0 && S.P <= SERVED_TAIL_MAX) {
+    const int64_t aged = S.age_max > 0 ? hctl[CTL_AGED] : 0;
+    if (aged > 0) {
+        // queries routed more than age_max times sort last: each walks the rest of its traversal
+        // in one workgroup from the leaf in node[q], so a request is not held by its longest walks
+        ScanArgs a{};
+        a.leaf_off = T.d_leaf_off.as<int32_t>();
+        a.base = T.d_chunk[0].as<float>();
+        a.blk = T.d_leaf_blk.as<int64_t>();
+        a.Q = S.Qpool.as<float>();
+        a.d = H.d;
+        a.keys = S.keys.as<uint64_t>();
+        a.kth = S.kth.as<uint32_t>();
+        a.tail_q = qbuf[S.cur] + (total - aged);
+        a.tail_count = (int32_t)aged;
+        a.tail_from_node = 1;
+        a.tail_wide = (H.n >> H.h) >= TAIL_WIDE_LEAF;
+        a.node = S.node.as<int32_t>();
+        a.split = T.d_split.as<float>();
+        a.h = H.h;
+        a.k = S.K;
+        a.ctl = ctl;
+        a.kq = S.kq.as<int32_t>();
+        a.req_of = S.req_of.as<int32_t>();
+        a.req_left = S.req_left.as<int32_t>();
+        a.done_list = S.done.as<int32_t>();
+        a.dims = T.dims_dev();
+        a.boxes = T.boxes_dev();
+        launch_leaf_scan(a, S.K, 2, S.s);
+        S.aged += aged;
+    }
+    if (S.P > 0 && S.P <= S.tail_max) {
         // few queries in flight: each finishes its traversal in one workgroup, and its request
         // completes as its last query does
         ScanArgs a{};
@@ -288,6 +395,8 @@ static void session_round(Session &S, int64_t nnew)
         a.req_of = S.req_of.as<int32_t>();
         a.req_left = S.req_left.as<int32_t>();
         a.done_list = S.done.as<int32_t>();
+        a.dims = T.dims_dev();
+        a.boxes = T.boxes_dev();
         launch_leaf_scan(a, S.K, 2, S.s);
         S.P = 0;
         S.tails++;
@@ -318,6 +427,8 @@ static void session_round(Session &S, int64_t nnew)
         a.exact_only = (T.wide || S.wide) ? 1 : 0;
         a.centers = T.d_centers.as<float>();
         a.scales = a.centers + (size_t)nleaf * H.d;
+        a.dims = T.dims_dev();
+        a.boxes = T.boxes_dev();
         launch_leaf_scan(a, S.K, 0, S.s);
         launch_leaf_scan(a, S.K, 1, S.s);
         S.scans++;
@@ -437,6 +548,8 @@ static Session &session_for(Server &V, int tree_id, int K)
     S->K = K;
     S->cap = V.slots_per_session;
     S->max_req = V.max_requests;
+    S->age_max = V.age_max;
+    S->tail_max = V.tail_max;
     session_init(*S);
     S->th = std::thread(session_loop, S.get());
     V.sessions.push_back(std::move(S));
@@ -460,7 +573,8 @@ int bkd_server_create(const bkd_server_opts *opts, bkd_server **out)
         if (opts) o = *opts;
         if (o.slots_per_session == 0) o.slots_per_session = 1 << 20;
         if (o.max_requests == 0) o.max_requests = 4096;
-        if (o.slots_per_session < 1 || o.slots_per_session > INT32_MAX || o.max_requests < 1 || o.device < 0)
+        if (o.slots_per_session < 1 || o.slots_per_session > INT32_MAX || o.max_requests < 1 || o.device < 0 ||
+            o.age_max < 0)
             bkd::fail(BKD_EINVAL, "invalid server options");
         int ndev = 0;
         BKD_HIP(hipGetDeviceCount(&ndev));
@@ -470,6 +584,8 @@ int bkd_server_create(const bkd_server_opts *opts, bkd_server **out)
         s->v.slots_per_session = o.slots_per_session;
         s->v.max_requests = o.max_requests;
         s->v.flags = o.flags;
+        s->v.age_max = o.age_max;
+        s->v.tail_max = o.tail_max == 0 ? bkd::SERVED_TAIL_MAX : (o.tail_max < 0 ? 0 : o.tail_max);
         *out = s.release();
     });
 }
@@ -589,6 +705,8 @@ int bkd_server_stats_get(bkd_server *srv, bkd_server_stats *out)
             out->rounds += s->rounds;
             out->scan_rounds += s->scans;
             out->tail_rounds += s->tails;
+            out->direct_launches += s->directs;
+            out->aged_queries += s->aged;
             out->queries += s->admitted;
             out->busy_s += s->busy_s;
             out->admit_s += s->admit_s;

@@ -140,3 +140,25 @@ def test_dropped_handles_are_kept_until_release():
             bkd.poll(srv, ids[0])
         assert e.value.code == bkd.ENOTFOUND
     ta.free()
+
+
+@pytest.mark.parametrize("age_max", [1, 4])
+def test_aged_queries_leave_the_rounds(age_max):
+    say(f"case: served age_max={age_max}: long walks handed from the rounds to single walks")
+    (PA, hA), (PB, hB) = trees()
+    ta = bkd.build(PA, hA, flags=bkd.FLAG_SQUARED)
+    tb = bkd.build(PB, hB, flags=bkd.FLAG_SQUARED)
+    reqs = []
+    for i, (P, m, k) in enumerate(((PA, 5000, 10), (PB, 4000, 32), (PA, 3000, 1), (PB, 100, 10))):
+        _, Q = datagen.mixture_pq(seed=70 + i, n=1, m=m, d=P.shape[1], comps=16)
+        reqs.append((P, Q, k))
+    with bkd.server_create(flags=bkd.FLAG_SQUARED, age_max=age_max) as srv:
+        ids = [bkd.server_add_tree(srv, t) for t in (ta, tb)]
+        hs = [bkd.submit(srv, ids[0] if P is PA else ids[1], Q, k) for P, Q, k in reqs]
+        for (P, Q, k), h in zip(reqs, hs):
+            idx, d2 = bkd.wait(srv, h, 60_000_000)
+            assert np.array_equal(keys_of(idx, d2), oracle.brute_f32c(P, Q, k)), (len(Q), k)
+        st = bkd.server_stats(srv)
+    assert st["aged_queries"] > 0
+    ta.free()
+    tb.free()
