@@ -152,7 +152,9 @@ def test_aged_queries_leave_the_rounds(age_max):
     for i, (P, m, k) in enumerate(((PA, 5000, 10), (PB, 4000, 32), (PA, 3000, 1), (PB, 100, 10))):
         _, Q = datagen.mixture_pq(seed=70 + i, n=1, m=m, d=P.shape[1], comps=16)
         reqs.append((P, Q, k))
-    with bkd.server_create(flags=bkd.FLAG_SQUARED, age_max=age_max) as srv:
+    # tail_max=-1: the rounds never hand the whole remainder to the tail, so these few
+    # thousand queries stay in the rounds long enough to age
+    with bkd.server_create(flags=bkd.FLAG_SQUARED, age_max=age_max, tail_max=-1) as srv:
         ids = [bkd.server_add_tree(srv, t) for t in (ta, tb)]
         hs = [bkd.submit(srv, ids[0] if P is PA else ids[1], Q, k) for P, Q, k in reqs]
         for (P, Q, k), h in zip(reqs, hs):
