@@ -485,22 +485,37 @@ __global__ __launch_bounds__(256) void k_count_work(const int32_t *__restrict__ 
 
 // Chunk sweep: route entries of the drained chunk c to the pending regions of
 // their next chunk; entries staying in c go to a side buffer, finished ones are dropped.
-__global__ void k_distribute(const uint32_t *__restrict__ leaf, const int32_t *__restrict__ q, int64_t n,
-                             uint32_t nleaf, const int32_t *__restrict__ chunk_of, int c, uint32_t *__restrict__ rleaf,
-                             int32_t *__restrict__ rq, int64_t rcap, int32_t *__restrict__ rcnt,
-                             uint32_t *__restrict__ sleaf, int32_t *__restrict__ sq, int nchunks)
+// The order inside a region is free (a region is grouped by leaf before its scan),
+// so a block first counts its entries per target in LDS and then reserves each
+// target's range with one device-scope atomic: a few atomics per 1024 entries
+// instead of one per entry on a handful of words.
+__global__ __launch_bounds__(1024) void k_distribute(const uint32_t *__restrict__ leaf, const int32_t *__restrict__ q,
+                                                     int64_t n, uint32_t nleaf, const int32_t *__restrict__ chunk_of,
+                                                     int c, uint32_t *__restrict__ rleaf, int32_t *__restrict__ rq,
+                                                     int64_t rcap, int32_t *__restrict__ rcnt,
+                                                     uint32_t *__restrict__ sleaf, int32_t *__restrict__ sq, int nchunks)
 {
+    __shared__ int32_t cnt[DISTRIBUTE_MAX_TARGETS], base[DISTRIBUTE_MAX_TARGETS];
+    for (int j = threadIdx.x; j <= nchunks; j += blockDim.x) cnt[j] = 0;
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t l = leaf[i];
-    if (l >= nleaf) return;
-    const int t = chunk_of[l];
-    if (t == c) {
-        const int32_t pos = atomicAdd(&rcnt[nchunks], 1);
+    const uint32_t l = i < n ? leaf[i] : nleaf;
+    int t = -1, pos = 0;
+    if (l < nleaf) {
+        const int tc = chunk_of[l];
+        t = tc == c ? nchunks : tc;
+        pos = atomicAdd(&cnt[t], 1);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j <= nchunks; j += blockDim.x)
+        if (cnt[j]) base[j] = atomicAdd(&rcnt[j], cnt[j]);
+    __syncthreads();
+    if (t < 0) return;
+    pos += base[t];
+    if (t == nchunks) {
         sleaf[pos] = l;
         sq[pos] = q[i];
     } else {
-        const int32_t pos = atomicAdd(&rcnt[t], 1);
         rleaf[(int64_t)t * rcap + pos] = l;
         rq[(int64_t)t * rcap + pos] = q[i];
     }
@@ -688,8 +703,9 @@ void launch_distribute(const uint32_t *leaf, const int32_t *q, int64_t n, int nl
                        int nchunks, hipStream_t s)
 {
     if (n <= 0) return;
-    k_distribute<<<grid_for(n, 256), 256, 0, s>>>(leaf, q, n, (uint32_t)nleaf, chunk_of, c, rleaf, rq, rcap, rcnt, sleaf,
-                                                  sq, nchunks);
+    if (nchunks + 1 > DISTRIBUTE_MAX_TARGETS) fail(BKD_EINVAL, "chunk sweep: too many chunks");
+    k_distribute<<<grid_for(n, 1024), 1024, 0, s>>>(leaf, q, n, (uint32_t)nleaf, chunk_of, c, rleaf, rq, rcap, rcnt,
+                                                    sleaf, sq, nchunks);
     check_launch();
 }
 

@@ -169,7 +169,8 @@ void tree_build(Tree &t, const float *P, int64_t n, int d, int h, const bkd_opti
     else build_canonical(P, n, d, h, t.host, true, opt.split_rule);
     if (opt.prune == BKD_PRUNE_BOX) build_boxes(P, t.host);
     plan_chunks(t);
-    t.sweep = !t.resident && t.opt.chunk_mode == BKD_CHUNK_LEAF;
+    t.sweep = !t.resident && t.opt.chunk_mode == BKD_CHUNK_LEAF &&
+              (int64_t)t.chunks.size() < DISTRIBUTE_MAX_TARGETS;
     for (int l = 0; l < t.nleaf; l++)
         if (t.host.leaf_off[(size_t)l + 1] - t.host.leaf_off[(size_t)l] >= (int64_t(1) << 30)) t.dense_min = INT32_MAX;
 
@@ -317,6 +318,7 @@ struct Run {
     int32_t *qbuf[2];
     int cur = 0;  // pair holding the pending list
     const int32_t *bufq_override = nullptr;  // scan input other than the pending pair (chunk sweep)
+    uint32_t *route_override = nullptr;     // chunk sweep: the scans route into this list
     Timer tdense, tsparse, tfind, tgroup, tcopy;
     double wait_ms = 0;  // host time spent waiting for the device
     std::vector<int32_t> tr_q, tr_l;
@@ -654,6 +656,14 @@ struct Run {
         a.item_count = htiles()[c.leaf_last + 1] - htiles()[c.leaf_first];
         a.sitem_first = hsparse()[c.leaf_first];
         a.sitem_count = hsparse()[c.leaf_last + 1] - hsparse()[c.leaf_first];
+        if (route_override) {
+            // every query of the chunk's region is scanned once here and takes its next
+            // FindLeafBatch step at the end of its scan, written into its list position
+            a.route_leaf = route_override;
+            a.node = ws.node;
+            a.split = t.d_split.as<float>();
+            a.h = h;
+        }
         run_scan(a);
         chunk_done(b, j, nj);
     }
@@ -839,6 +849,8 @@ struct Run {
         const bool use_tail = !tracing && !(t.opt.flags & BKD_FLAG_NO_TAIL) && t.opt.tail_max >= 0;
         uint32_t *sleaf = leafbuf[1 - cur];
         int32_t *sq = qbuf[1 - cur];
+        // the scans route their queries themselves (original splitting rule, untraced)
+        const bool scan_routes = !tracing && !t.dims_dev() && !t.boxes_dev();
         auto read_counts = [&]() {
             BKD_HIP(hipMemcpyAsync(hr, rcnt, sizeof(int32_t) * (N + 1), hipMemcpyDeviceToHost, s));
             waiting([&] { BKD_HIP(hipStreamSynchronize(s)); });
@@ -914,13 +926,20 @@ struct Run {
             readback();
             count_work(lf, ll);
             bufq_override = Rq;
+            route_override = scan_routes ? Rl : nullptr;
             scan_chunk(c, nc);
             bufq_override = nullptr;
+            route_override = nullptr;
             end_call();
-            // route again in place, then move every entry to the region of its next chunk
-            FetchSpec f{Rq, 0, n, std::max<int64_t>(n, 1), 0, 0};
-            f.count_leaves = false;
-            find_leaf_into(f, Rl, Rq, 0);
+            // route again in place (done by the scans unless traced or a variant tree), then
+            // move every entry to the region of its next chunk
+            if (!scan_routes) {
+                FetchSpec f{Rq, 0, n, std::max<int64_t>(n, 1), 0, 0};
+                f.count_leaves = false;
+                find_leaf_into(f, Rl, Rq, 0);
+            } else {
+                t.stats.fetches++;
+            }
             tgroup.begin(s);
             launch_distribute(Rl, Rq, n, nleaf, chunk_of, c, rleaf, rq, m, rcnt, sleaf, sq, N, s);
             launch_restore(sleaf, sq, n, Rl, Rq, rcnt, c, N, s);
