@@ -226,8 +226,9 @@ void launch_find_leaf(const FetchSpec &f, const float *Q, int d, int32_t *node, 
                       const float *split, int h, uint32_t *pend_leaf, int32_t *pend_q, int64_t pend_base,
                       int32_t *cnt, int32_t *ctl, hipStream_t s);
 // Stable sort of (leaf, query) pairs by leaf; returns which buffer holds the result (0: a, 1: b).
+// With dcount the pair count is read on the device (*dcount <= count; count sizes the grids).
 int launch_sort_pairs(uint32_t *key_a, int32_t *val_a, uint32_t *key_b, int32_t *val_b, int64_t count, int key_bits,
-                      uint32_t *hist, hipStream_t s);
+                      uint32_t *hist, hipStream_t s, const int32_t *dcount = nullptr);
 size_t sort_hist_words(int64_t count);
 // Grouping of (leaf, query) pairs by leaf in one pass, order within a leaf unspecified, for
 // at most bucket_max_keys() distinct keys: launch_bucket_count writes per-block key counts
@@ -243,12 +244,13 @@ void launch_bucket_scatter(const uint32_t *kin, const int32_t *vin, uint32_t *ko
 void launch_leaf_offsets(const int32_t *cnt, const int32_t *start, const int32_t *leaf_off, int nleaf, int qt,
                          int dense_min, int32_t *off, int32_t *tiles, int32_t *sparse, int32_t *ctl, hipStream_t s,
                          bool count_work = false);
-void launch_run_bounds(const uint32_t *leaf, int64_t count, int nleaf, int32_t *start, int32_t *end, hipStream_t s);
+void launch_run_bounds(const uint32_t *leaf, int64_t count, int nleaf, int32_t *start, int32_t *end, hipStream_t s,
+                       const int32_t *dcount = nullptr);
 // The chunk sweep's distribution counts its targets (the chunks and a side buffer) in LDS.
 constexpr int DISTRIBUTE_MAX_TARGETS = 1024;
 void launch_distribute(const uint32_t *leaf, const int32_t *q, int64_t n, int nleaf, const int32_t *chunk_of, int c,
                        uint32_t *rleaf, int32_t *rq, int64_t rcap, int32_t *rcnt, uint32_t *sleaf, int32_t *sq,
-                       int nchunks, hipStream_t s);
+                       int nchunks, hipStream_t s, const int32_t *dn = nullptr);
 void launch_restore(const uint32_t *sleaf, const int32_t *sq, int64_t n, uint32_t *rleaf, int32_t *rq, int32_t *rcnt,
                     int c, int nchunks, hipStream_t s);
 void launch_count_work(const int32_t *off, const int32_t *leaf_off, int lf, int ll, int dense_min, int32_t *ctl,

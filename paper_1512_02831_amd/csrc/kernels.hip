@@ -149,10 +149,12 @@ __global__ __launch_bounds__(256) void k_find_leaf(FetchSpec f, const float *__r
 
 // Per-leaf counts of a pending list sorted by leaf, without atomics: the run
 // of leaf l occupies [start[l], end[l]); both arrays are zero for absent leaves.
-__global__ void k_run_bounds(const uint32_t *__restrict__ leaf, int64_t count, uint32_t nleaf,
-                             int32_t *__restrict__ start, int32_t *__restrict__ end)
+// With dcount the element count is *dcount (count only bounds the grid).
+__global__ void k_run_bounds(const uint32_t *__restrict__ leaf, int64_t count, const int32_t *__restrict__ dcount,
+                             uint32_t nleaf, int32_t *__restrict__ start, int32_t *__restrict__ end)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (dcount) count = *dcount;
     if (i >= count) return;
     const uint32_t l = leaf[i];
     if (l >= nleaf) return;
@@ -168,10 +170,12 @@ constexpr int SORT_ROUNDS = 8;
 constexpr int SORT_TILE = SORT_THREADS * SORT_ROUNDS;
 
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t count,
-                                                             int shift, uint32_t *__restrict__ hist, int nblocks)
+                                                             const int32_t *__restrict__ dcount, int shift,
+                                                             uint32_t *__restrict__ hist, int nblocks)
 {
     __shared__ uint32_t hcount[256];
     const int tid = threadIdx.x;
+    if (dcount) count = *dcount;
     hcount[tid] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
@@ -213,10 +217,12 @@ __global__ __launch_bounds__(256) void k_scan_columns(uint32_t *__restrict__ his
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const uint32_t *__restrict__ kin,
                                                                 const int32_t *__restrict__ vin,
                                                                 uint32_t *__restrict__ kout,
-                                                                int32_t *__restrict__ vout, int64_t count, int shift,
+                                                                int32_t *__restrict__ vout, int64_t count,
+                                                                const int32_t *__restrict__ dcount, int shift,
                                                                 const uint32_t *__restrict__ hist, int nblocks,
                                                                 const uint32_t *__restrict__ totals)
 {
+    if (dcount) count = *dcount;
     constexpr int W = SORT_THREADS / 64;
     __shared__ uint32_t run[256];      // next output position per digit for this block
     __shared__ uint32_t wcount[W][256];
@@ -490,12 +496,14 @@ __global__ __launch_bounds__(256) void k_count_work(const int32_t *__restrict__ 
 // target's range with one device-scope atomic: a few atomics per 1024 entries
 // instead of one per entry on a handful of words.
 __global__ __launch_bounds__(1024) void k_distribute(const uint32_t *__restrict__ leaf, const int32_t *__restrict__ q,
-                                                     int64_t n, uint32_t nleaf, const int32_t *__restrict__ chunk_of,
+                                                     int64_t n, const int32_t *__restrict__ dn, uint32_t nleaf,
+                                                     const int32_t *__restrict__ chunk_of,
                                                      int c, uint32_t *__restrict__ rleaf, int32_t *__restrict__ rq,
                                                      int64_t rcap, int32_t *__restrict__ rcnt,
                                                      uint32_t *__restrict__ sleaf, int32_t *__restrict__ sq, int nchunks)
 {
     __shared__ int32_t cnt[DISTRIBUTE_MAX_TARGETS], base[DISTRIBUTE_MAX_TARGETS];
+    if (dn) n = *dn;
     for (int j = threadIdx.x; j <= nchunks; j += blockDim.x) cnt[j] = 0;
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -655,9 +663,9 @@ void launch_bucket_scatter(const uint32_t *kin, const int32_t *vin, uint32_t *ko
 }
 
 int launch_sort_pairs(uint32_t *key_a, int32_t *val_a, uint32_t *key_b, int32_t *val_b, int64_t count, int key_bits,
-                      uint32_t *hist, hipStream_t s)
+                      uint32_t *hist, hipStream_t s, const int32_t *dcount)
 {
-    if (count <= 1) return 0;
+    if (count <= (dcount ? 0 : 1)) return 0;
     int nblocks = (int)((count + SORT_TILE - 1) / SORT_TILE);
     int passes = (key_bits + 7) / 8;
     uint32_t *kin = key_a, *kout = key_b;
@@ -665,9 +673,10 @@ int launch_sort_pairs(uint32_t *key_a, int32_t *val_a, uint32_t *key_b, int32_t 
     for (int p = 0; p < passes; p++) {
         int shift = 8 * p;
         uint32_t *totals = hist + (size_t)nblocks * 256;
-        k_radix_hist<<<nblocks, SORT_THREADS, 0, s>>>(kin, count, shift, hist, nblocks);
+        k_radix_hist<<<nblocks, SORT_THREADS, 0, s>>>(kin, count, dcount, shift, hist, nblocks);
         k_scan_columns<<<256, 256, 0, s>>>(hist, nblocks, totals);
-        k_radix_scatter<<<nblocks, SORT_THREADS, 0, s>>>(kin, vin, kout, vout, count, shift, hist, nblocks, totals);
+        k_radix_scatter<<<nblocks, SORT_THREADS, 0, s>>>(kin, vin, kout, vout, count, dcount, shift, hist, nblocks,
+                                                         totals);
         check_launch();
         std::swap(kin, kout);
         std::swap(vin, vout);
@@ -684,10 +693,11 @@ void launch_leaf_offsets(const int32_t *cnt, const int32_t *start, const int32_t
     check_launch();
 }
 
-void launch_run_bounds(const uint32_t *leaf, int64_t count, int nleaf, int32_t *start, int32_t *end, hipStream_t s)
+void launch_run_bounds(const uint32_t *leaf, int64_t count, int nleaf, int32_t *start, int32_t *end, hipStream_t s,
+                       const int32_t *dcount)
 {
     if (count <= 0) return;
-    k_run_bounds<<<grid_for(count, 256), 256, 0, s>>>(leaf, count, (uint32_t)nleaf, start, end);
+    k_run_bounds<<<grid_for(count, 256), 256, 0, s>>>(leaf, count, dcount, (uint32_t)nleaf, start, end);
     check_launch();
 }
 
@@ -700,11 +710,11 @@ void launch_count_work(const int32_t *off, const int32_t *leaf_off, int lf, int 
 
 void launch_distribute(const uint32_t *leaf, const int32_t *q, int64_t n, int nleaf, const int32_t *chunk_of, int c,
                        uint32_t *rleaf, int32_t *rq, int64_t rcap, int32_t *rcnt, uint32_t *sleaf, int32_t *sq,
-                       int nchunks, hipStream_t s)
+                       int nchunks, hipStream_t s, const int32_t *dn)
 {
     if (n <= 0) return;
     if (nchunks + 1 > DISTRIBUTE_MAX_TARGETS) fail(BKD_EINVAL, "chunk sweep: too many chunks");
-    k_distribute<<<grid_for(n, 1024), 1024, 0, s>>>(leaf, q, n, (uint32_t)nleaf, chunk_of, c, rleaf, rq, rcap, rcnt,
+    k_distribute<<<grid_for(n, 1024), 1024, 0, s>>>(leaf, q, n, dn, (uint32_t)nleaf, chunk_of, c, rleaf, rq, rcap, rcnt,
                                                     sleaf, sq, nchunks);
     check_launch();
 }

@@ -853,7 +853,7 @@ struct Run {
         const bool scan_routes = !tracing && !t.dims_dev() && !t.boxes_dev();
         auto read_counts = [&]() {
             BKD_HIP(hipMemcpyAsync(hr, rcnt, sizeof(int32_t) * (N + 1), hipMemcpyDeviceToHost, s));
-            waiting([&] { BKD_HIP(hipStreamSynchronize(s)); });
+            readback();
         };
         tgroup.begin(s);
         launch_fill_i32(rcnt, 0, N + 1, s);
@@ -905,46 +905,82 @@ struct Run {
                 read_counts();
                 continue;
             }
-            // sort the region by leaf, then offsets and work items of chunk c's leaves
-            tgroup.begin(s);
-            if (launch_sort_pairs(Rl, Rq, sleaf, sq, n, kbits, ws.hist, s)) {
-                BKD_HIP(hipMemcpyAsync(Rl, sleaf, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
-                BKD_HIP(hipMemcpyAsync(Rq, sq, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+            // Steps on c, pipelined: a step's grouping and its dense scan are queued before the
+            // host has its counts (read back ahead of the dense scan), and from the second step
+            // on they take the region's size on the device (the previous step's distribution),
+            // so the host queues a step's sparse scan and distribution, and the next step, while
+            // the dense scan runs.  The host sees a region's size one step late, so it may stay
+            // on c for one step more than the mark asks.
+            int64_t nstep = n;               // bound on the size of the step being queued
+            const int32_t *dstep = nullptr;  // its size on the device (from the second step on)
+            for (;;) {
+                tgroup.begin(s);
+                if (launch_sort_pairs(Rl, Rq, sleaf, sq, nstep, kbits, ws.hist, s, dstep)) {
+                    BKD_HIP(hipMemcpyAsync(Rl, sleaf, sizeof(uint32_t) * nstep, hipMemcpyDeviceToDevice, s));
+                    BKD_HIP(hipMemcpyAsync(Rq, sq, sizeof(int32_t) * nstep, hipMemcpyDeviceToDevice, s));
+                }
+                int32_t *dtiles = ws.tiles;
+                int32_t *start = ws.cnt0;
+                launch_fill_i32(cnt + lf, 0, nl, s);
+                launch_fill_i32(start + lf, 0, nl, s);
+                launch_run_bounds(Rl, nstep, nleaf, start, cnt, s, dstep);
+                launch_leaf_offsets(cnt + lf, start + lf, t.d_leaf_off.as<int32_t>() + lf, nl, SCAN_QT, t.dense_min,
+                                    ws.off + lf, dtiles + lf, dtiles + nleaf + 1 + lf, ctl, s);
+                tgroup.end(s);
+                count_work(lf, ll);
+                // this step's counts, and every region's size before its distribution: read back
+                // while the dense scan (queued next) runs
+                BKD_HIP(hipMemcpyAsync(hr, rcnt, sizeof(int32_t) * (N + 1), hipMemcpyDeviceToHost, s));
+                readback_issue();
+                const int bb = chunk_buffer(c, nc);
+                ScanArgs a = scan_args(t.d_chunk[bb].as<float>(), -C.word_lo);
+                a.bufq = Rq;
+                a.chunk_lo = C.lo;
+                a.chunk_hi = C.hi;
+                a.leaf_first = lf;
+                a.leaf_last = ll;
+                a.item_first = 0;  // the chunk's work items are numbered from its first leaf
+                a.item_count = (int32_t)std::min<int64_t>(
+                    nstep / SCAN_QT + std::min<int64_t>(nl, nstep / std::max(1, t.dense_min)) + 1, INT32_MAX);
+                a.dev_counts = ctl;
+                a.sitem_first = 0;
+                a.sitem_count = 0;
+                if (scan_routes) {
+                    // every query of the region is scanned once in this step and takes its next
+                    // FindLeafBatch step at the end of its scan, written into its list position
+                    a.route_leaf = Rl;
+                    a.node = ws.node;
+                    a.split = t.d_split.as<float>();
+                    a.h = h;
+                }
+                run_scan(a);
+                readback_wait();
+                const int64_t nthis = hr[c];
+                a.dev_counts = nullptr;
+                a.item_count = 0;
+                a.sitem_count = hctl[CTL_S];
+                run_scan(a);
+                chunk_done(bb, c, nc);
+                end_call();
+                if (!scan_routes) {
+                    FetchSpec f{Rq, 0, nthis, std::max<int64_t>(nthis, 1), 0, 0};
+                    f.count_leaves = false;
+                    find_leaf_into(f, Rl, Rq, 0);
+                } else {
+                    t.stats.fetches++;
+                }
+                // move every entry to the region of its next chunk
+                tgroup.begin(s);
+                launch_distribute(Rl, Rq, nthis, nleaf, chunk_of, c, rleaf, rq, m, rcnt, sleaf, sq, N, s);
+                launch_restore(sleaf, sq, nthis, Rl, Rq, rcnt, c, N, s);
+                launch_fill_i32(rcnt + N, 0, 1, s);
+                tgroup.end(s);
+                int64_t tot = 0;
+                for (int j = 0; j < N; j++) tot += hr[j];
+                if (nthis < std::max<int64_t>(1, tot / N / 4) || (use_tail && nthis <= tail_max)) break;
+                nstep = nthis;
+                dstep = rcnt + c;
             }
-            int32_t *dtiles = ws.tiles;
-            int32_t *start = ws.cnt0;
-            launch_fill_i32(cnt + lf, 0, nl, s);
-            launch_fill_i32(start + lf, 0, nl, s);
-            launch_run_bounds(Rl, n, nleaf, start, cnt, s);
-            launch_leaf_offsets(cnt + lf, start + lf, t.d_leaf_off.as<int32_t>() + lf, nl, SCAN_QT, t.dense_min,
-                                ws.off + lf, dtiles + lf, dtiles + nleaf + 1 + lf, ctl, s);
-            tgroup.end(s);
-            BKD_HIP(hipMemcpyAsync(t.h_tiles.as<int32_t>() + lf, dtiles + lf, sizeof(int32_t) * (nl + 1),
-                                   hipMemcpyDeviceToHost, s));
-            BKD_HIP(hipMemcpyAsync(t.h_tiles.as<int32_t>() + nleaf + 1 + lf, dtiles + nleaf + 1 + lf,
-                                   sizeof(int32_t) * (nl + 1), hipMemcpyDeviceToHost, s));
-            readback();
-            count_work(lf, ll);
-            bufq_override = Rq;
-            route_override = scan_routes ? Rl : nullptr;
-            scan_chunk(c, nc);
-            bufq_override = nullptr;
-            route_override = nullptr;
-            end_call();
-            // route again in place (done by the scans unless traced or a variant tree), then
-            // move every entry to the region of its next chunk
-            if (!scan_routes) {
-                FetchSpec f{Rq, 0, n, std::max<int64_t>(n, 1), 0, 0};
-                f.count_leaves = false;
-                find_leaf_into(f, Rl, Rq, 0);
-            } else {
-                t.stats.fetches++;
-            }
-            tgroup.begin(s);
-            launch_distribute(Rl, Rq, n, nleaf, chunk_of, c, rleaf, rq, m, rcnt, sleaf, sq, N, s);
-            launch_restore(sleaf, sq, n, Rl, Rq, rcnt, c, N, s);
-            launch_fill_i32(rcnt + N, 0, 1, s);
-            tgroup.end(s);
             read_counts();
         }
     }
