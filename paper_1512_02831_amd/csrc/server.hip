@@ -108,6 +108,8 @@ struct Session {
         stage, oidx, odist, gslots, fleaf, fq, age;
     PinnedBuf hctl, hdone, hstage, hout, hgslots;
     hipEvent_t ev_stage = nullptr;  // after the last admission's staging copies
+    hipEvent_t ev_sync = nullptr;   // the round's readback
+    hipEvent_t ev_out = nullptr;    // the delivered requests' results on the host
     bool stage_pending = false;
     bool wide = false;  // a request with coordinates beyond +-FILTER_RANGE was admitted: exact scans from then on
     // host state
@@ -175,6 +177,8 @@ static void session_init(Session &S)
     for (int i = 0; i < S.max_req; i++) S.free_tables[(size_t)i] = S.max_req - 1 - i;
     BKD_HIP(hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking));
     BKD_HIP(hipEventCreateWithFlags(&S.ev_stage, hipEventDisableTiming));
+    BKD_HIP(hipEventCreateWithFlags(&S.ev_sync, hipEventDisableTiming));
+    BKD_HIP(hipEventCreateWithFlags(&S.ev_out, hipEventDisableTiming));
     launch_fill_i32(S.cnt.as<int32_t>(), 0, nleaf, S.s);
     launch_fill_i32(S.ctl.as<int32_t>(), 0, CTL_WORDS, S.s);
     launch_fill_i32(S.done.as<int32_t>(), 0, 1, S.s);
@@ -260,8 +264,90 @@ static int64_t session_admit(Session &S, std::unique_lock<std::mutex> &lk)
 constexpr int SERVED_DENSE_MIN = 8;
 
 
-// One round: route the last round's queries and the new ones, buffer them, scan.
-static void session_round(Session &S, int64_t nnew)
+// Wait for an event recorded on the session's stream, spinning (a blocking wait can sleep
+// well past the event on a busy host, and every round waits once).
+static void session_wait_event(hipEvent_t ev)
+{
+    for (int spins = 0;; spins++) {
+        const hipError_t e = hipEventQuery(ev);
+        if (e == hipSuccess) return;
+        if (e != hipErrorNotReady) BKD_HIP(e);
+        if ((spins & 63) == 63) std::this_thread::yield();
+    }
+}
+
+// Delivery of finished requests, part one (no server lock): every finished request's slot
+// list up, one gather per request, the results down, then an event; queued before the
+// round's scans, so the wait for it does not cover them.
+static void session_deliver_begin(Session &S, const std::vector<Request *> &fin)
+{
+    int64_t nslots = 0, nout = 0;
+    for (Request *r : fin) {
+        nslots += r->m;
+        nout += r->m * r->k;
+    }
+    S.hgslots.ensure(sizeof(int32_t) * (size_t)nslots);
+    S.gslots.ensure(sizeof(int32_t) * (size_t)nslots);
+    S.oidx.ensure(sizeof(int64_t) * (size_t)nout);
+    S.odist.ensure(sizeof(float) * (size_t)nout);
+    S.hout.ensure((sizeof(int64_t) + sizeof(float)) * (size_t)nout);
+    int64_t so = 0;
+    for (Request *r : fin) {
+        std::memcpy(S.hgslots.as<int32_t>() + so, r->slots.data(), sizeof(int32_t) * (size_t)r->m);
+        so += r->m;
+    }
+    BKD_HIP(hipMemcpyAsync(S.gslots.p, S.hgslots.p, sizeof(int32_t) * (size_t)nslots, hipMemcpyHostToDevice, S.s));
+    so = 0;
+    int64_t oo = 0;
+    for (Request *r : fin) {
+        const int64_t cnt = r->m * r->k;
+        k_gather<<<(unsigned)((cnt + 255) / 256), 256, 0, S.s>>>(
+            S.keys.as<uint64_t>(), S.gslots.as<int32_t>() + so, r->m, S.K, r->k, S.oidx.as<int64_t>() + oo,
+            S.odist.as<float>() + oo, (S.srv->flags & BKD_FLAG_SQUARED) ? 1 : 0);
+        so += r->m;
+        oo += cnt;
+    }
+    int64_t *hidx = S.hout.as<int64_t>();
+    float *hdist = reinterpret_cast<float *>(hidx + nout);
+    BKD_HIP(hipMemcpyAsync(hidx, S.oidx.p, sizeof(int64_t) * (size_t)nout, hipMemcpyDeviceToHost, S.s));
+    BKD_HIP(hipMemcpyAsync(hdist, S.odist.p, sizeof(float) * (size_t)nout, hipMemcpyDeviceToHost, S.s));
+    BKD_HIP(hipEventRecord(S.ev_out, S.s));
+}
+
+// Part two: once the results are on the host, copy them to the callers' arrays, then (under
+// the server lock) free the requests' slots and tables and wake the waiters.
+static void session_deliver_end(Session &S, std::unique_lock<std::mutex> &lk, const std::vector<Request *> &fin)
+{
+    session_wait_event(S.ev_out);
+    int64_t nout = 0;
+    for (Request *r : fin) nout += r->m * r->k;
+    const int64_t *hidx = S.hout.as<int64_t>();
+    const float *hdist = reinterpret_cast<const float *>(hidx + nout);
+    int64_t oo = 0;
+    for (Request *r : fin) {
+        const int64_t cnt = r->m * r->k;
+        std::memcpy(r->out_idx, hidx + oo, sizeof(int64_t) * (size_t)cnt);
+        std::memcpy(r->out_dist, hdist + oo, sizeof(float) * (size_t)cnt);
+        oo += cnt;
+        r->t_done = now_s();
+    }
+    lk.lock();
+    for (Request *r : fin) {
+        S.running.erase(r->table);
+        S.free_tables.push_back(r->table);
+        S.free_slots.insert(S.free_slots.end(), r->slots.begin(), r->slots.end());
+        r->slots.clear();
+        r->slots.shrink_to_fit();
+        r->state = r->cancel ? 3 : 2;
+    }
+    S.srv->done_cv.notify_all();
+    lk.unlock();
+}
+
+// One round: route the last round's queries and the new ones, buffer them, read the counts
+// and the completion list back (the round's one wait, which also covers the last round's
+// scans), hand the finished requests' results down, scan.  Called without the server lock.
+static void session_round(Session &S, int64_t nnew, std::unique_lock<std::mutex> &lk)
 {
     Tree &T = S.tree->t;
     const HostTree &H = T.host;
@@ -339,8 +425,26 @@ static void session_round(Session &S, int64_t nnew)
                         T.dense_min == INT32_MAX ? INT32_MAX : SERVED_DENSE_MIN,
                         S.off.as<int32_t>(), S.tiles.as<int32_t>(), S.tiles.as<int32_t>() + nleaf + 1, ctl, S.s);
     BKD_HIP(hipMemcpyAsync(hctl, ctl, sizeof(int32_t) * CTL_WORDS, hipMemcpyDeviceToHost, S.s));
-    BKD_HIP(hipStreamSynchronize(S.s));
+    // the completion list (its count and every entry, at most max_req): requests whose last
+    // query finished in this round's routing or in the last round's tail launches
+    BKD_HIP(hipMemcpyAsync(S.hdone.p, S.done.p, sizeof(int32_t) * (size_t)(1 + S.max_req), hipMemcpyDeviceToHost,
+                           S.s));
+    BKD_HIP(hipEventRecord(S.ev_sync, S.s));
+    session_wait_event(S.ev_sync);
     S.P = hctl[CTL_V];
+    std::vector<Request *> fin;
+    const double tc = now_s();
+    if (const int nd = S.hdone.as<int32_t>()[0]) {
+        launch_fill_i32(S.done.as<int32_t>(), 0, 1, S.s);  // before any launch that appends to it
+        lk.lock();
+        for (int x = 0; x < nd; x++) {
+            auto it = S.running.find(S.hdone.as<int32_t>()[1 + x]);
+            if (it != S.running.end()) fin.push_back(it->second);
+        }
+        lk.unlock();
+        if (!fin.empty()) session_deliver_begin(S, fin);
+    }
+    S.complete_s += now_s() - tc;
     const int64_t aged = S.age_max > 0 ? hctl[CTL_AGED] : 0;
     if (aged > 0) {
         // queries routed more than age_max times sort last: each walks the rest of its traversal
@@ -434,74 +538,11 @@ static void session_round(Session &S, int64_t nnew)
         S.scans++;
     }
     S.rounds++;
-}
-
-// Deliver completed requests (their last query finished in this round's routing).
-static void session_complete(Session &S, std::unique_lock<std::mutex> &lk)
-{
-    // the completion list: its count and every entry in one copy (at most max_req entries)
-    BKD_HIP(hipMemcpyAsync(S.hdone.p, S.done.p, sizeof(int32_t) * (size_t)(1 + S.max_req), hipMemcpyDeviceToHost,
-                           S.s));
-    BKD_HIP(hipStreamSynchronize(S.s));
-    const int nd = S.hdone.as<int32_t>()[0];
-    if (nd == 0) return;
-    launch_fill_i32(S.done.as<int32_t>(), 0, 1, S.s);
-    std::vector<Request *> fin;
-    for (int x = 0; x < nd; x++) {
-        auto it = S.running.find(S.hdone.as<int32_t>()[1 + x]);
-        if (it != S.running.end()) fin.push_back(it->second);
+    if (!fin.empty()) {
+        const double td = now_s();
+        session_deliver_end(S, lk, fin);
+        S.complete_s += now_s() - td;
     }
-    lk.unlock();
-    // every finished request in one pass: slot lists up, one gather per request, results down
-    int64_t nslots = 0, nout = 0;
-    for (Request *r : fin) {
-        nslots += r->m;
-        nout += r->m * r->k;
-    }
-    S.hgslots.ensure(sizeof(int32_t) * (size_t)nslots);
-    S.gslots.ensure(sizeof(int32_t) * (size_t)nslots);
-    S.oidx.ensure(sizeof(int64_t) * (size_t)nout);
-    S.odist.ensure(sizeof(float) * (size_t)nout);
-    S.hout.ensure((sizeof(int64_t) + sizeof(float)) * (size_t)nout);
-    int64_t so = 0;
-    for (Request *r : fin) {
-        std::memcpy(S.hgslots.as<int32_t>() + so, r->slots.data(), sizeof(int32_t) * (size_t)r->m);
-        so += r->m;
-    }
-    BKD_HIP(hipMemcpyAsync(S.gslots.p, S.hgslots.p, sizeof(int32_t) * (size_t)nslots, hipMemcpyHostToDevice, S.s));
-    so = 0;
-    int64_t oo = 0;
-    for (Request *r : fin) {
-        const int64_t cnt = r->m * r->k;
-        k_gather<<<(unsigned)((cnt + 255) / 256), 256, 0, S.s>>>(
-            S.keys.as<uint64_t>(), S.gslots.as<int32_t>() + so, r->m, S.K, r->k, S.oidx.as<int64_t>() + oo,
-            S.odist.as<float>() + oo, (S.srv->flags & BKD_FLAG_SQUARED) ? 1 : 0);
-        so += r->m;
-        oo += cnt;
-    }
-    int64_t *hidx = S.hout.as<int64_t>();
-    float *hdist = reinterpret_cast<float *>(hidx + nout);
-    BKD_HIP(hipMemcpyAsync(hidx, S.oidx.p, sizeof(int64_t) * (size_t)nout, hipMemcpyDeviceToHost, S.s));
-    BKD_HIP(hipMemcpyAsync(hdist, S.odist.p, sizeof(float) * (size_t)nout, hipMemcpyDeviceToHost, S.s));
-    BKD_HIP(hipStreamSynchronize(S.s));
-    oo = 0;
-    for (Request *r : fin) {
-        const int64_t cnt = r->m * r->k;
-        std::memcpy(r->out_idx, hidx + oo, sizeof(int64_t) * (size_t)cnt);
-        std::memcpy(r->out_dist, hdist + oo, sizeof(float) * (size_t)cnt);
-        oo += cnt;
-        r->t_done = now_s();
-    }
-    lk.lock();
-    for (Request *r : fin) {
-        S.running.erase(r->table);
-        S.free_tables.push_back(r->table);
-        S.free_slots.insert(S.free_slots.end(), r->slots.begin(), r->slots.end());
-        r->slots.clear();
-        r->slots.shrink_to_fit();
-        r->state = r->cancel ? 3 : 2;
-    }
-    S.srv->done_cv.notify_all();
 }
 
 static void session_loop(Session *Sp)
@@ -521,13 +562,10 @@ static void session_loop(Session *Sp)
                 continue;
             }
             lk.unlock();
-            const double t0 = now_s();
-            session_round(S, nnew);
-            S.busy_s += now_s() - t0;
+            const double t0 = now_s(), c0 = S.complete_s;
+            session_round(S, nnew, lk);
+            S.busy_s += now_s() - t0 - (S.complete_s - c0);  // the delivery inside is counted apart
             lk.lock();
-            const double tc = now_s();
-            session_complete(S, lk);
-            S.complete_s += now_s() - tc;
         }
     } catch (const BkdError &e) {
         std::lock_guard<std::mutex> g(V.mu);
@@ -742,6 +780,8 @@ int bkd_server_destroy(bkd_server *srv)
         (void)hipDeviceSynchronize();
         for (auto &s : srv->v.sessions) {
             if (s->ev_stage) (void)hipEventDestroy(s->ev_stage);
+            if (s->ev_sync) (void)hipEventDestroy(s->ev_sync);
+            if (s->ev_out) (void)hipEventDestroy(s->ev_out);
             if (s->s) (void)hipStreamDestroy(s->s);
         }
         delete srv;
