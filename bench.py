@@ -320,6 +320,28 @@ def run_served(args, torch, bkd, plain_requests=600, cpu_queries=None):
                              "requests": len(trace), "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
                              "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3)}
     srv.destroy()
+    latency_mode = None
+    if args.served_latency_age_max > 0:
+        # the same trees and traces with the age hand-over: a query still travelling after
+        # that many rounds finishes its traversal alone, which bounds a request's round count
+        # (lower latency, lower saturated rate)
+        note(f"served: age hand-over after {args.served_latency_age_max} rounds")
+        srv = bkd.server_create(slots_per_session=1 << 21, age_max=args.served_latency_age_max,
+                                tail_max=args.served_tail_max)
+        tids = [bkd.server_add_tree(srv, t) for t in trees]
+        replay(warm, request_queries(warm), False)
+        wall_l, _ = replay(closed, Qc, False)
+        x_sat_l = qc / wall_l
+        rate = 0.5 * x_sat_l / mean_m
+        trace = datagen.request_trace(args.seed + 5, args.served_requests // 4, rate)
+        wall, lat = replay(trace, request_queries(trace), True)
+        latency_mode = {"age_max": args.served_latency_age_max, "saturated_queries_per_s": round(x_sat_l, 1),
+                        "open_loop_0.5": {"offered_queries_per_s": round(0.5 * x_sat_l, 1),
+                                          "achieved_queries_per_s": round(sum(r["m"] for r in trace) / wall, 1),
+                                          "requests": len(trace),
+                                          "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                                          "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3)}}
+        srv.destroy()
     for t in trees:
         t.free()
     cpu = None
@@ -343,7 +365,8 @@ def run_served(args, torch, bkd, plain_requests=600, cpu_queries=None):
                    "plain_loop_queries_per_s": round(loop_qps, 1),
                    "plain_loop_requests": npl,
                    "speedup_vs_plain_loop": round(x_sat / loop_qps, 2),
-                   "open_loop": levels},
+                   "open_loop": levels,
+                   "latency_mode": latency_mode},
     }
     if cpu:
         out["cpu_baseline"] = cpu
@@ -443,6 +466,8 @@ def main():
     ap.add_argument("--served-requests", type=int, default=2000, help="requests per open-loop level")
     ap.add_argument("--served-age-max", type=int, default=0,
                     help="served form: rounds after which a query leaves the rounds for a single walk (0: never)")
+    ap.add_argument("--served-latency-age-max", type=int, default=64,
+                    help="served form: also measure the age hand-over after this many rounds (0: skip)")
     ap.add_argument("--served-tail-max", type=int, default=0,
                     help="served form: queries in flight at or below which a round hands them to single walks "
                          "(0: the library default)")
@@ -490,7 +515,7 @@ def main():
         # the bigger-than-budget (streamed) workload and the served form's latency
         deadline = T_START + args.time_budget
         out["streamed"] = section("streamed", deadline, 240, lambda: streamed_summary(args, torch, bkd))
-        out["served"] = section("served", deadline, 200, lambda: served_summary(args, torch, bkd))
+        out["served"] = section("served", deadline, 260, lambda: served_summary(args, torch, bkd))
     print(json.dumps(out), flush=True)
 
 
