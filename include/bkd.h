@@ -62,6 +62,8 @@ extern "C" {
 #define BKD_FLAG_DEVICE_BUILD 16 /* build the top tree on the device: one stable radix sort per     */
                                  /* level (the same canonical tree as the host build, Section 2.3); */
                                  /* needs about 8d + 32 bytes of device memory per point meanwhile  */
+#define BKD_FLAG_DEVICE_PTRS 32 /* batched form: every instance's P, Q, out_idx and out_dist are    */
+                                /* device pointers on the batch's device (else host pointers)       */
 
 /* Splitting rule and pruning bound of the tree (Section 2.3).  The original k-d tree splits
    dimension (level mod d) and prunes with the splitting hyperplane; the footnote on splitting
@@ -347,15 +349,15 @@ int bkd_trace_get(const bkd_tree *tree, int64_t *call_off, int32_t *query, int32
 /* unspecified in this form; results are the same as bkd_query's.           */
 
 typedef struct bkd_instance {
-    const float *P;     /* host [n][d] float32, finite                              */
+    const float *P;     /* [n][d] float32, finite; host (device: BKD_FLAG_DEVICE_PTRS) */
     int64_t n;          /* 1 <= n <= 2^31 - 1                                       */
-    const float *Q;     /* host [m][d] float32, finite                              */
+    const float *Q;     /* [m][d] float32, finite; host (device: BKD_FLAG_DEVICE_PTRS) */
     int64_t m;          /* 0 <= m <= 2^31 - 1                                       */
     int32_t d;          /* 1 <= d <= BKD_MAX_DIM                                    */
     int32_t k;          /* 1 <= k <= min(n, BKD_MAX_K)                              */
     int32_t height;     /* 0 <= h <= 12 and 2^h <= n                                */
-    int64_t *out_idx;   /* host [m][k], filled by bkd_batch_results                 */
-    float *out_dist;    /* host [m][k], filled by bkd_batch_results                 */
+    int64_t *out_idx;   /* [m][k], filled by bkd_batch_results; host or device      */
+    float *out_dist;    /* [m][k], filled by bkd_batch_results; host or device      */
 } bkd_instance;
 
 /* Schedule of the persistent launch (results do not depend on it). */
@@ -384,9 +386,12 @@ typedef struct bkd_batch bkd_batch;
 /*
  * Build every instance's tree on the host (Section 3.1) and upload trees and
  * queries to `device`.  The library copies P and Q; the out_* pointers are
- * kept and written by bkd_batch_results.  flags: BKD_FLAG_SQUARED or 0.
- * Errors: BKD_EINVAL (any instance's arguments, with its index in the
- * message), BKD_ENOMEM, BKD_EDEVICE.
+ * kept and written by bkd_batch_results.  flags: BKD_FLAG_SQUARED and
+ * BKD_FLAG_DEVICE_PTRS (P, Q and the outputs of every instance are device
+ * memory on `device`: P and Q are read back for the host build, results are
+ * copied device to device).  Errors: BKD_EINVAL (any instance's arguments,
+ * with its index in the message, including a pointer that is not device
+ * memory under BKD_FLAG_DEVICE_PTRS), BKD_ENOMEM, BKD_EDEVICE.
  */
 int bkd_batch_create(const bkd_instance *inst, int32_t count, int32_t device, int32_t flags, bkd_batch **out);
 
@@ -407,6 +412,17 @@ int bkd_batch_results(bkd_batch *batch);
  * *best and *best_ms (either may be NULL) receive the winner.
  */
 int bkd_batch_autotune(bkd_batch *batch, bkd_tuning *best, double *best_ms);
+
+/*
+ * Persistent tuning cache (a text file, one line per batch signature: the device's architecture
+ * name and compute-unit count and every instance's n, m, d, k and height).  _save writes the
+ * batch's tuning (from bkd_batch_autotune or an earlier _load) in place of any line of the same
+ * signature; BKD_EINVAL if the batch is untuned or the file cannot be written.  _load makes the
+ * cached tuning the batch's own, as bkd_batch_autotune would, and copies it to *tuning (may be
+ * NULL); BKD_ENOTFOUND if the file or its line is missing.  The caller owns the path string.
+ */
+int bkd_batch_tuning_save(const bkd_batch *batch, const char *path);
+int bkd_batch_tuning_load(bkd_batch *batch, const char *path, bkd_tuning *tuning);
 
 int bkd_batch_stats_get(const bkd_batch *batch, bkd_batch_stats *out);
 int bkd_batch_free(bkd_batch *batch);

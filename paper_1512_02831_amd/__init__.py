@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libbkd.so")
 
 OK, EINVAL, ENOMEM, EBUDGET, EDEVICE, EBUSY, ETIMEOUT, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7
 CHUNK_LEAF, CHUNK_POSITION = 0, 1
-FLAG_TRACE, FLAG_TIMING, FLAG_SQUARED, FLAG_NO_TAIL, FLAG_DEVICE_BUILD = 1, 2, 4, 8, 16
+FLAG_TRACE, FLAG_TIMING, FLAG_SQUARED, FLAG_NO_TAIL, FLAG_DEVICE_BUILD, FLAG_DEVICE_PTRS = 1, 2, 4, 8, 16, 32
 MAX_DIM, MAX_K, MAX_HEIGHT = 32, 64, 24
 SPLIT_CYCLIC, SPLIT_LONGEST = 0, 1
 PRUNE_PLANE, PRUNE_BOX = 0, 1
@@ -87,6 +87,8 @@ _PROTOS = {
     "bkd_batch_run": (ctypes.c_int, [_V, _V, _V]),
     "bkd_batch_results": (ctypes.c_int, [_V]),
     "bkd_batch_autotune": (ctypes.c_int, [_V, _V, _V]),
+    "bkd_batch_tuning_save": (ctypes.c_int, [_V, ctypes.c_char_p]),
+    "bkd_batch_tuning_load": (ctypes.c_int, [_V, ctypes.c_char_p, _V]),
     "bkd_batch_stats_get": (ctypes.c_int, [_V, _V]),
     "bkd_batch_free": (ctypes.c_int, [_V]),
     "bkd_server_create": (ctypes.c_int, [_V, _V]),
@@ -364,9 +366,27 @@ class Batch:
 
 
 def batch_create(instances, device: int = 0, flags: int = 0) -> Batch:
-    """``bkd_batch_create``: instances = iterable of (P [n,d], Q [m,d], k, height)."""
+    """``bkd_batch_create``: instances = iterable of (P [n,d], Q [m,d], k, height); numpy
+    arrays, or with FLAG_DEVICE_PTRS torch float32 tensors on the GPU (the outputs are then
+    torch tensors on the GPU too)."""
     inst = (Instance * max(1, len(instances)))()
     arrays, outputs = [], []
+    if flags & FLAG_DEVICE_PTRS:
+        import torch
+        for i, (P, Q, k, h) in enumerate(instances):
+            P = P.contiguous()
+            Q = Q.contiguous()
+            m = Q.shape[0]
+            oi = torch.zeros((m, k), dtype=torch.int64, device=P.device)
+            od = torch.zeros((m, k), dtype=torch.float32, device=P.device)
+            arrays += [P, Q]
+            outputs.append((oi, od))
+            inst[i] = Instance(P.data_ptr(), P.shape[0], Q.data_ptr() if m else None, m, P.shape[1], k, h,
+                               oi.data_ptr() if m else None, od.data_ptr() if m else None)
+        h = ctypes.c_void_p()
+        _check(lib().bkd_batch_create(ctypes.cast(inst, ctypes.c_void_p), len(instances), device, flags,
+                                      ctypes.byref(h)))
+        return Batch(h.value, arrays, outputs)
     for i, (P, Q, k, h) in enumerate(instances):
         P = np.ascontiguousarray(P, dtype=np.float32)
         Q = np.ascontiguousarray(Q, dtype=np.float32)
@@ -399,6 +419,18 @@ def batch_autotune(batch: Batch):
     ms = ctypes.c_double()
     _check(lib().bkd_batch_autotune(batch.handle, ctypes.byref(t), ctypes.byref(ms)))
     return t, ms.value
+
+
+def batch_tuning_save(batch: Batch, path: str):
+    """``bkd_batch_tuning_save``: the batch's tuning into the cache file."""
+    _check(lib().bkd_batch_tuning_save(batch.handle, path.encode()))
+
+
+def batch_tuning_load(batch: Batch, path: str):
+    """``bkd_batch_tuning_load``: the cached tuning of this batch (raises ENOTFOUND if absent)."""
+    t = Tuning()
+    _check(lib().bkd_batch_tuning_load(batch.handle, path.encode(), ctypes.byref(t)))
+    return t
 
 
 def batch_stats(batch: Batch) -> dict:

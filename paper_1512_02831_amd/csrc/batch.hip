@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cmath>
 #include <map>
 #include <tuple>
@@ -740,18 +741,60 @@ template <class T> static void upload(DevBuf &b, const std::vector<T> &v)
     if (!v.empty()) BKD_HIP(hipMemcpy(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
 }
 
-Batch *batch_create(const bkd_instance *in, int32_t count, int32_t device, int32_t flags)
+// Under BKD_FLAG_DEVICE_PTRS: every pointer of the instances must be device memory on `device`.
+static void check_device_pointer(const void *p, int device, int i, const char *what)
 {
-    batch_validate(in, count);
+    hipPointerAttribute_t at{};
+    const hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess || at.type != hipMemoryTypeDevice || at.device != device) {
+        (void)hipGetLastError();
+        fail(BKD_EINVAL, "instance " + std::to_string(i) + ": " + what + " is not device memory on the batch's device");
+    }
+}
+
+Batch *batch_create(const bkd_instance *in_given, int32_t count, int32_t device, int32_t flags)
+{
+    if (!in_given || count < 0) fail(BKD_EINVAL, "instances must be a non-NULL array and count >= 0");
     int ndev = 0;
     BKD_HIP(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) fail(BKD_EINVAL, "device ordinal out of range");
     BKD_HIP(hipSetDevice(device));
+    // device instances: P and Q read back into host copies for the host build and checks
+    const bool dev_ptrs = (flags & BKD_FLAG_DEVICE_PTRS) != 0;
+    std::vector<bkd_instance> hin;
+    std::vector<std::vector<float>> hcopy;
+    const bkd_instance *in = in_given;
+    if (dev_ptrs) {
+        hin.assign(in_given, in_given + count);
+        hcopy.resize(2 * (size_t)count);
+        for (int i = 0; i < count; i++) {
+            bkd_instance &x = hin[(size_t)i];
+            if (x.n < 1 || x.n > INT32_MAX || x.d < 1 || x.d > BKD_MAX_DIM || x.m < 0 || x.m > INT32_MAX) continue;
+            if (x.P) {
+                check_device_pointer(x.P, device, i, "P");
+                hcopy[2 * (size_t)i].resize((size_t)(x.n * x.d));
+                BKD_HIP(hipMemcpy(hcopy[2 * (size_t)i].data(), x.P, sizeof(float) * (size_t)(x.n * x.d),
+                                  hipMemcpyDeviceToHost));
+                x.P = hcopy[2 * (size_t)i].data();
+            }
+            if (x.m > 0 && x.Q) {
+                check_device_pointer(x.Q, device, i, "Q");
+                hcopy[2 * (size_t)i + 1].resize((size_t)(x.m * x.d));
+                BKD_HIP(hipMemcpy(hcopy[2 * (size_t)i + 1].data(), x.Q, sizeof(float) * (size_t)(x.m * x.d),
+                                  hipMemcpyDeviceToHost));
+                x.Q = hcopy[2 * (size_t)i + 1].data();
+            }
+            if (x.m > 0 && x.out_idx) check_device_pointer(x.out_idx, device, i, "out_idx");
+            if (x.m > 0 && x.out_dist) check_device_pointer(x.out_dist, device, i, "out_dist");
+        }
+        in = hin.data();
+    }
+    batch_validate(in, count);
     auto b = std::make_unique<Batch>();
     b->device = device;
     b->count = count;
     b->flags = flags;
-    b->inst.assign(in, in + count);
+    b->inst.assign(in_given, in_given + count);  // the caller's output pointers (host or device)
     // trees, built in parallel over instances
     std::vector<HostTree> trees((size_t)count);
     parallel_for(count, [&](int64_t lo, int64_t hi) {
@@ -961,6 +1004,20 @@ void batch_results(Batch &b)
     if (!b.ran) fail(BKD_EINVAL, "bkd_batch_run has not been called");
     BQueue q = read_queue(b);
     if (q.error) fail(BKD_EDEVICE, "batched launch stopped early (error flag " + std::to_string(q.error) + ")");
+    if (b.flags & BKD_FLAG_DEVICE_PTRS) {
+        // device outputs: one device-to-device copy per instance and array
+        for (int i = 0; i < b.count; i++) {
+            const bkd_instance &x = b.inst[(size_t)i];
+            const int64_t o = b.desc[(size_t)i].key_off, c = x.m * x.k;
+            if (!c) continue;
+            BKD_HIP(hipMemcpyAsync(x.out_idx, b.d_oidx.as<int64_t>() + o, sizeof(int64_t) * c,
+                                   hipMemcpyDeviceToDevice, b.cap_stream));
+            BKD_HIP(hipMemcpyAsync(x.out_dist, b.d_odist.as<float>() + o, sizeof(float) * c,
+                                   hipMemcpyDeviceToDevice, b.cap_stream));
+        }
+        BKD_HIP(hipStreamSynchronize(b.cap_stream));
+        return;
+    }
     std::vector<int64_t> idx((size_t)b.keys_total);
     std::vector<float> dist((size_t)b.keys_total);
     if (b.keys_total) {
@@ -1025,6 +1082,76 @@ void batch_autotune(Batch &b, bkd_tuning *best, double *best_ms)
     if (best_ms) *best_ms = bm;
 }
 
+// Signature of a batch for the tuning cache: the device's name and compute-unit count, and every
+// instance's (n, m, d, k, height), hashed with 64-bit FNV-1a.
+static uint64_t batch_signature(const Batch &b)
+{
+    uint64_t hsh = 1469598103934665603ull;
+    auto mix = [&](const void *p, size_t n) {
+        const unsigned char *c = static_cast<const unsigned char *>(p);
+        for (size_t i = 0; i < n; i++) hsh = (hsh ^ c[i]) * 1099511628211ull;
+    };
+    hipDeviceProp_t prop;
+    BKD_HIP(hipGetDeviceProperties(&prop, b.device));
+    mix(prop.gcnArchName, std::strlen(prop.gcnArchName));
+    mix(&b.cus, sizeof(b.cus));
+    for (const bkd_instance &x : b.inst) {
+        const int64_t v[5] = {x.n, x.m, x.d, x.k, x.height};
+        mix(v, sizeof(v));
+    }
+    return hsh;
+}
+
+// The tuning cache: a text file of lines "signature leaves_per_task groups_per_cu solo_max ms".
+void batch_tuning_save(const Batch &b, const char *path)
+{
+    if (!path) fail(BKD_EINVAL, "path is NULL");
+    if (!b.have_tuned) fail(BKD_EINVAL, "the batch has not been tuned (bkd_batch_autotune)");
+    const uint64_t sig = batch_signature(b);
+    std::vector<std::string> keep;
+    if (FILE *f = std::fopen(path, "r")) {  // other batches' lines stay
+        char line[256];
+        while (std::fgets(line, sizeof line, f)) {
+            unsigned long long s = 0;
+            if (std::sscanf(line, "%llx", &s) == 1 && s != sig) keep.emplace_back(line);
+        }
+        std::fclose(f);
+    }
+    FILE *f = std::fopen(path, "w");
+    if (!f) fail(BKD_EINVAL, std::string("cannot write the tuning cache ") + path);
+    for (const std::string &l : keep) std::fputs(l.c_str(), f);
+    std::fprintf(f, "%016llx %d %d %d\n", (unsigned long long)sig, b.tuned.leaves_per_task, b.tuned.groups_per_cu,
+                 b.tuned.solo_max);
+    const bool ok = std::fclose(f) == 0;
+    if (!ok) fail(BKD_EINVAL, std::string("cannot write the tuning cache ") + path);
+}
+
+// Returns false (nothing changed) when the cache has no line for this batch.
+bool batch_tuning_load(Batch &b, const char *path, bkd_tuning *out)
+{
+    if (!path) fail(BKD_EINVAL, "path is NULL");
+    const uint64_t sig = batch_signature(b);
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[256];
+    bool found = false;
+    bkd_tuning t{};
+    while (std::fgets(line, sizeof line, f)) {
+        unsigned long long s = 0;
+        bkd_tuning u{};
+        if (std::sscanf(line, "%llx %d %d %d", &s, &u.leaves_per_task, &u.groups_per_cu, &u.solo_max) == 4 && s == sig) {
+            t = u;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    if (!found) return false;
+    b.tuned = normalise(&t);
+    b.have_tuned = true;
+    if (out) *out = b.tuned;
+    return true;
+}
+
 }  // namespace bkd
 
 struct bkd_batch {
@@ -1068,6 +1195,23 @@ int bkd_batch_autotune(bkd_batch *batch, bkd_tuning *best, double *best_ms)
     return bkd::guarded_call([&] {
         if (!batch) bkd::fail(BKD_EINVAL, "batch is NULL");
         bkd::batch_autotune(*batch->b, best, best_ms);
+    });
+}
+
+int bkd_batch_tuning_save(const bkd_batch *batch, const char *path)
+{
+    return bkd::guarded_call([&] {
+        if (!batch) bkd::fail(BKD_EINVAL, "batch is NULL");
+        bkd::batch_tuning_save(*batch->b, path);
+    });
+}
+
+int bkd_batch_tuning_load(bkd_batch *batch, const char *path, bkd_tuning *tuning)
+{
+    return bkd::guarded_call([&] {
+        if (!batch) bkd::fail(BKD_EINVAL, "batch is NULL");
+        if (!bkd::batch_tuning_load(*batch->b, path, tuning))
+            bkd::fail(BKD_ENOTFOUND, "no tuning for this batch in the cache");
     });
 }
 

@@ -54,6 +54,39 @@ def test_batch_mixed_shapes_match_oracle_and_single_path():
         assert np.array_equal(i2, idx) and np.array_equal(e2, d2), i
 
 
+def test_batch_device_pointers_match_host_pointers():
+    """BKD_FLAG_DEVICE_PTRS: P, Q and the outputs on the GPU (torch tensors) give the host
+    form's results, and the oracle's; a host pointer under the flag is refused."""
+    import torch
+    say("case: batch of 16 mixed instances from device pointers")
+    inst = mixed_instances(23, 16)
+    dev = [(torch.from_numpy(P).cuda(), torch.from_numpy(Q).cuda(), k, h) for P, Q, k, h in inst]
+    with bkd.batch_create(dev, flags=bkd.FLAG_SQUARED | bkd.FLAG_DEVICE_PTRS) as b:
+        bkd.batch_run(b)
+        res = [(i.cpu().numpy(), d.cpu().numpy()) for i, d in bkd.batch_results(b)]
+    with bkd.batch_create(inst, flags=bkd.FLAG_SQUARED) as b:
+        bkd.batch_run(b)
+        ref = bkd.batch_results(b)
+    for i, ((P, Q, k, h), (idx, d2), (ri, rd)) in enumerate(zip(inst, res, ref)):
+        assert np.array_equal(idx, ri) and np.array_equal(d2, rd), i
+        if len(Q):
+            assert np.array_equal(keys_of(idx, d2), oracle.brute_f32c(P, Q, k)), i
+    # a host array where the flag promises device memory
+    P, Q, k, h = inst[0]
+    bad = [(dev[0][0], dev[0][1], k, h)]
+    host_p = np.ascontiguousarray(P)
+    inst_t = (bkd.Instance * 1)()
+    oi = torch.zeros((len(Q), k), dtype=torch.int64, device="cuda")
+    od = torch.zeros((len(Q), k), dtype=torch.float32, device="cuda")
+    inst_t[0] = bkd.Instance(host_p.ctypes.data, len(P), bad[0][1].data_ptr(), len(Q), P.shape[1], k, h,
+                             oi.data_ptr(), od.data_ptr())
+    import ctypes
+    hnd = ctypes.c_void_p()
+    rc = bkd.lib().bkd_batch_create(ctypes.cast(inst_t, ctypes.c_void_p), 1, 0, bkd.FLAG_DEVICE_PTRS,
+                                    ctypes.byref(hnd))
+    assert rc == bkd.EINVAL and "not device memory" in bkd.lib().bkd_last_error().decode()
+
+
 def test_batch_same_alone_and_in_mix_and_under_tunings():
     say("case: alone vs mix, tunings")
     inst = mixed_instances(11, 24)
@@ -107,3 +140,27 @@ def test_batched_config_sampled_parity():
         rows = rng.choice(len(Q), min(len(Q), 64), replace=False)
         idx, d2 = res[i]
         assert np.array_equal(keys_of(idx[rows], d2[rows]), oracle.brute_f32c(P, Q[rows], k)), i
+
+
+def test_batch_tuning_cache_roundtrip(tmp_path):
+    """The tuning cache keeps one line per batch signature: a new batch of the same shapes
+    loads the tuned schedule, another batch finds none, and the results do not depend on it."""
+    say("case: tuning cache")
+    inst = mixed_instances(29, 12)
+    path = str(tmp_path / "tuning.txt")
+    with bkd.batch_create(inst) as b:
+        best, _ = bkd.batch_autotune(b)
+        bkd.batch_tuning_save(b, path)
+        bkd.batch_run(b)
+        want = [(i.copy(), d.copy()) for i, d in bkd.batch_results(b)]
+    with bkd.batch_create(inst) as b2:
+        got = bkd.batch_tuning_load(b2, path)
+        assert (got.leaves_per_task, got.groups_per_cu, got.solo_max) == \
+            (best.leaves_per_task, best.groups_per_cu, best.solo_max)
+        bkd.batch_run(b2)
+        for (i1, d1), (i2, d2) in zip(want, bkd.batch_results(b2)):
+            assert np.array_equal(i1, i2) and np.array_equal(d1, d2)
+    with bkd.batch_create(mixed_instances(31, 5)) as b3:
+        with pytest.raises(bkd.BkdError) as e:
+            bkd.batch_tuning_load(b3, path)
+        assert e.value.code == bkd.ENOTFOUND
