@@ -54,8 +54,11 @@ WORKLOADS = {
 }
 
 
+# the dense scan's source, its instantiations, the constants that shape its launches (query tile,
+# dense threshold, launch arguments) and the build flags: counters taken before a change to any of
+# them no longer describe the launch
 KERNEL_FILES = ("paper_1512_02831_amd/csrc/leaf_scan.h", "paper_1512_02831_amd/csrc/scan_inst.h",
-                "paper_1512_02831_amd/compile.py")
+                "paper_1512_02831_amd/csrc/internal.h", "paper_1512_02831_amd/compile.py")
 
 
 def kernel_source_hash():

@@ -115,12 +115,15 @@ enum Ctl : int {
 
 // Query-tile width of the dense leaf scan (queries per work item), and the
 // buffer fill below which a leaf is scanned with one wave per buffered query.
-// One staged read of a leaf for four queries already beats four waves that each
-// stream the whole leaf: 4 against 32 measured 1.3% faster on the 2^22-point,
-// 4096-point-leaf workload and 19% faster (3.07 -> 2.48 s per call) on the
-// 2^28-point, 16384-point-leaf one (resident), 2 and 8 within 0.3% of 4.
+// A single call scans every buffered leaf densely: one staged read of a leaf
+// with the matrix-core filter costs about what one wave streaming the whole
+// leaf for one query does, and less from two queries on.  1 against 4: 0.8%
+// faster on the 2^22-point, 4096-point-leaf workload (55.2 -> 54.8 ms per
+// call), 7.5% on the 2^28-point, 16384-point-leaf one streamed in 12 chunks
+// (4.91 -> 4.54 s) and 1.7% resident; 2 within 0.4% of 4.  (4 against 32 had
+// measured 1.3% and 19% faster.)
 constexpr int SCAN_QT = 256;
-constexpr int SCAN_DENSE_MIN = 4;
+constexpr int SCAN_DENSE_MIN = 1;
 
 // Disk-backed leaf structure (bkd_options.leaf_path): chunks are read from the
 // file into two pinned staging buffers by a reader thread, then copied to the

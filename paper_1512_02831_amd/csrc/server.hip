@@ -257,10 +257,9 @@ static int64_t session_admit(Session &S, std::unique_lock<std::mutex> &lk)
     return nnew;
 }
 
-// Buffers of at least this many queries take the dense scan in a session round (8 against the
-// single call's 32: a session's rounds hold few queries per leaf, and reading a leaf once for
-// eight queries beats eight walks of it; saturated throughput 0.70 -> 0.77 M queries/s on the
-// two-tree workload).
+// Buffers of at least this many queries take the dense scan in a session round (8 against 32:
+// a session's rounds hold few queries per leaf, and reading a leaf once for eight queries beats
+// eight walks of it; saturated throughput 0.70 -> 0.77 M queries/s on the two-tree workload).
 constexpr int SERVED_DENSE_MIN = 8;
 
 
