@@ -252,11 +252,24 @@ __device__ __forceinline__ int organize_core(const BatchArgs &a, int i, RouteLds
     int32_t *ne = a.ne + I.ne_off;
 
     unsigned long long pr = 0;
-    for (int l = tid; l < nleaf; l += BT) {
-        const int32_t c = cnt[l];
-        cnt[l] = 0;
-        L.cur[l] = c;
-        pr += (unsigned long long)c * (unsigned)(loffs[l + 1] - loffs[l]);
+    constexpr int CU = 4;  // leaves per thread whose loads go out together
+    for (int l0 = tid; l0 < nleaf; l0 += BT * CU) {
+        int32_t c[CU], len[CU];
+#pragma unroll
+        for (int u = 0; u < CU; u++) {
+            const int l = l0 + u * BT;
+            c[u] = l < nleaf ? cnt[l] : 0;
+            len[u] = l < nleaf ? loffs[l + 1] - loffs[l] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < CU; u++) {
+            const int l = l0 + u * BT;
+            if (l < nleaf) {
+                cnt[l] = 0;
+                L.cur[l] = c[u];
+                pr += (unsigned long long)c[u] * (unsigned)len[u];
+            }
+        }
     }
     for (int o = 32; o > 0; o >>= 1) pr += __shfl_xor(pr, o);
     if ((tid & 63) == 0) L.red[tid >> 6] = pr;
@@ -272,9 +285,21 @@ __device__ __forceinline__ int organize_core(const BatchArgs &a, int i, RouteLds
     for (int l = tid; l < nleaf; l += BT)
         if ((l + 1 < nleaf ? L.cur[l + 1] : V) > L.cur[l]) ne[L.hist[l]] = l;
     __syncthreads();
-    for (int j = tid; j < A; j += BT) {
-        const int32_t lf = tmp[j];
-        if (lf >= 0) outb[atomicAdd(&L.cur[lf], 1)] = round == 0 ? j : inb[j];
+    // eight entries per thread at a time: their loads are all issued before the first store
+    // (which the compiler may not move a later load above), so the scatter waits for memory
+    // once per eight entries instead of once per entry
+    constexpr int SU = 8;
+    for (int j0 = tid; j0 < A; j0 += BT * SU) {
+        int32_t lf[SU], id[SU];
+#pragma unroll
+        for (int u = 0; u < SU; u++) {
+            const int j = j0 + u * BT;
+            lf[u] = j < A ? tmp[j] : -1;
+            id[u] = (j < A && round != 0) ? inb[j] : j;
+        }
+#pragma unroll
+        for (int u = 0; u < SU; u++)
+            if (lf[u] >= 0) outb[atomicAdd(&L.cur[lf[u]], 1)] = id[u];
     }
     if (tid == 0) {
         unsigned long long p = 0;
