@@ -456,6 +456,9 @@ typedef struct bkd_server_opts {
                                /* workgroup), so long walks do not hold a request; 0: never       */
     int64_t tail_max;          /* a round with at most this many queries in flight hands them    */
                                /* all to single walks; 0: 16384; < 0: never                       */
+    int32_t straggle_max;      /* > 0: once a request has at most this many queries travelling,   */
+                               /* they leave the rounds for single walks (its slowest walks do    */
+                               /* not hold it one round per leaf); 0: never                       */
 } bkd_server_opts;
 
 typedef struct bkd_server bkd_server;
@@ -503,7 +506,8 @@ typedef struct bkd_server_stats {
     int64_t direct_launches;/* launches of the direct path: requests of at most 2048 queries  */
                             /* skip the rounds, each query walking its whole traversal in one */
                             /* workgroup right after admission                                 */
-    int64_t aged_queries;   /* queries handed from the rounds to single walks (age_max)       */
+    int64_t aged_queries;   /* queries handed from the rounds to single walks (age_max,       */
+                            /* straggle_max)                                                  */
 } bkd_server_stats;
 
 int bkd_server_stats_get(bkd_server *srv, bkd_server_stats *out);

@@ -447,7 +447,8 @@ REQ_WAITING, REQ_RUNNING, REQ_DONE, REQ_CANCELLED = 0, 1, 2, 3
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("slots_per_session", ctypes.c_int64), ("max_requests", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("age_max", ctypes.c_int32), ("tail_max", ctypes.c_int64)]
+                ("flags", ctypes.c_int32), ("age_max", ctypes.c_int32), ("tail_max", ctypes.c_int64),
+                ("straggle_max", ctypes.c_int32)]
 
 
 class Request:
@@ -496,8 +497,8 @@ class Server:
 
 
 def server_create(slots_per_session: int = 0, max_requests: int = 0, device: int = 0, flags: int = 0,
-                  age_max: int = 0, tail_max: int = 0) -> Server:
-    o = ServerOpts(slots_per_session, max_requests, device, flags, age_max, tail_max)
+                  age_max: int = 0, tail_max: int = 0, straggle_max: int = 0) -> Server:
+    o = ServerOpts(slots_per_session, max_requests, device, flags, age_max, tail_max, straggle_max)
     h = ctypes.c_void_p()
     _check(lib().bkd_server_create(ctypes.byref(o), ctypes.byref(h)))
     return Server(h.value)

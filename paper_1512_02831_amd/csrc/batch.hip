@@ -52,6 +52,13 @@ constexpr int TASK_SCAN = 3;
 constexpr int TASK_TAIL = 5;
 constexpr int FIND_CHUNK = 2048;  // active queries per FIND task
 constexpr int TAIL_CHUNK = 16;    // queries per TAIL task (four per wave)
+// A round's leaf scans are dealt out in pieces of at most this many buffered queries of one
+// leaf (an instance with fewer than 2^26 queries; a piece is coded as the unsigned word
+// leaf << 20 | index, leaf < 4096):
+// a leaf holding thousands of queries then spreads over many waves instead of one wave
+// walking them all.
+constexpr int SCAN_PIECE = 64;
+constexpr int PIECE_M_MAX = 1 << 26;
 
 struct BInst {
     int32_t d, k, h, nleaf, m, n;
@@ -331,7 +338,24 @@ __device__ __forceinline__ int organize_core(const BatchArgs &a, int i, RouteLds
 __device__ __forceinline__ void organize_task(const BatchArgs &a, int i, RouteLds &L)
 {
     if (organize_core(a, i, L) == 0) return;
-    const int E = L.E;
+    const BInst I = a.inst[i];
+    int E = L.E;
+    if (I.m < PIECE_M_MAX) {
+        // L.cur holds each leaf's end offset after the scatter (the next leaf's start)
+        const int nleaf = I.nleaf;
+        for (int l = threadIdx.x; l < nleaf; l += BT) {
+            const int32_t c = L.cur[l] - (l ? L.cur[l - 1] : 0);
+            L.hist[l] = (c + SCAN_PIECE - 1) / SCAN_PIECE;
+        }
+        __syncthreads();
+        E = block_scan_lds(L.hist, nleaf, L.part);  // pieces in all; L.hist: each leaf's first
+        int32_t *pieces = a.tmp + I.tmp_off;         // free until the next FindLeafBatch phase
+        for (int l = threadIdx.x; l < nleaf; l += BT) {
+            const int32_t c = L.cur[l] - (l ? L.cur[l - 1] : 0);
+            const int np = (c + SCAN_PIECE - 1) / SCAN_PIECE;
+            for (int x = 0; x < np; x++) pieces[L.hist[l] + x] = (int32_t)(((uint32_t)l << 20) | (uint32_t)x);
+        }
+    }
     const int lpt = a.leaves_per_task;
     const int T = (E + lpt - 1) / lpt;
     if (threadIdx.x == 0) a.state[i].pending = T;
@@ -354,9 +378,20 @@ template <int D, int G> __device__ __forceinline__ void scan_leaves(const BatchA
     uint64_t *keys = a.keys + I.key_off;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int d = I.d, k = I.k;
+    const bool by_piece = I.m < PIECE_M_MAX;
+    const int32_t *pieces = a.tmp + I.tmp_off;
     for (int e = e0 + wave; e < e1; e += BT / 64) {
-        const int Lf = __builtin_amdgcn_readfirstlane(ne[e]);
-        const int qs = loff[Lf], qe = loff[Lf + 1];
+        int Lf, qs, qe;
+        if (by_piece) {
+            const uint32_t pc = (uint32_t)__builtin_amdgcn_readfirstlane(pieces[e]);
+            Lf = (int)(pc >> 20);
+            qs = loff[Lf] + (int)(pc & 0xfffffu) * SCAN_PIECE;
+            qe = min(loff[Lf + 1], qs + SCAN_PIECE);
+        } else {
+            Lf = __builtin_amdgcn_readfirstlane(ne[e]);
+            qs = loff[Lf];
+            qe = loff[Lf + 1];
+        }
         const int len = lo_pos[Lf + 1] - lo_pos[Lf];
         const float *X = pts + blk[Lf];
         const int32_t *orig = reinterpret_cast<const int32_t *>(X) + (int64_t)d * len;

@@ -221,6 +221,9 @@ struct FetchSpec {
     // finished ones) and it is counted in ctl[CTL_AGED]
     int32_t *age = nullptr;
     int32_t age_max = 0;
+    // served form: a query whose request has at most this many queries still travelling
+    // leaves the rounds the same way (0: never; needs req_of and req_left)
+    int32_t strag_max = 0;
 };
 
 void launch_init_state(int32_t *node, uint64_t *keys, uint32_t *kth, int64_t m, int K, hipStream_t s);

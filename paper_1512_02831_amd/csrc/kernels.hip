@@ -109,6 +109,13 @@ __global__ __launch_bounds__(256) void k_find_leaf(FetchSpec f, const float *__r
             // a long traversal leaves the rounds: the tail walks it to its end from node[q]
             leaf = nleaf + 1;
             atomicAdd(&ctl[CTL_AGED], 1);
+        } else if (f.strag_max > 0 && v >= 0 && f.req_left[f.req_of[q]] <= f.strag_max) {
+            // one of its request's last few travelling queries: leaves the rounds likewise, so
+            // the request does not wait out its slowest walks one round at a time (the count
+            // is read while other queries of the request may finish: at worst a query hands
+            // over a round early or late)
+            leaf = nleaf + 1;
+            atomicAdd(&ctl[CTL_AGED], 1);
         }
         pend_leaf[pend_base + j] = leaf;
         pend_q[pend_base + j] = q;

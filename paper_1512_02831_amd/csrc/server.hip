@@ -101,6 +101,7 @@ struct Session {
     int64_t cap = 0;  // query slots
     int max_req = 0;
     int age_max = 0;  // rounds after which a query leaves the rounds for the tail (0: never)
+    int strag_max = 0;  // a request's travelling queries at or below which they leave likewise (0: never)
     int64_t tail_max = 0;  // pending queries at or below which a round hands them all to the tail
     hipStream_t s = nullptr;
     // device state
@@ -130,6 +131,7 @@ struct Server {
     int32_t max_requests = 0;
     int32_t flags = 0;
     int32_t age_max = 0;
+    int32_t strag_max = 0;
     int64_t tail_max = SERVED_TAIL_MAX;
     std::mutex mu;
     std::condition_variable cv;       // wakes sessions (new work, stop)
@@ -407,8 +409,9 @@ static void session_round(Session &S, int64_t nnew, std::unique_lock<std::mutex>
     if (S.age_max > 0) {
         f.age = S.age.as<int32_t>();
         f.age_max = S.age_max;
-        launch_fill_i32(ctl + CTL_AGED, 0, 1, S.s);
     }
+    f.strag_max = S.strag_max;
+    if (S.age_max > 0 || S.strag_max > 0) launch_fill_i32(ctl + CTL_AGED, 0, 1, S.s);
     launch_find_leaf(f, S.Qpool.as<float>(), H.d, S.node.as<int32_t>(), S.kth.as<uint32_t>(),
                      T.d_split.as<float>(), H.h, leafbuf[S.cur], qbuf[S.cur], 0, S.cnt.as<int32_t>(), ctl, S.s);
     const int64_t total = S.P + nnew;
@@ -444,10 +447,11 @@ static void session_round(Session &S, int64_t nnew, std::unique_lock<std::mutex>
         if (!fin.empty()) session_deliver_begin(S, fin);
     }
     S.complete_s += now_s() - tc;
-    const int64_t aged = S.age_max > 0 ? hctl[CTL_AGED] : 0;
+    const int64_t aged = (S.age_max > 0 || S.strag_max > 0) ? hctl[CTL_AGED] : 0;
     if (aged > 0) {
-        // queries routed more than age_max times sort last: each walks the rest of its traversal
-        // in one workgroup from the leaf in node[q], so a request is not held by its longest walks
+        // queries routed more than age_max times, or among their request's last strag_max
+        // travelling ones, sort last: each walks the rest of its traversal in one workgroup
+        // from the leaf in node[q], so a request is not held by its longest walks
         ScanArgs a{};
         a.leaf_off = T.d_leaf_off.as<int32_t>();
         a.base = T.d_chunk[0].as<float>();
@@ -586,6 +590,7 @@ static Session &session_for(Server &V, int tree_id, int K)
     S->cap = V.slots_per_session;
     S->max_req = V.max_requests;
     S->age_max = V.age_max;
+    S->strag_max = V.strag_max;
     S->tail_max = V.tail_max;
     session_init(*S);
     S->th = std::thread(session_loop, S.get());
@@ -611,7 +616,7 @@ int bkd_server_create(const bkd_server_opts *opts, bkd_server **out)
         if (o.slots_per_session == 0) o.slots_per_session = 1 << 20;
         if (o.max_requests == 0) o.max_requests = 4096;
         if (o.slots_per_session < 1 || o.slots_per_session > INT32_MAX || o.max_requests < 1 || o.device < 0 ||
-            o.age_max < 0)
+            o.age_max < 0 || o.straggle_max < 0)
             bkd::fail(BKD_EINVAL, "invalid server options");
         int ndev = 0;
         BKD_HIP(hipGetDeviceCount(&ndev));
@@ -622,6 +627,7 @@ int bkd_server_create(const bkd_server_opts *opts, bkd_server **out)
         s->v.max_requests = o.max_requests;
         s->v.flags = o.flags;
         s->v.age_max = o.age_max;
+        s->v.strag_max = o.straggle_max;
         s->v.tail_max = o.tail_max == 0 ? bkd::SERVED_TAIL_MAX : (o.tail_max < 0 ? 0 : o.tail_max);
         *out = s.release();
     });

@@ -62,3 +62,16 @@ def test_query_rejects_null_tree():
     Q = np.zeros((1, 2), dtype=np.float32)
     assert L.bkd_query(None, Q.ctypes.data_as(ctypes.c_void_p), 1, 1, None, None) == bkd.EINVAL
     assert L.bkd_free(None) == bkd.OK
+
+
+@pytest.mark.parametrize("field,value", [("age_max", -1), ("straggle_max", -1), ("max_requests", -2),
+                                         ("slots_per_session", -5), ("device", -1)])
+def test_server_create_rejects_invalid_options(field, value):
+    # checked before any device is touched
+    L = bkd.lib()
+    o = bkd.ServerOpts()
+    setattr(o, field, value)
+    out = ctypes.c_void_p()
+    assert L.bkd_server_create(ctypes.byref(o), ctypes.byref(out)) == bkd.EINVAL
+    assert b"invalid server options" in L.bkd_last_error()
+    assert out.value is None
