@@ -109,6 +109,26 @@ def test_batch_same_alone_and_in_mix_and_under_tunings():
         assert np.array_equal(i, ref[j][0]) and np.array_equal(d, ref[j][1])
 
 
+@pytest.mark.parametrize("lpt", [1, 8, 64])
+def test_batch_round_pieces_match_oracle(lpt):
+    # solo_max 1 keeps every instance in rounds to the end, so every leaf scan runs as pieces of
+    # at most 64 queries: thousands of queries on two leaves (many pieces per leaf), 4096 leaves
+    # (piece codes with the top bit set), and d = 15, k = 32
+    say(f"case: batched rounds as pieces, {lpt} pieces per task")
+    shapes = [(300, 3, 1, 5000, 5), (65536, 5, 12, 8000, 10), (4000, 15, 5, 3000, 32), (5000, 10, 6, 1, 1)]
+    inst = []
+    for i, (n, d, h, m, k) in enumerate(shapes):
+        P, Q = datagen.batch_instance(41, i, n, m, d)
+        inst.append((P, Q, k, h))
+    with bkd.batch_create(inst, flags=bkd.FLAG_SQUARED) as b:
+        bkd.batch_run(b, bkd.Tuning(lpt, 4, 1))
+        res = bkd.batch_results(b)
+        st = bkd.batch_stats(b)
+    assert st["error"] == 0 and st["rounds"] > 0
+    for i, ((P, Q, k, h), (idx, d2)) in enumerate(zip(inst, res)):
+        assert np.array_equal(keys_of(idx, d2), oracle.brute_f32c(P, Q, k)), i
+
+
 def test_batch_rejects_bad_instances():
     P, Q = datagen.batch_instance(1, 0, 100, 10, 3)
     with pytest.raises(bkd.BkdError) as e:
