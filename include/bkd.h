@@ -362,7 +362,7 @@ typedef struct bkd_instance {
 
 /* Schedule of the persistent launch (results do not depend on it). */
 typedef struct bkd_tuning {
-    int32_t leaves_per_task; /* pieces per scan task (1..256; a piece: up to 64 buffered      */
+    int32_t leaves_per_task; /* pieces per scan task (1..256; a piece: up to 32 buffered      */
                              /* queries of one leaf); 0: default 8                           */
     int32_t groups_per_cu;   /* persistent workgroups per compute unit (1..16); 0: default 4  */
     int32_t solo_max;        /* once an instance has at most this many active queries, each  */

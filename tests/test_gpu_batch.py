@@ -112,7 +112,7 @@ def test_batch_same_alone_and_in_mix_and_under_tunings():
 @pytest.mark.parametrize("lpt", [1, 8, 64])
 def test_batch_round_pieces_match_oracle(lpt):
     # solo_max 1 keeps every instance in rounds to the end, so every leaf scan runs as pieces of
-    # at most 64 queries: thousands of queries on two leaves (many pieces per leaf), 4096 leaves
+    # at most 32 queries: thousands of queries on two leaves (many pieces per leaf), 4096 leaves
     # (piece codes with the top bit set), and d = 15, k = 32
     say(f"case: batched rounds as pieces, {lpt} pieces per task")
     shapes = [(300, 3, 1, 5000, 5), (65536, 5, 12, 8000, 10), (4000, 15, 5, 3000, 32), (5000, 10, 6, 1, 1)]
