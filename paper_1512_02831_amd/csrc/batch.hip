@@ -1121,7 +1121,7 @@ void batch_autotune(Batch &b, bkd_tuning *best, double *best_ms)
 {
     const int lpts[] = {4, 16, 64};
     const int gpcs[] = {2, 4};
-    const int solos[] = {512, 2048, 8192, 32768};
+    const int solos[] = {2048, 8192, 16384, 32768};
     hipStream_t s = b.cap_stream;
     double bm = 1e300;
     bkd_tuning bt{8, 4, 2048};
