@@ -239,12 +239,15 @@ size_t sort_hist_words(int64_t count);
 // Grouping of (leaf, query) pairs by leaf in one pass, order within a leaf unspecified, for
 // at most bucket_max_keys() distinct keys: launch_bucket_count writes per-block key counts
 // and their column prefixes into hist and returns the key totals (inside hist);
-// launch_bucket_scatter then places the pairs, key k starting at off[k].
+// launch_bucket_scatter then places the pairs, key k starting at off[k].  Keys are counted
+// relative to key_base (key - key_base in [0, nb); others are skipped) and written as they
+// are; with dcount the pair count is read on the device and count only bounds it.
 int bucket_max_keys();
 const int32_t *launch_bucket_count(const uint32_t *keys, int64_t count, int nb, uint32_t *hist,
-                                   hipStream_t s);
+                                   hipStream_t s, uint32_t key_base = 0, const int32_t *dcount = nullptr);
 void launch_bucket_scatter(const uint32_t *kin, const int32_t *vin, uint32_t *kout, int32_t *vout, int64_t count,
-                           int nb, const uint32_t *hist, const int32_t *off, hipStream_t s);
+                           int nb, const uint32_t *hist, const int32_t *off, hipStream_t s, uint32_t key_base = 0,
+                           const int32_t *dcount = nullptr);
 // tiles: [2][nleaf+1] -- dense work-item offsets, then sparse (per buffered query) offsets.
 // count_work: also add the visits and pairs of scanning every buffer to the ctl counters.
 void launch_leaf_offsets(const int32_t *cnt, const int32_t *start, const int32_t *leaf_off, int nleaf, int qt,

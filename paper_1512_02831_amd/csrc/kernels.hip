@@ -301,9 +301,11 @@ constexpr int BK_TILE = BK_THREADS * BK_PER;
 constexpr int BK_MAX = 2048;
 
 __global__ __launch_bounds__(BK_THREADS) void k_bucket_hist(const uint32_t *__restrict__ keys, int64_t count, int nb,
-                                                            uint32_t *__restrict__ hist, int nblocks)
+                                                            uint32_t *__restrict__ hist, int nblocks,
+                                                            uint32_t key_base, const int32_t *__restrict__ dcount)
 {
     __shared__ uint32_t h[BK_MAX];
+    if (dcount) count = *dcount;
     for (int i = threadIdx.x; i < nb; i += BK_THREADS) h[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * BK_TILE + threadIdx.x;
@@ -311,11 +313,11 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_hist(const uint32_t *__re
 #pragma unroll
     for (int r = 0; r < BK_PER; r++) {
         const int64_t i = base + (int64_t)r * BK_THREADS;
-        kr[r] = i < count ? keys[i] : 0u;
+        kr[r] = i < count ? keys[i] - key_base : 0u;
     }
 #pragma unroll
     for (int r = 0; r < BK_PER; r++)
-        if (base + (int64_t)r * BK_THREADS < count) atomicAdd(&h[kr[r]], 1u);
+        if (base + (int64_t)r * BK_THREADS < count && kr[r] < (uint32_t)nb) atomicAdd(&h[kr[r]], 1u);
     __syncthreads();
     for (int i = threadIdx.x; i < nb; i += BK_THREADS) hist[(int64_t)i * nblocks + blockIdx.x] = h[i];
 }
@@ -327,9 +329,11 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_scatter(const uint32_t *_
                                                                uint32_t *__restrict__ kout, int32_t *__restrict__ vout,
                                                                int64_t count, int nb,
                                                                const uint32_t *__restrict__ hist, int nblocks,
-                                                               const int32_t *__restrict__ off)
+                                                               const int32_t *__restrict__ off, uint32_t key_base,
+                                                               const int32_t *__restrict__ dcount)
 {
     __shared__ uint32_t run[BK_MAX];
+    if (dcount) count = *dcount;
     for (int i = threadIdx.x; i < nb; i += BK_THREADS)
         run[i] = (uint32_t)off[i] + hist[(int64_t)i * nblocks + blockIdx.x];
     __syncthreads();
@@ -344,8 +348,9 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_scatter(const uint32_t *_
     }
 #pragma unroll
     for (int r = 0; r < BK_PER; r++) {
-        if (base + (int64_t)r * BK_THREADS < count) {
-            const uint32_t pos = atomicAdd(&run[kr[r]], 1u);
+        const uint32_t lk = kr[r] - key_base;
+        if (base + (int64_t)r * BK_THREADS < count && lk < (uint32_t)nb) {
+            const uint32_t pos = atomicAdd(&run[lk], 1u);
             kout[pos] = kr[r];
             vout[pos] = vr[r];
         }
@@ -650,22 +655,24 @@ size_t sort_hist_words(int64_t count)
 int bucket_max_keys() { return BK_MAX; }
 
 const int32_t *launch_bucket_count(const uint32_t *keys, int64_t count, int nb, uint32_t *hist,
-                                   hipStream_t s)
+                                   hipStream_t s, uint32_t key_base, const int32_t *dcount)
 {
     const int nblocks = (int)((count + BK_TILE - 1) / BK_TILE);
     uint32_t *totals = hist + (size_t)nb * nblocks;
-    if (nblocks > 0) k_bucket_hist<<<nblocks, BK_THREADS, 0, s>>>(keys, count, nb, hist, nblocks);
+    if (nblocks > 0) k_bucket_hist<<<nblocks, BK_THREADS, 0, s>>>(keys, count, nb, hist, nblocks, key_base, dcount);
     k_scan_columns<<<nb, 256, 0, s>>>(hist, nblocks, totals);
     check_launch();
     return reinterpret_cast<const int32_t *>(totals);
 }
 
 void launch_bucket_scatter(const uint32_t *kin, const int32_t *vin, uint32_t *kout, int32_t *vout, int64_t count,
-                           int nb, const uint32_t *hist, const int32_t *off, hipStream_t s)
+                           int nb, const uint32_t *hist, const int32_t *off, hipStream_t s, uint32_t key_base,
+                           const int32_t *dcount)
 {
     const int nblocks = (int)((count + BK_TILE - 1) / BK_TILE);
     if (nblocks == 0) return;
-    k_bucket_scatter<<<nblocks, BK_THREADS, 0, s>>>(kin, vin, kout, vout, count, nb, hist, nblocks, off);
+    k_bucket_scatter<<<nblocks, BK_THREADS, 0, s>>>(kin, vin, kout, vout, count, nb, hist, nblocks, off, key_base,
+                                                    dcount);
     check_launch();
 }
 

@@ -915,17 +915,29 @@ struct Run {
             const int32_t *dstep = nullptr;  // its size on the device (from the second step on)
             for (;;) {
                 tgroup.begin(s);
-                if (launch_sort_pairs(Rl, Rq, sleaf, sq, nstep, kbits, ws.hist, s, dstep)) {
+                int32_t *dtiles = ws.tiles;
+                if (!tracing && nl <= bucket_max_keys()) {
+                    // one pass: per-leaf counts of the region (keys relative to the chunk's
+                    // first leaf), the offsets, a scatter by leaf (order within a leaf free, as
+                    // in resident rounds), copied back into the region
+                    const int32_t *counts = launch_bucket_count(Rl, nstep, nl, ws.hist, s, (uint32_t)lf, dstep);
+                    launch_leaf_offsets(counts, nullptr, t.d_leaf_off.as<int32_t>() + lf, nl, SCAN_QT, t.dense_min,
+                                        ws.off + lf, dtiles + lf, dtiles + nleaf + 1 + lf, ctl, s);
+                    launch_bucket_scatter(Rl, Rq, sleaf, sq, nstep, nl, ws.hist, ws.off + lf, s, (uint32_t)lf, dstep);
                     BKD_HIP(hipMemcpyAsync(Rl, sleaf, sizeof(uint32_t) * nstep, hipMemcpyDeviceToDevice, s));
                     BKD_HIP(hipMemcpyAsync(Rq, sq, sizeof(int32_t) * nstep, hipMemcpyDeviceToDevice, s));
+                } else {
+                    if (launch_sort_pairs(Rl, Rq, sleaf, sq, nstep, kbits, ws.hist, s, dstep)) {
+                        BKD_HIP(hipMemcpyAsync(Rl, sleaf, sizeof(uint32_t) * nstep, hipMemcpyDeviceToDevice, s));
+                        BKD_HIP(hipMemcpyAsync(Rq, sq, sizeof(int32_t) * nstep, hipMemcpyDeviceToDevice, s));
+                    }
+                    int32_t *start = ws.cnt0;
+                    launch_fill_i32(cnt + lf, 0, nl, s);
+                    launch_fill_i32(start + lf, 0, nl, s);
+                    launch_run_bounds(Rl, nstep, nleaf, start, cnt, s, dstep);
+                    launch_leaf_offsets(cnt + lf, start + lf, t.d_leaf_off.as<int32_t>() + lf, nl, SCAN_QT,
+                                        t.dense_min, ws.off + lf, dtiles + lf, dtiles + nleaf + 1 + lf, ctl, s);
                 }
-                int32_t *dtiles = ws.tiles;
-                int32_t *start = ws.cnt0;
-                launch_fill_i32(cnt + lf, 0, nl, s);
-                launch_fill_i32(start + lf, 0, nl, s);
-                launch_run_bounds(Rl, nstep, nleaf, start, cnt, s, dstep);
-                launch_leaf_offsets(cnt + lf, start + lf, t.d_leaf_off.as<int32_t>() + lf, nl, SCAN_QT, t.dense_min,
-                                    ws.off + lf, dtiles + lf, dtiles + nleaf + 1 + lf, ctl, s);
                 tgroup.end(s);
                 count_work(lf, ll);
                 // this step's counts, and every region's size before its distribution: read back
