@@ -6,12 +6,14 @@
 //   FIND(i, j0, j1)  FindLeafBatch for a slice of i's active queries, with the
 //                    buffer fills counted by per-leaf atomics;
 //   ORGANIZE(i)      one workgroup: buffer offsets, the list of buffered
-//                    leaves and the scatter of the queries into buffer order;
-//                    an instance whose queries have all finished is done;
-//   SCAN(i, e0, e1)  one wave per buffered leaf: the leaf's points sit in
-//                    registers (lanes over points) while the wave walks the
-//                    leaf's buffered queries; each query's k best keys are
-//                    spread over the lanes and merged with ballots.
+//                    leaves and the scatter of the queries into buffer order,
+//                    then the list of pieces; an instance whose queries have
+//                    all finished is done;
+//   SCAN(i, e0, e1)  one wave per piece (at most SCAN_PIECE buffered queries
+//                    of one leaf): the leaf's points sit in registers (lanes
+//                    over points) while the wave walks the piece's queries;
+//                    each query's k best keys are spread over the lanes and
+//                    merged with ballots.
 //   TAIL(i, j0, j1)  once an instance has at most solo_max active queries
 //                    (or from the start, when it is that small): one wave per
 //                    query walks that query's traversal to the end, lanes over
@@ -367,7 +369,8 @@ __device__ __forceinline__ void organize_task(const BatchArgs &a, int i, RouteLd
 }
 
 
-// One wave per buffered leaf; G groups of 64 points per pass held in registers.
+// One wave per piece (up to SCAN_PIECE buffered queries of one leaf; per buffered leaf for an
+// instance of 2^26 queries or more); G groups of 64 points per pass held in registers.
 template <int D, int G> __device__ __forceinline__ void scan_leaves(const BatchArgs &a, int i, int e0, int e1)
 {
     const BInst I = a.inst[i];
